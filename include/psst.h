@@ -1,0 +1,251 @@
+/*
+ * psst.h -- C ABI of the MI355X (gfx950) engine for fixed-step fourth-order
+ * Runge-Kutta integration of coupled Hodgkin-Huxley networks.
+ *
+ * The calls follow the paper's statement of the problem (Mohanta & Assisi,
+ * "Parallel scalable simulations of biological neural networks using
+ * TensorFlow"):
+ *   - an initial value problem dy/dt = f(y, t), y(t0) = y0, integrated with
+ *     the classical RK4 step ("Brain simulations as computational graphs",
+ *     IVP equation and the RK4 paragraph);
+ *   - a scan of that step over a time grid whose output rows are the states
+ *     after each step, the initial value excluded (same section, the tf.scan
+ *     cumulative-sum example);
+ *   - per-neuron state [V, m, h, n] and per-neuron parameter vectors
+ *     C_m, g_Na, g_K, g_L, E_Na, E_K, E_L in structure-of-arrays form (same
+ *     section, vectorisation paragraph);
+ *   - synaptic coupling as dense n x n conductance matrices per synapse type
+ *     ("Circumventing memory constraints", item 1);
+ *   - long runs split into successive batches of steps that resume from the
+ *     carried state (same section, item 2).
+ *
+ * Conventions
+ *   - Every call returns psst_status; no C++ exception crosses the ABI.  On
+ *     failure psst_last_error() returns a thread-local description.
+ *   - Arguments are validated on the host before any device call; invalid
+ *     arguments never reach the GPU.
+ *   - Ownership: handles (psst_network, psst_batch) and their device copies of
+ *     parameters and conductances belong to the library.  State, stimulus,
+ *     record, checkpoint and gradient buffers belong to the caller (device
+ *     memory, e.g. from torch tensors); the library never frees them.
+ *   - create/destroy/poll calls are synchronous; integrate and adjoint calls
+ *     are asynchronous on the caller's HIP stream (NULL = default stream).
+ *   - Units: mV, ms, nS (synaptic g), nA (injected current), uF/cm^2, mS/cm^2
+ *     (intrinsic g).  With membrane area A (cm^2), 1 nS = 1e-6/A mS/cm^2 and
+ *     1 nA = 1e-3/A uA/cm^2.
+ *
+ * Numerics: the per-neuron right-hand side (rate functions, currents, gating
+ * ODEs) and the RK4 stage arithmetic run in float64; the synaptic products
+ * sum_j g_ij x_j run in float32 (g in nS as given, x rounded to float32);
+ * each state variable is stored as a float32 pair (value, compensation) whose
+ * sum is the float64-rounded state after every step.
+ */
+#ifndef PSST_H
+#define PSST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSST_OK = 0,
+    PSST_ERR_INVALID_ARGUMENT = 1,  /* a pointer, size, range or value is invalid */
+    PSST_ERR_OUT_OF_MEMORY = 2,     /* a device or host allocation failed */
+    PSST_ERR_DEVICE = 3,            /* no usable gfx950 device, or a HIP call failed */
+    PSST_ERR_NONFINITE = 4,         /* a state variable became NaN or infinite */
+    PSST_ERR_UNSUPPORTED = 5        /* valid request this build does not implement */
+} psst_status;
+
+/* Thread-local text describing the last failure of a call on this thread. */
+const char *psst_last_error(void);
+
+/* Library version string. */
+const char *psst_version(void);
+
+/* Number of visible HIP devices (0 when none); never fails. */
+int32_t psst_device_count(void);
+
+/* ------------------------------------------------------------------------ */
+/* Networks                                                                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct psst_network psst_network;   /* opaque, library-owned */
+typedef struct psst_batch psst_batch;       /* opaque, library-owned */
+
+typedef enum { PSST_SYN_ACH = 0, PSST_SYN_GABA_A = 1, PSST_SYN_GABA_B = 2 } psst_syn_type;
+
+/* Per-neuron parameter vectors (host pointers, length n_neurons each).
+ * Neurons [0, n_pn) are projection neurons (PN, cholinergic output),
+ * [n_pn, n) local neurons (LN, GABAergic output). */
+typedef struct {
+    const float *C_m, *g_Na, *g_K, *g_L;    /* uF/cm^2, mS/cm^2 */
+    const float *E_Na, *E_K, *E_L;          /* mV */
+    int32_t n_pn;
+    float area_cm2;                         /* > 0 */
+} psst_neuron_params;
+
+/* One dense masked block of synapses of one type: g_nS[(i - post_begin) *
+ * (pre_end - pre_begin) + (j - pre_begin)] is the conductance from
+ * presynaptic j to postsynaptic i (row-major [post x pre], host memory).
+ * Cholinergic blocks must have their presynaptic range inside the PN rows,
+ * GABA blocks inside the LN rows; blocks of one type must not overlap.
+ * mask (same shape, or NULL = all present): entries with mask == 0 are no
+ * synapse; their g is ignored and their gradient is 0. */
+typedef struct {
+    int32_t type;                           /* psst_syn_type */
+    int32_t pre_begin, pre_end, post_begin, post_end;
+    const float *g_nS;
+    const uint8_t *mask;
+} psst_pathway;
+
+/* Synapse kinetics per type (index = psst_syn_type).
+ * Release T(V_pre) = 1 / (1 + exp(-(V_pre - V_p) / K_p)).
+ * ACh, GABA_A: ds/dt = alpha T (1 - s) - beta s, activation x = s.
+ * GABA_B:      dr/dt = r1 T (1 - r) - r2 r, dG/dt = r3 r - r4 G,
+ *              activation x = G^n / (G^n + K_d), n = hill_n (integer 1..8).
+ * Current onto i: sum over types of (V_i - E_rev) * sum_j g_ij x_j. */
+typedef struct {
+    float alpha, beta, E_rev, V_p, K_p;
+    float r1, r2, r3, r4, K_d, hill_n;
+} psst_kinetics;
+
+/* Build a network and upload its parameters and conductance matrices to the
+ * current HIP device.  All pointers are host pointers and are only read
+ * during the call.  n_neurons in [1, 1 << 20]; n_pathways in [0, 64].
+ * Errors: INVALID_ARGUMENT (checked before any device call), DEVICE,
+ * OUT_OF_MEMORY. */
+psst_status psst_network_create(const psst_neuron_params *params, int32_t n_neurons,
+                                const psst_pathway *pathways, int32_t n_pathways,
+                                const psst_kinetics kinetics[3], psst_network **out);
+psst_status psst_network_destroy(psst_network *net);
+
+/* State layout: 7 variables (V, m, h, n, s, r, G) x 2 float32 words (value,
+ * compensation), plane-major: word (2 * var + c) * n_total + i.  n_words =
+ * 14 * n_neurons for a network.  s is the neuron's own outgoing transmitter
+ * gate (ACh for PN, fast GABA for LN); r, G are the slow-GABA pair of LN rows
+ * (zero and unused for PN rows or networks without slow GABA). */
+psst_status psst_state_layout(const psst_network *net, int64_t *n_words, int32_t *n_vars);
+
+/* Initial state from v0 (device, [n] mV): gates at their steady state for
+ * v0, synaptic variables 0, compensation words 0.  state: device
+ * [n_words] float32, written.  Asynchronous on stream. */
+psst_status psst_state_init(const psst_network *net, const float *v0, float *state,
+                            void *hip_stream);
+
+/* Injected current (device pointers, nA), indexed by neuron (packed over all
+ * instances for a batch: n_total entries): i_const (or NULL = 0) plus
+ * pulses; neuron k owns pulses pulse_ptr[k] .. pulse_ptr[k+1]-1 (pulse_ptr
+ * NULL = no pulses), each on during global steps on_step <= g < off_step.
+ * The current is held constant over each step (zero-order hold). */
+typedef struct {
+    const float *i_const_nA;
+    const int32_t *pulse_ptr;
+    const int64_t *on_step, *off_step;
+    const float *amp_nA;
+} psst_stimulus;
+
+/* Recording (device pointers; any member may be NULL/0 to skip it).
+ * v_out [capacity x n_total] float32: row r holds V of every neuron after
+ * global step g + 1 = (step0 / stride + 1 + r) * stride, i.e. every stride-th
+ * state after the call's first step (the initial state is not a row); rows
+ * beyond capacity are dropped.
+ * spike_count [n_total] int32 (in/out, incremented) and spike_t_ms
+ * [n_total x spike_cap] float32: upward crossings of 0 mV, V_g < 0 <= V_g+1,
+ * at time (g + (0 - V_g) / (V_g+1 - V_g)) * dt; spikes beyond spike_cap are
+ * counted but not stored. */
+typedef struct {
+    float *v_out;
+    int64_t stride, capacity;
+    int32_t *spike_count;
+    float *spike_t_ms;
+    int32_t spike_cap;
+} psst_record;
+
+/* Integrate one network (the plain one-network-per-launch form): n_steps
+ * RK4 steps of size dt_ms from global step index step0 (time t = step0 *
+ * dt), state in/out.  Calling it with (n1, step0) then (n2, step0 + n1)
+ * gives bitwise the same state and records as one call with n1 + n2.
+ * stim, rec may be NULL.  n_steps >= 0, dt_ms > 0 and finite, step0 >= 0.
+ * Errors: INVALID_ARGUMENT, DEVICE, UNSUPPORTED (n beyond the single-network
+ * kernel's limit).  Non-finite states are reported by psst_network_poll. */
+psst_status psst_integrate(psst_network *net, float *state, const psst_stimulus *stim,
+                           float dt_ms, int64_t n_steps, int64_t step0,
+                           const psst_record *rec, void *hip_stream);
+
+/* Synchronize the stream and report (then clear) the non-finite flag set by
+ * earlier integrate calls on this network: PSST_OK or PSST_ERR_NONFINITE. */
+psst_status psst_network_poll(psst_network *net, void *hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: many independent instances in one launch                         */
+/* ------------------------------------------------------------------------ */
+
+/* Batch of n instances; nets[b] may repeat (trials of one network share its
+ * device conductances).  The batch keeps references: the networks must
+ * outlive it.  Instance b owns neurons [off_b, off_b + n_b) of every packed
+ * array, off_b = sum of the sizes of instances before b.  Creation also tunes
+ * the launch shape on the device (timing a few short candidate runs) unless
+ * the environment variable PSST_TUNE=0.  n in [1, 1 << 20]. */
+psst_status psst_batch_create(psst_network *const *nets, int32_t n, psst_batch **out);
+psst_status psst_batch_destroy(psst_batch *batch);
+
+/* n_total = total neurons, n_words = 14 * n_total; offsets (host, may be
+ * NULL) receives n + 1 neuron offsets. */
+psst_status psst_batch_layout(const psst_batch *batch, int64_t *n_total, int64_t *n_words,
+                              int64_t *offsets);
+
+/* Packed initial state for every instance from v0 [n_total] (device). */
+psst_status psst_batch_state_init(const psst_batch *batch, const float *v0, float *states,
+                                  void *hip_stream);
+
+/* Integrate every instance of the batch by n_steps (same semantics as
+ * psst_integrate per instance; instance results are bitwise independent of
+ * the batch's order and composition).  states, stim, rec are packed over
+ * n_total neurons.  checkpoints: NULL, or device [n_steps / K + 1 x n_words]
+ * float32 receiving the state before global steps step0 + c K (c = 0, 1,
+ * ...), for psst_adjoint.  Submitted as one graph launch. */
+psst_status psst_integrate_batch(psst_batch *batch, float *states, const psst_stimulus *stim,
+                                 float dt_ms, int64_t n_steps, int64_t step0,
+                                 const psst_record *rec, float *checkpoints, int32_t K,
+                                 void *hip_stream);
+
+psst_status psst_batch_poll(psst_batch *batch, void *hip_stream);
+
+/* Text description of the tuned launch shape (for logs and benchmarks). */
+psst_status psst_batch_describe(const psst_batch *batch, char *buf, int32_t buf_len);
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Gradients of a loss of the recorded potentials with respect to the synaptic
+ * and intrinsic conductances, by reverse differentiation of the RK4 map.
+ * checkpoints: as written by psst_integrate_batch(..., K) for the same
+ * stimulus, dt, n_steps and step0.  dL_dV: device [n_steps x n_total],
+ * row k = dL/dV after global step step0 + k + 1.
+ * grad_g: device, per instance the pathway blocks of its network in pathway
+ * order, each [post x pre] (nS^-1 units of L), zero where there is no synapse;
+ * grad_gNa, grad_gK, grad_gL: device per-neuron gradients (per mS/cm^2).
+ * per_instance = 1: outputs are per instance (grad_g packed instance after
+ * instance, per-neuron arrays [n_total]); per_instance = 0: all instances
+ * must share one network and outputs hold the sum over instances
+ * (grad_g [network's blocks], per-neuron arrays [n]).  Sums over time and
+ * instances use compensated float32.  Outputs are overwritten.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, DEVICE, OUT_OF_MEMORY. */
+psst_status psst_adjoint(psst_batch *batch, const float *checkpoints, int32_t K,
+                         const psst_stimulus *stim, float dt_ms, int64_t n_steps,
+                         int64_t step0, const float *dL_dV, float *grad_g, float *grad_gNa,
+                         float *grad_gK, float *grad_gL, int32_t per_instance,
+                         void *hip_stream);
+
+/* Number of float32 gradient entries one copy of the network's pathway blocks
+ * occupies in grad_g. */
+psst_status psst_network_grad_size(const psst_network *net, int64_t *n_entries);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSST_H */

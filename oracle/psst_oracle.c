@@ -25,8 +25,9 @@
  *    synapses and a two-variable (r, G) G-protein scheme for slow GABA;
  *  - every step in float64, no compensation, no reassociation.
  *
- * State layout: y[var * n + i], var = V, m, h, n, s, r, G (7 planes; r and G
- * are only driven for LN rows and only matter when a GABA_B pathway exists).
+ * State layout: y[var * n + i], var = V, m, h, n, s, r, G (7 planes; the
+ * slow-GABA pair r, G exists only for LN rows of networks that have a slow-GABA
+ * pathway, and stays constant otherwise).
  */
 #include <math.h>
 #include <stdint.h>
@@ -136,6 +137,13 @@ static const double *own_kin(const or_net *net, int i)
     return net->kin + (i < net->n_pn ? T_ACH : T_GABA_A) * NKIN;
 }
 
+static int has_slow_gaba(const or_net *net)
+{
+    for (int p = 0; p < net->n_path; ++p)
+        if (net->pinfo[5 * p] == T_GABA_B) return 1;
+    return 0;
+}
+
 static int64_t path_offset(const or_net *net, int p)
 {
     int64_t off = 0;
@@ -201,6 +209,7 @@ void or_rhs(const or_net *net, const double *y, const double *I_nA, double *f)
     double *A = (double *)malloc(sizeof(double) * 3 * n);
     synaptic_sums(net, y, A);
     const double *kb = net->kin + T_GABA_B * NKIN;
+    int gb = has_slow_gaba(net);
     for (int i = 0; i < n; ++i) {
         double V = y[YV * n + i], m = y[YM * n + i], h = y[YH * n + i];
         double nn = y[YN * n + i], s = y[YS * n + i];
@@ -222,7 +231,7 @@ void or_rhs(const or_net *net, const double *y, const double *I_nA, double *f)
         const double *k = own_kin(net, i);
         double T = release(V, k);
         f[YS * n + i] = k[K_ALPHA] * T * (1.0 - s) - k[K_BETA] * s;
-        if (i >= net->n_pn) {
+        if (gb && i >= net->n_pn) {
             double TB = release(V, kb);
             f[YR * n + i] = kb[K_R1] * TB * (1.0 - r) - kb[K_R2] * r;
             f[YG * n + i] = kb[K_R3] * r - kb[K_R4] * G;
@@ -466,6 +475,7 @@ static void rhs_vjp(const or_net *net, const double *Y, const double *w,
     double *A = (double *)malloc(sizeof(double) * 3 * n);
     double *q = (double *)malloc(sizeof(double) * 3 * n);  /* dI_syn weights */
     synaptic_sums(net, Y, A);
+    int gb = has_slow_gaba(net);
     memset(u, 0, sizeof(double) * NVAR * n);
     for (int i = 0; i < n; ++i) {
         double V = Y[YV * n + i], m = Y[YM * n + i], h = Y[YH * n + i];
@@ -486,7 +496,7 @@ static void rhs_vjp(const or_net *net, const double *Y, const double *w,
         double T = release(V, k);
         uV += w[YS * n + i] * k[K_ALPHA] * (T * (1 - T) / k[K_KP]) * (1 - s);
         u[YS * n + i] += w[YS * n + i] * (-(k[K_ALPHA] * T + k[K_BETA]));
-        if (i >= net->n_pn) {
+        if (gb && i >= net->n_pn) {
             double TB = release(V, kb);
             uV += w[YR * n + i] * kb[K_R1] * (TB * (1 - TB) / kb[K_KP]) * (1 - r);
             u[YR * n + i] += w[YR * n + i] * (-(kb[K_R1] * TB + kb[K_R2])) + w[YG * n + i] * kb[K_R3];

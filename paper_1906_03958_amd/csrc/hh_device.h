@@ -1,0 +1,178 @@
+// hh_device.h -- per-neuron Hodgkin-Huxley right-hand side on the GPU.
+//
+// State of neuron i (paper, "Brain simulations as computational graphs",
+// vectorisation paragraph: X = [V, m, n, h] with per-neuron parameters
+// C_m, g_K, ..., E_L): V, m, h, n, plus its outgoing transmitter gate s and,
+// for local neurons of networks with slow GABA, the G-protein pair r, G.
+//
+// Everything here runs in float64: the per-neuron work is a few hundred
+// operations per stage, negligible next to the synaptic products, and float64
+// keeps the trajectory within 1e-3 mV of an exact-arithmetic solution for the
+// first 50 ms (float32 rate functions alone would not).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psst {
+
+enum { YV = 0, YM = 1, YH = 2, YN = 3, YS = 4, YR = 5, YG = 6, NVAR = 7 };
+enum { K_ALPHA = 0, K_BETA, K_EREV, K_VP, K_KP, K_R1, K_R2, K_R3, K_R4, K_KD, K_HILL, NKIN = 11 };
+enum { P_CM = 0, P_GNA, P_GK, P_GL, P_ENA, P_EK, P_EL, NPRM = 7 };
+enum { T_ACH = 0, T_GABA_A = 1, T_GABA_B = 2 };
+
+// Instance descriptor: one network copy inside a launch.
+struct InstDesc {
+    const float *gt;    // fast conductances, transposed: gt[j * ld + i] = g(pre j -> post i), nS
+    const float *gtb;   // slow-GABA conductances, transposed: gtb[(j - n_pn) * ld + i]; null if none
+    const float *prm;   // [NPRM][ld] per-neuron parameters
+    const float *kin;   // [3][NKIN] synapse kinetics
+    int64_t off;        // first neuron of this instance in the packed arrays
+    int32_t n, n_pn, ld, flags;   // flags bit 0: has slow GABA
+    double cg, ci;      // nS -> mS/cm^2 and nA -> uA/cm^2 for this network's area
+};
+
+enum { DESC_GABAB = 1 };
+
+// Synapse kinetics widened to float64.
+struct Kin {
+    double a_ach, b_ach, vp_ach, kp_ach, e_ach;
+    double a_ga, b_ga, vp_ga, kp_ga, e_ga;
+    double r1, r2, r3, r4, kd, vp_gb, kp_gb, e_gb;
+    int hill;
+};
+
+__device__ inline Kin load_kin(const float *k)
+{
+    Kin q;
+    q.a_ach = k[T_ACH * NKIN + K_ALPHA];  q.b_ach = k[T_ACH * NKIN + K_BETA];
+    q.vp_ach = k[T_ACH * NKIN + K_VP];    q.kp_ach = k[T_ACH * NKIN + K_KP];
+    q.e_ach = k[T_ACH * NKIN + K_EREV];
+    q.a_ga = k[T_GABA_A * NKIN + K_ALPHA]; q.b_ga = k[T_GABA_A * NKIN + K_BETA];
+    q.vp_ga = k[T_GABA_A * NKIN + K_VP];   q.kp_ga = k[T_GABA_A * NKIN + K_KP];
+    q.e_ga = k[T_GABA_A * NKIN + K_EREV];
+    q.r1 = k[T_GABA_B * NKIN + K_R1]; q.r2 = k[T_GABA_B * NKIN + K_R2];
+    q.r3 = k[T_GABA_B * NKIN + K_R3]; q.r4 = k[T_GABA_B * NKIN + K_R4];
+    q.kd = k[T_GABA_B * NKIN + K_KD];
+    q.vp_gb = k[T_GABA_B * NKIN + K_VP]; q.kp_gb = k[T_GABA_B * NKIN + K_KP];
+    q.e_gb = k[T_GABA_B * NKIN + K_EREV];
+    q.hill = (int)k[T_GABA_B * NKIN + K_HILL];
+    return q;
+}
+
+struct Prm {
+    double C, gNa, gK, gL, ENa, EK, EL;
+};
+
+__device__ inline Prm load_prm(const float *p, int ld, int i)
+{
+    Prm q;
+    q.C = p[P_CM * ld + i];   q.gNa = p[P_GNA * ld + i]; q.gK = p[P_GK * ld + i];
+    q.gL = p[P_GL * ld + i];  q.ENa = p[P_ENA * ld + i]; q.EK = p[P_EK * ld + i];
+    q.EL = p[P_EL * ld + i];
+    return q;
+}
+
+// u / (1 - exp(-u)), extended by continuity (value 1) at u = 0.
+__device__ inline double exprel(double u)
+{
+    if (fabs(u) < 1e-6) return 1.0 + u * 0.5 + u * u * (1.0 / 12.0);
+    return u / (-expm1(-u));
+}
+
+__device__ inline double exprel_d(double u)
+{
+    if (fabs(u) < 1e-4) return 0.5 + u * (1.0 / 6.0) - u * u * u * (1.0 / 180.0);
+    double e = exp(-u);
+    double d = -expm1(-u);
+    return (d - u * e) / (d * d);
+}
+
+struct Rates {
+    double am, bm, ah, bh, an, bn;
+};
+
+// Hodgkin & Huxley 1952 rate functions, -65 mV convention, ms^-1.
+__device__ inline Rates hh_rates(double V)
+{
+    Rates r;
+    r.am = exprel((V + 40.0) * 0.1);
+    r.bm = 4.0 * exp(-(V + 65.0) * (1.0 / 18.0));
+    r.ah = 0.07 * exp(-(V + 65.0) * 0.05);
+    r.bh = 1.0 / (1.0 + exp(-(V + 35.0) * 0.1));
+    r.an = 0.1 * exprel((V + 55.0) * 0.1);
+    r.bn = 0.125 * exp(-(V + 65.0) * 0.0125);
+    return r;
+}
+
+__device__ inline double release(double V, double vp, double kp)
+{
+    return 1.0 / (1.0 + exp(-(V - vp) / kp));
+}
+
+__device__ inline double ipow(double x, int n)
+{
+    double p = 1.0;
+    for (int i = 0; i < n; ++i) p *= x;
+    return p;
+}
+
+// Slow-GABA activation x = G^n / (G^n + K_d).
+__device__ inline double gabab_act(double G, const Kin &k)
+{
+    double gn = ipow(G, k.hill);
+    return gn / (gn + k.kd);
+}
+
+__device__ inline double gabab_act_d(double G, const Kin &k)
+{
+    double gn = ipow(G, k.hill);
+    double den = gn + k.kd;
+    return k.hill * k.kd * ipow(G, k.hill - 1) / (den * den);
+}
+
+// f(Y) for one neuron.  gs_* are the synaptic conductance sums already in
+// mS/cm^2 (cg * sum_j g_ij x_j); Iu is the injected current in uA/cm^2.
+__device__ inline void hh_rhs(const double Y[NVAR], const Prm &P, const Kin &K,
+                              double gs_ach, double gs_ga, double gs_gb, double Iu,
+                              bool is_ln, bool gabab, double f[NVAR])
+{
+    const double V = Y[YV], m = Y[YM], h = Y[YH], n = Y[YN], s = Y[YS];
+    const Rates r = hh_rates(V);
+    const double m3h = m * m * m * h;
+    const double n4 = (n * n) * (n * n);
+    const double Iion = P.gNa * m3h * (V - P.ENa) + P.gK * n4 * (V - P.EK) + P.gL * (V - P.EL);
+    const double Isyn = (V - K.e_ach) * gs_ach + (V - K.e_ga) * gs_ga + (V - K.e_gb) * gs_gb;
+    f[YV] = (Iu - Iion - Isyn) / P.C;
+    f[YM] = r.am * (1.0 - m) - r.bm * m;
+    f[YH] = r.ah * (1.0 - h) - r.bh * h;
+    f[YN] = r.an * (1.0 - n) - r.bn * n;
+    const double a = is_ln ? K.a_ga : K.a_ach;
+    const double b = is_ln ? K.b_ga : K.b_ach;
+    const double T = is_ln ? release(V, K.vp_ga, K.kp_ga) : release(V, K.vp_ach, K.kp_ach);
+    f[YS] = a * T * (1.0 - s) - b * s;
+    if (is_ln && gabab) {
+        const double TB = release(V, K.vp_gb, K.kp_gb);
+        f[YR] = K.r1 * TB * (1.0 - Y[YR]) - K.r2 * Y[YR];
+        f[YG] = K.r3 * Y[YR] - K.r4 * Y[YG];
+    } else {
+        f[YR] = 0.0;
+        f[YG] = 0.0;
+    }
+}
+
+// Store a float64 value as a float32 pair (value, compensation); returns the
+// exact float64 sum of the pair, which becomes the carried state.
+__device__ inline double split_store(double y, float &hi, float &lo)
+{
+    hi = (float)y;
+    lo = (float)(y - (double)hi);
+    return (double)hi + (double)lo;
+}
+
+__device__ inline bool finite_d(double x)
+{
+    return !(x != x) && fabs(x) <= 1.7976931348623157e308;
+}
+
+}  // namespace psst

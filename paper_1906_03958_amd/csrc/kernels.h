@@ -1,0 +1,72 @@
+// kernels.h -- launch arguments shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hh_device.h"
+
+namespace psst {
+
+struct StimDev {
+    const float *i_const;       // [n_total] nA or null
+    const int32_t *pulse_ptr;   // [n_total + 1] or null
+    const int64_t *on_step, *off_step;
+    const float *amp;           // nA
+};
+
+struct RecDev {
+    float *v_out;               // [capacity x n_total] or null
+    int64_t stride, capacity;
+    int32_t *spike_count;       // [n_total] or null
+    float *spike_t;             // [n_total x spike_cap]
+    int32_t spike_cap;
+};
+
+// Arguments of the persistent per-instance kernel (one workgroup integrates
+// one instance for all steps of the call).
+struct WGArgs {
+    const InstDesc *desc;       // [n_instances]
+    const int32_t *order;       // launch-local block -> instance index
+    float *state;               // packed [14][n_total]
+    int64_t nt;                 // n_total
+    StimDev stim;
+    RecDev rec;
+    double dt;
+    int64_t n_steps, step0;
+    float *ckpt;                // [ceil(n_steps / K)][14 * n_total] or null
+    int32_t K;
+    int32_t lds_ld;             // activation buffer stride in LDS (max ld of the launch)
+    int32_t *flag;              // set to 1 when a state turns non-finite
+};
+
+typedef void (*wg_kernel_t)(WGArgs);
+
+// Kernel variant: threads per workgroup, neurons per thread, G in LDS.
+struct WGVariant {
+    int bs, npt;
+    bool glds;
+    const void *fn;
+};
+
+// All compiled variants (terminated by fn == nullptr).
+const WGVariant *wg_variants();
+const void *init_kernel();
+
+// LDS bytes a launch of the persistent kernel needs: two double-buffered
+// activation vectors of lds_ld floats, plus (G in LDS) the largest instance's
+// conductance floats n * ld (+ n_ln * ld with slow GABA).
+inline size_t wg_lds_bytes(bool glds, int lds_ld, int64_t max_g_floats)
+{
+    return sizeof(float) * (4 * (size_t)lds_ld + (glds ? (size_t)max_g_floats : 0));
+}
+
+struct InitArgs {
+    const InstDesc *desc;
+    int32_t n_inst;
+    const float *v0;
+    float *state;
+    int64_t nt;
+};
+
+}  // namespace psst

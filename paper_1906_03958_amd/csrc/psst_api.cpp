@@ -1,0 +1,843 @@
+// psst_api.cpp -- host runtime behind the C ABI in include/psst.h: argument
+// validation, device copies of networks, batch packing and scheduling, graph
+// submission and launch-shape tuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/psst.h"
+#include "kernels.h"
+#include "stage.h"
+
+using namespace psst;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static psst_status fail(psst_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return fail(e_ == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY        \
+                                                  : PSST_ERR_DEVICE,              \
+                        "%s failed: %s", #call, hipGetErrorString(e_));           \
+    } while (0)
+
+extern "C" const char *psst_last_error(void) { return g_err.c_str(); }
+extern "C" const char *psst_version(void) { return "psst-mi355x 0.1 (gfx950)"; }
+
+extern "C" int32_t psst_device_count(void)
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    return n;
+}
+
+static psst_status check_device(int *dev_out)
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+        return fail(PSST_ERR_DEVICE, "no HIP device available");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(PSST_ERR_DEVICE, "device %d is %s; this library is built for gfx950", dev,
+                    prop.gcnArchName);
+    *dev_out = dev;
+    return PSST_OK;
+}
+
+static bool is_finite_f(float x) { return std::isfinite(x); }
+
+// ---------------------------------------------------------------------------
+// networks
+// ---------------------------------------------------------------------------
+
+struct PathInfo {
+    int32_t type, pre0, pre1, post0, post1;
+    int64_t grad_off;   // offset of this block in a grad_g copy
+};
+
+struct psst_network {
+    int device = 0;
+    int32_t n = 0, n_pn = 0, ld = 0;
+    bool gabab = false;
+    float area = 0.f;
+    double cg = 0, ci = 0;
+    std::vector<PathInfo> paths;
+    int64_t grad_entries = 0;
+    // device
+    float *d_gt = nullptr, *d_gtb = nullptr, *d_prm = nullptr, *d_kin = nullptr;
+    uint8_t *d_maskt = nullptr;     // fast/slow mask transposed like gt (1 = synapse)
+    InstDesc desc{};
+    InstDesc *d_desc = nullptr;
+    int32_t *d_order = nullptr;
+    int32_t *d_flag = nullptr;
+    // host copies used for gradient scatter and sizing
+    std::vector<float> h_kin;
+    int64_t g_floats = 0;           // n * ld (+ n_ln * ld)
+};
+
+static void net_free(psst_network *n)
+{
+    if (!n) return;
+    hipFree(n->d_gt);
+    hipFree(n->d_gtb);
+    hipFree(n->d_prm);
+    hipFree(n->d_kin);
+    hipFree(n->d_maskt);
+    hipFree(n->d_desc);
+    hipFree(n->d_order);
+    hipFree(n->d_flag);
+    delete n;
+}
+
+static psst_status validate_network(const psst_neuron_params *p, int32_t n,
+                                    const psst_pathway *paths, int32_t np,
+                                    const psst_kinetics *kin)
+{
+    if (!p) return fail(PSST_ERR_INVALID_ARGUMENT, "params is NULL");
+    if (n < 1 || n > (1 << 20)) return fail(PSST_ERR_INVALID_ARGUMENT, "n_neurons=%d out of [1, 2^20]", n);
+    if (np < 0 || np > 64) return fail(PSST_ERR_INVALID_ARGUMENT, "n_pathways=%d out of [0, 64]", np);
+    if (np > 0 && !paths) return fail(PSST_ERR_INVALID_ARGUMENT, "pathways is NULL");
+    if (!kin) return fail(PSST_ERR_INVALID_ARGUMENT, "kinetics is NULL");
+    if (p->n_pn < 0 || p->n_pn > n) return fail(PSST_ERR_INVALID_ARGUMENT, "n_pn=%d out of [0, n]", p->n_pn);
+    if (!(p->area_cm2 > 0.f) || !is_finite_f(p->area_cm2))
+        return fail(PSST_ERR_INVALID_ARGUMENT, "area_cm2 must be positive and finite");
+    const float *vecs[7] = {p->C_m, p->g_Na, p->g_K, p->g_L, p->E_Na, p->E_K, p->E_L};
+    const char *names[7] = {"C_m", "g_Na", "g_K", "g_L", "E_Na", "E_K", "E_L"};
+    for (int k = 0; k < 7; ++k) {
+        if (!vecs[k]) return fail(PSST_ERR_INVALID_ARGUMENT, "params.%s is NULL", names[k]);
+        for (int i = 0; i < n; ++i)
+            if (!is_finite_f(vecs[k][i]))
+                return fail(PSST_ERR_INVALID_ARGUMENT, "params.%s[%d] is not finite", names[k], i);
+    }
+    for (int i = 0; i < n; ++i)
+        if (!(p->C_m[i] > 0.f)) return fail(PSST_ERR_INVALID_ARGUMENT, "C_m[%d] must be > 0", i);
+    for (int t = 0; t < 3; ++t) {
+        const float *f = &kin[t].alpha;
+        for (int k = 0; k < NKIN; ++k)
+            if (!is_finite_f(f[k])) return fail(PSST_ERR_INVALID_ARGUMENT, "kinetics[%d] field %d not finite", t, k);
+        if (kin[t].K_p == 0.f) return fail(PSST_ERR_INVALID_ARGUMENT, "kinetics[%d].K_p is 0", t);
+    }
+    const float hill = kin[PSST_SYN_GABA_B].hill_n;
+    bool has_gb = false;
+    for (int q = 0; q < np; ++q) has_gb |= paths[q].type == PSST_SYN_GABA_B;
+    if (has_gb) {
+        if (!(hill >= 1.f && hill <= 8.f && hill == std::floor(hill)))
+            return fail(PSST_ERR_INVALID_ARGUMENT, "kinetics[GABA_B].hill_n must be an integer in [1, 8]");
+        if (!(kin[PSST_SYN_GABA_B].K_d > 0.f))
+            return fail(PSST_ERR_INVALID_ARGUMENT, "kinetics[GABA_B].K_d must be > 0");
+    }
+    for (int q = 0; q < np; ++q) {
+        const psst_pathway &w = paths[q];
+        if (w.type < 0 || w.type > 2) return fail(PSST_ERR_INVALID_ARGUMENT, "pathway %d: bad type %d", q, w.type);
+        if (!(0 <= w.pre_begin && w.pre_begin < w.pre_end && w.pre_end <= n &&
+              0 <= w.post_begin && w.post_begin < w.post_end && w.post_end <= n))
+            return fail(PSST_ERR_INVALID_ARGUMENT, "pathway %d: empty or out-of-range block", q);
+        if (w.type == PSST_SYN_ACH && w.pre_end > p->n_pn)
+            return fail(PSST_ERR_INVALID_ARGUMENT, "pathway %d: cholinergic presynaptic range must lie in the PN rows", q);
+        if (w.type != PSST_SYN_ACH && w.pre_begin < p->n_pn)
+            return fail(PSST_ERR_INVALID_ARGUMENT, "pathway %d: GABA presynaptic range must lie in the LN rows", q);
+        if (!w.g_nS) return fail(PSST_ERR_INVALID_ARGUMENT, "pathway %d: g_nS is NULL", q);
+        const int64_t cnt = (int64_t)(w.post_end - w.post_begin) * (w.pre_end - w.pre_begin);
+        for (int64_t e = 0; e < cnt; ++e)
+            if (!is_finite_f(w.g_nS[e])) return fail(PSST_ERR_INVALID_ARGUMENT, "pathway %d: g_nS[%lld] not finite", q, (long long)e);
+        for (int r = 0; r < q; ++r) {
+            const psst_pathway &o = paths[r];
+            bool same_matrix = (o.type == PSST_SYN_GABA_B) == (w.type == PSST_SYN_GABA_B);
+            if (same_matrix && o.pre_begin < w.pre_end && w.pre_begin < o.pre_end &&
+                o.post_begin < w.post_end && w.post_begin < o.post_end && o.type == w.type)
+                return fail(PSST_ERR_INVALID_ARGUMENT, "pathways %d and %d of one type overlap", r, q);
+        }
+    }
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t n,
+                                           const psst_pathway *paths, int32_t np,
+                                           const psst_kinetics kin[3], psst_network **out)
+{
+    if (!out) return fail(PSST_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    psst_status s = validate_network(p, n, paths, np, kin);
+    if (s != PSST_OK) return s;
+    int dev = 0;
+    if ((s = check_device(&dev)) != PSST_OK) return s;
+
+    psst_network *net = new psst_network();
+    net->device = dev;
+    net->n = n;
+    net->n_pn = p->n_pn;
+    net->ld = (n + 3) & ~3;
+    net->area = p->area_cm2;
+    net->cg = 1e-6 / (double)p->area_cm2;
+    net->ci = 1e-3 / (double)p->area_cm2;
+    const int ld = net->ld, n_ln = n - p->n_pn;
+    for (int q = 0; q < np; ++q) net->gabab |= paths[q].type == PSST_SYN_GABA_B;
+
+    // transposed conductance matrices, padded rows: gt[j * ld + i]
+    std::vector<float> gt((size_t)n * ld, 0.f);
+    std::vector<float> gtb(net->gabab ? (size_t)n_ln * ld : 0, 0.f);
+    std::vector<uint8_t> mt((size_t)n * ld + gtb.size(), 0);
+    int64_t goff = 0;
+    for (int q = 0; q < np; ++q) {
+        const psst_pathway &w = paths[q];
+        PathInfo pi{w.type, w.pre_begin, w.pre_end, w.post_begin, w.post_end, goff};
+        net->paths.push_back(pi);
+        const int npre = w.pre_end - w.pre_begin;
+        for (int i = w.post_begin; i < w.post_end; ++i)
+            for (int j = w.pre_begin; j < w.pre_end; ++j) {
+                const int64_t e = (int64_t)(i - w.post_begin) * npre + (j - w.pre_begin);
+                const bool present = !w.mask || w.mask[e] != 0;
+                const float g = present ? w.g_nS[e] : 0.f;
+                if (w.type == PSST_SYN_GABA_B) {
+                    gtb[(size_t)(j - p->n_pn) * ld + i] = g;
+                    mt[(size_t)n * ld + (size_t)(j - p->n_pn) * ld + i] = present;
+                } else {
+                    gt[(size_t)j * ld + i] = g;
+                    mt[(size_t)j * ld + i] = present;
+                }
+            }
+        goff += (int64_t)(w.post_end - w.post_begin) * npre;
+    }
+    net->grad_entries = goff;
+    net->g_floats = (int64_t)n * ld + (int64_t)gtb.size();
+
+    std::vector<float> prm((size_t)NPRM * ld, 0.f);
+    const float *vecs[7] = {p->C_m, p->g_Na, p->g_K, p->g_L, p->E_Na, p->E_K, p->E_L};
+    for (int k = 0; k < 7; ++k)
+        for (int i = 0; i < ld; ++i) prm[(size_t)k * ld + i] = i < n ? vecs[k][i] : (k == 0 ? 1.f : 0.f);
+    net->h_kin.assign(&kin[0].alpha, &kin[0].alpha + 3 * NKIN);
+
+#define NETCHK(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            net_free(net);                                                        \
+            return fail(e_ == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY        \
+                                                  : PSST_ERR_DEVICE,              \
+                        "%s failed: %s", #call, hipGetErrorString(e_));           \
+        }                                                                         \
+    } while (0)
+
+    NETCHK(hipMalloc(&net->d_gt, sizeof(float) * gt.size()));
+    NETCHK(hipMemcpy(net->d_gt, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice));
+    if (!gtb.empty()) {
+        NETCHK(hipMalloc(&net->d_gtb, sizeof(float) * gtb.size()));
+        NETCHK(hipMemcpy(net->d_gtb, gtb.data(), sizeof(float) * gtb.size(), hipMemcpyHostToDevice));
+    }
+    NETCHK(hipMalloc(&net->d_maskt, mt.size()));
+    NETCHK(hipMemcpy(net->d_maskt, mt.data(), mt.size(), hipMemcpyHostToDevice));
+    NETCHK(hipMalloc(&net->d_prm, sizeof(float) * prm.size()));
+    NETCHK(hipMemcpy(net->d_prm, prm.data(), sizeof(float) * prm.size(), hipMemcpyHostToDevice));
+    NETCHK(hipMalloc(&net->d_kin, sizeof(float) * 3 * NKIN));
+    NETCHK(hipMemcpy(net->d_kin, net->h_kin.data(), sizeof(float) * 3 * NKIN, hipMemcpyHostToDevice));
+    InstDesc &d = net->desc;
+    d.gt = net->d_gt;
+    d.gtb = net->d_gtb;
+    d.prm = net->d_prm;
+    d.kin = net->d_kin;
+    d.off = 0;
+    d.n = n;
+    d.n_pn = p->n_pn;
+    d.ld = ld;
+    d.flags = net->gabab ? DESC_GABAB : 0;
+    d.cg = net->cg;
+    d.ci = net->ci;
+    NETCHK(hipMalloc(&net->d_desc, sizeof(InstDesc)));
+    NETCHK(hipMemcpy(net->d_desc, &d, sizeof(InstDesc), hipMemcpyHostToDevice));
+    int32_t zero = 0;
+    NETCHK(hipMalloc(&net->d_order, sizeof(int32_t)));
+    NETCHK(hipMemcpy(net->d_order, &zero, sizeof(int32_t), hipMemcpyHostToDevice));
+    NETCHK(hipMalloc(&net->d_flag, sizeof(int32_t)));
+    NETCHK(hipMemset(net->d_flag, 0, sizeof(int32_t)));
+#undef NETCHK
+    *out = net;
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_network_destroy(psst_network *net)
+{
+    if (!net) return fail(PSST_ERR_INVALID_ARGUMENT, "network is NULL");
+    net_free(net);
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_state_layout(const psst_network *net, int64_t *n_words, int32_t *n_vars)
+{
+    if (!net) return fail(PSST_ERR_INVALID_ARGUMENT, "network is NULL");
+    if (n_words) *n_words = 2LL * NVAR * net->n;
+    if (n_vars) *n_vars = NVAR;
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_network_grad_size(const psst_network *net, int64_t *n_entries)
+{
+    if (!net || !n_entries) return fail(PSST_ERR_INVALID_ARGUMENT, "NULL argument");
+    *n_entries = net->grad_entries;
+    return PSST_OK;
+}
+
+static psst_status launch_init(const InstDesc *d_desc, int32_t n_inst, const float *v0,
+                               float *state, int64_t nt, hipStream_t s)
+{
+    InitArgs a{d_desc, n_inst, v0, state, nt};
+    void *args[] = {&a};
+    HIPCHK(hipLaunchKernel(init_kernel(), dim3(n_inst), dim3(256), args, 0, s));
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_state_init(const psst_network *net, const float *v0, float *state,
+                                       void *stream)
+{
+    if (!net || !v0 || !state) return fail(PSST_ERR_INVALID_ARGUMENT, "NULL argument");
+    return launch_init(net->d_desc, 1, v0, state, net->n, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// the per-instance persistent kernel: variant choice and launch
+// ---------------------------------------------------------------------------
+
+static const WGVariant *find_variant(int bs, int npt, bool glds)
+{
+    for (const WGVariant *v = wg_variants(); v->fn; ++v)
+        if (v->bs == bs && v->npt == npt && v->glds == glds) return v;
+    return nullptr;
+}
+
+static size_t max_lds_per_block()
+{
+    static size_t cached = 0;
+    if (!cached) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cached = prop.sharedMemPerBlock;
+        if (!cached) cached = 65536;
+    }
+    return cached;
+}
+
+static psst_status set_lds_attr(const void *fn, size_t bytes)
+{
+    if (bytes > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return PSST_OK;
+}
+
+// Default variant for instances up to max_n neurons.
+static void default_shape(int max_n, int *bs, int *npt)
+{
+    if (max_n <= 64) { *bs = 64; *npt = 1; }
+    else if (max_n <= 128) { *bs = 128; *npt = 1; }
+    else if (max_n <= 256) { *bs = 256; *npt = 1; }
+    else if (max_n <= 512) { *bs = 256; *npt = 2; }
+    else { *bs = 256; *npt = 4; }
+}
+
+static const int kMaxWGNeurons = 1024;
+
+static psst_status validate_common(float dt, int64_t n_steps, int64_t step0, const psst_record *rec)
+{
+    if (!(dt > 0.f) || !is_finite_f(dt)) return fail(PSST_ERR_INVALID_ARGUMENT, "dt_ms must be positive and finite");
+    if (n_steps < 0) return fail(PSST_ERR_INVALID_ARGUMENT, "n_steps < 0");
+    if (step0 < 0) return fail(PSST_ERR_INVALID_ARGUMENT, "step0 < 0");
+    if (rec) {
+        if (rec->v_out && (rec->stride <= 0 || rec->capacity < 0))
+            return fail(PSST_ERR_INVALID_ARGUMENT, "record: v_out needs stride > 0 and capacity >= 0");
+        if (rec->spike_count && rec->spike_cap > 0 && !rec->spike_t_ms)
+            return fail(PSST_ERR_INVALID_ARGUMENT, "record: spike_cap > 0 needs spike_t_ms");
+        if (rec->spike_cap < 0) return fail(PSST_ERR_INVALID_ARGUMENT, "record: spike_cap < 0");
+    }
+    return PSST_OK;
+}
+
+static psst_status validate_stim(const psst_stimulus *st)
+{
+    if (st && st->pulse_ptr && (!st->on_step || !st->off_step || !st->amp_nA))
+        return fail(PSST_ERR_INVALID_ARGUMENT, "stimulus: pulse_ptr given without on/off/amp arrays");
+    return PSST_OK;
+}
+
+static StimDev to_dev(const psst_stimulus *st)
+{
+    StimDev s{};
+    if (st) {
+        s.i_const = st->i_const_nA;
+        s.pulse_ptr = st->pulse_ptr;
+        s.on_step = st->on_step;
+        s.off_step = st->off_step;
+        s.amp = st->amp_nA;
+    }
+    return s;
+}
+
+static RecDev to_dev(const psst_record *r)
+{
+    RecDev d{};
+    if (r) {
+        d.v_out = r->v_out;
+        d.stride = r->stride;
+        d.capacity = r->capacity;
+        d.spike_count = r->spike_count;
+        d.spike_t = r->spike_t_ms;
+        d.spike_cap = r->spike_cap;
+    }
+    return d;
+}
+
+extern "C" psst_status psst_integrate(psst_network *net, float *state, const psst_stimulus *stim,
+                                      float dt, int64_t n_steps, int64_t step0,
+                                      const psst_record *rec, void *stream)
+{
+    if (!net) return fail(PSST_ERR_INVALID_ARGUMENT, "network is NULL");
+    if (!state) return fail(PSST_ERR_INVALID_ARGUMENT, "state is NULL");
+    psst_status s = validate_common(dt, n_steps, step0, rec);
+    if (s != PSST_OK) return s;
+    if ((s = validate_stim(stim)) != PSST_OK) return s;
+    if (net->n > kMaxWGNeurons)
+        return stage_integrate_single(net, state, stim, dt, n_steps, step0, rec, stream);
+    if (n_steps == 0) return PSST_OK;
+    int bs, npt;
+    default_shape(net->n, &bs, &npt);
+    const int lds_ld = net->ld;
+    size_t lds_g = wg_lds_bytes(true, lds_ld, net->g_floats);
+    const bool glds = lds_g <= max_lds_per_block();
+    const WGVariant *v = find_variant(bs, npt, glds);
+    if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant for n=%d", net->n);
+    const size_t lds = wg_lds_bytes(glds, lds_ld, net->g_floats);
+    if ((s = set_lds_attr(v->fn, lds)) != PSST_OK) return s;
+    WGArgs a{};
+    a.desc = net->d_desc;
+    a.order = net->d_order;
+    a.state = state;
+    a.nt = net->n;
+    a.stim = to_dev(stim);
+    a.rec = to_dev(rec);
+    a.dt = (double)dt;
+    a.n_steps = n_steps;
+    a.step0 = step0;
+    a.ckpt = nullptr;
+    a.K = 1;
+    a.lds_ld = lds_ld;
+    a.flag = net->d_flag;
+    void *args[] = {&a};
+    HIPCHK(hipLaunchKernel(v->fn, dim3(1), dim3(bs), args, lds, (hipStream_t)stream));
+    return PSST_OK;
+}
+
+static psst_status poll_flag(int32_t *d_flag, void *stream)
+{
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    int32_t f = 0;
+    HIPCHK(hipMemcpy(&f, d_flag, sizeof f, hipMemcpyDeviceToHost));
+    if (f) {
+        int32_t z = 0;
+        HIPCHK(hipMemcpy(d_flag, &z, sizeof z, hipMemcpyHostToDevice));
+        return fail(PSST_ERR_NONFINITE, "a state variable became non-finite");
+    }
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_network_poll(psst_network *net, void *stream)
+{
+    if (!net) return fail(PSST_ERR_INVALID_ARGUMENT, "network is NULL");
+    return poll_flag(net->d_flag, stream);
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+struct Group {
+    std::vector<int32_t> order;     // instance indices, largest first
+    int32_t *d_order = nullptr;
+    int max_n = 0, lds_ld = 0;
+    int64_t max_g = 0;
+    bool glds = false;
+    int bs = 0, npt = 0;
+    size_t lds = 0;
+};
+
+struct psst_batch {
+    std::vector<psst_network *> nets;
+    int32_t n = 0;
+    int64_t nt = 0;
+    std::vector<int64_t> offsets;
+    InstDesc *d_desc = nullptr;
+    std::vector<Group> groups;
+    int32_t *d_flag = nullptr;
+    bool shared = false;            // every instance is the same network
+    bool stage_path = false;        // large shared network: per-stage kernels
+    StageBatch *stage = nullptr;
+    std::string describe;
+    // graph of the persistent launches
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> nodes;
+    std::vector<WGArgs> node_args;
+};
+
+static void batch_free(psst_batch *b)
+{
+    if (!b) return;
+    for (auto &g : b->groups) hipFree(g.d_order);
+    hipFree(b->d_desc);
+    hipFree(b->d_flag);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    stage_batch_free(b->stage);
+    delete b;
+}
+
+static WGArgs group_args(psst_batch *b, const Group &g, float *states, const psst_stimulus *stim,
+                         float dt, int64_t n_steps, int64_t step0, const psst_record *rec,
+                         float *ckpt, int32_t K)
+{
+    WGArgs a{};
+    a.desc = b->d_desc;
+    a.order = g.d_order;
+    a.state = states;
+    a.nt = b->nt;
+    a.stim = to_dev(stim);
+    a.rec = to_dev(rec);
+    a.dt = (double)dt;
+    a.n_steps = n_steps;
+    a.step0 = step0;
+    a.ckpt = ckpt;
+    a.K = K > 0 ? K : 1;
+    a.lds_ld = g.lds_ld;
+    a.flag = b->d_flag;
+    return a;
+}
+
+static psst_status launch_group(const Group &g, WGArgs &a, hipStream_t s)
+{
+    const WGVariant *v = find_variant(g.bs, g.npt, g.glds);
+    if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant bs=%d npt=%d", g.bs, g.npt);
+    psst_status st = set_lds_attr(v->fn, g.lds);
+    if (st != PSST_OK) return st;
+    void *args[] = {&a};
+    HIPCHK(hipLaunchKernel(v->fn, dim3((unsigned)g.order.size()), dim3(g.bs), args, g.lds, s));
+    return PSST_OK;
+}
+
+// Time candidate shapes for one group on a scratch state (short run, no
+// stimulus, no recording) and keep the fastest.
+static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream_t s)
+{
+    std::vector<std::pair<int, int>> cands;
+    for (const WGVariant *v = wg_variants(); v->fn; ++v) {
+        if (v->glds != g.glds) continue;
+        const int cap = v->bs * v->npt;
+        if (cap < g.max_n || cap >= 4 * std::max(g.max_n, 64)) continue;
+        cands.push_back({v->bs, v->npt});
+    }
+    if (cands.size() <= 1) return PSST_OK;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bbs = g.bs, bnpt = g.npt;
+    for (auto &c : cands) {
+        Group t = g;
+        t.bs = c.first;
+        t.npt = c.second;
+        WGArgs a = group_args(b, t, scratch, nullptr, 0.01f, 4, 0, nullptr, nullptr, 1);
+        psst_status st = launch_group(t, a, s);        // warm-up
+        if (st != PSST_OK) return st;
+        a.n_steps = 16;
+        HIPCHK(hipEventRecord(e0, s));
+        if ((st = launch_group(t, a, s)) != PSST_OK) return st;
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; bbs = c.first; bnpt = c.second; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g.bs = bbs;
+    g.npt = bnpt;
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, psst_batch **out)
+{
+    if (!out) return fail(PSST_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    if (!nets) return fail(PSST_ERR_INVALID_ARGUMENT, "nets is NULL");
+    if (n < 1 || n > (1 << 20)) return fail(PSST_ERR_INVALID_ARGUMENT, "n=%d out of [1, 2^20]", n);
+    for (int32_t k = 0; k < n; ++k)
+        if (!nets[k]) return fail(PSST_ERR_INVALID_ARGUMENT, "nets[%d] is NULL", k);
+    int dev = 0;
+    psst_status s = check_device(&dev);
+    if (s != PSST_OK) return s;
+
+    psst_batch *b = new psst_batch();
+    b->nets.assign(nets, nets + n);
+    b->n = n;
+    b->offsets.resize(n + 1);
+    b->offsets[0] = 0;
+    b->shared = true;
+    for (int32_t k = 0; k < n; ++k) {
+        b->offsets[k + 1] = b->offsets[k] + nets[k]->n;
+        b->shared &= nets[k] == nets[0];
+    }
+    b->nt = b->offsets[n];
+
+#define BCHK(call)                                                                \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            batch_free(b);                                                        \
+            return fail(e_ == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY        \
+                                                  : PSST_ERR_DEVICE,              \
+                        "%s failed: %s", #call, hipGetErrorString(e_));           \
+        }                                                                         \
+    } while (0)
+
+    BCHK(hipMalloc(&b->d_flag, sizeof(int32_t)));
+    BCHK(hipMemset(b->d_flag, 0, sizeof(int32_t)));
+    std::vector<InstDesc> desc(n);
+    for (int32_t k = 0; k < n; ++k) {
+        desc[k] = nets[k]->desc;
+        desc[k].off = b->offsets[k];
+    }
+    BCHK(hipMalloc(&b->d_desc, sizeof(InstDesc) * n));
+    BCHK(hipMemcpy(b->d_desc, desc.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
+
+    int max_n = 0;
+    for (auto *q : b->nets) max_n = std::max(max_n, q->n);
+    if (max_n > kMaxWGNeurons) {
+        if (!b->shared) {
+            batch_free(b);
+            return fail(PSST_ERR_UNSUPPORTED,
+                        "instances above %d neurons are supported when all instances share one network",
+                        kMaxWGNeurons);
+        }
+        b->stage_path = true;
+        s = stage_batch_create(nets[0], n, &b->stage);
+        if (s != PSST_OK) {
+            batch_free(b);
+            return s;
+        }
+        b->describe = stage_batch_describe(b->stage);
+        *out = b;
+        return PSST_OK;
+    }
+
+    // Largest-first (LPT) order by cost ~ n^2, then tiers by where G lives:
+    // G in LDS when the instance's conductances fit, with the LDS request
+    // sized per tier so small instances keep several workgroups per CU.
+    std::vector<int32_t> idx(n);
+    for (int32_t k = 0; k < n; ++k) idx[k] = k;
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+        return nets[x]->g_floats > nets[y]->g_floats;
+    });
+    const size_t lmax = max_lds_per_block();
+    const size_t tiers[3] = {lmax / 4, lmax / 2, lmax};
+    const char *env = std::getenv("PSST_LDS_G");
+    const bool allow_lds = !(env && env[0] == '0');
+    std::vector<Group> groups(4);     // tiers 0..2 in LDS, 3 = G from global memory
+    for (int32_t k : idx) {
+        const psst_network *q = nets[k];
+        int t = 3;
+        for (int c = 0; c < 3 && allow_lds; ++c)
+            if (wg_lds_bytes(true, q->ld, q->g_floats) <= tiers[c]) { t = c; break; }
+        Group &g = groups[t];
+        g.order.push_back(k);
+        g.max_n = std::max(g.max_n, q->n);
+        g.lds_ld = std::max(g.lds_ld, q->ld);
+        g.max_g = std::max(g.max_g, q->g_floats);
+        g.glds = t < 3;
+    }
+    for (auto &g : groups) {
+        if (g.order.empty()) continue;
+        default_shape(g.max_n, &g.bs, &g.npt);
+        g.lds = wg_lds_bytes(g.glds, g.lds_ld, g.max_g);
+        BCHK(hipMalloc(&g.d_order, sizeof(int32_t) * g.order.size()));
+        BCHK(hipMemcpy(g.d_order, g.order.data(), sizeof(int32_t) * g.order.size(), hipMemcpyHostToDevice));
+        b->groups.push_back(g);
+    }
+    // launch-shape tuning on a scratch state
+    const char *tenv = std::getenv("PSST_TUNE");
+    if (!(tenv && tenv[0] == '0')) {
+        float *scratch = nullptr;
+        float *v0 = nullptr;
+        BCHK(hipMalloc(&scratch, sizeof(float) * 14 * b->nt));
+        BCHK(hipMalloc(&v0, sizeof(float) * b->nt));
+        std::vector<float> hv(b->nt, -65.f);
+        BCHK(hipMemcpy(v0, hv.data(), sizeof(float) * b->nt, hipMemcpyHostToDevice));
+        hipStream_t st;
+        BCHK(hipStreamCreate(&st));
+        s = launch_init(b->d_desc, n, v0, scratch, b->nt, st);
+        for (auto &g : b->groups)
+            if (s == PSST_OK) s = tune_group(b, g, scratch, st);
+        hipStreamSynchronize(st);
+        hipStreamDestroy(st);
+        hipFree(scratch);
+        hipFree(v0);
+        BCHK(hipMemset(b->d_flag, 0, sizeof(int32_t)));
+        if (s != PSST_OK) {
+            batch_free(b);
+            return s;
+        }
+    }
+#undef BCHK
+    char buf[256];
+    for (auto &g : b->groups) {
+        snprintf(buf, sizeof buf, "[%zu inst, n<=%d, G in %s, %d thr x %d, lds %zu B] ",
+                 g.order.size(), g.max_n, g.glds ? "LDS" : "global", g.bs, g.npt, g.lds);
+        b->describe += buf;
+    }
+    *out = b;
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_batch_destroy(psst_batch *b)
+{
+    if (!b) return fail(PSST_ERR_INVALID_ARGUMENT, "batch is NULL");
+    batch_free(b);
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_batch_layout(const psst_batch *b, int64_t *n_total, int64_t *n_words,
+                                         int64_t *offsets)
+{
+    if (!b) return fail(PSST_ERR_INVALID_ARGUMENT, "batch is NULL");
+    if (n_total) *n_total = b->nt;
+    if (n_words) *n_words = 2LL * NVAR * b->nt;
+    if (offsets) std::memcpy(offsets, b->offsets.data(), sizeof(int64_t) * (b->n + 1));
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_batch_describe(const psst_batch *b, char *buf, int32_t len)
+{
+    if (!b || !buf || len <= 0) return fail(PSST_ERR_INVALID_ARGUMENT, "bad argument");
+    snprintf(buf, len, "%s", b->describe.c_str());
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_batch_state_init(const psst_batch *b, const float *v0, float *states,
+                                             void *stream)
+{
+    if (!b || !v0 || !states) return fail(PSST_ERR_INVALID_ARGUMENT, "NULL argument");
+    return launch_init(b->d_desc, b->n, v0, states, b->nt, (hipStream_t)stream);
+}
+
+// Build (first call) or update the graph holding one kernel node per group;
+// the nodes are independent, so tiers may run side by side.
+static psst_status submit_graph(psst_batch *b, std::vector<WGArgs> &args, hipStream_t s)
+{
+    const size_t G = b->groups.size();
+    if (!b->exec) {
+        HIPCHK(hipGraphCreate(&b->graph, 0));
+        b->nodes.resize(G);
+        b->node_args = args;
+        for (size_t k = 0; k < G; ++k) {
+            const Group &g = b->groups[k];
+            const WGVariant *v = find_variant(g.bs, g.npt, g.glds);
+            if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant");
+            psst_status st = set_lds_attr(v->fn, g.lds);
+            if (st != PSST_OK) return st;
+            void *kp[] = {&b->node_args[k]};
+            hipKernelNodeParams p{};
+            p.func = const_cast<void *>(v->fn);
+            p.gridDim = dim3((unsigned)g.order.size());
+            p.blockDim = dim3(g.bs);
+            p.sharedMemBytes = (unsigned)g.lds;
+            p.kernelParams = kp;
+            p.extra = nullptr;
+            HIPCHK(hipGraphAddKernelNode(&b->nodes[k], b->graph, nullptr, 0, &p));
+        }
+        HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    } else {
+        for (size_t k = 0; k < G; ++k) {
+            if (std::memcmp(&b->node_args[k], &args[k], sizeof(WGArgs)) == 0) continue;
+            b->node_args[k] = args[k];
+            const Group &g = b->groups[k];
+            const WGVariant *v = find_variant(g.bs, g.npt, g.glds);
+            void *kp[] = {&b->node_args[k]};
+            hipKernelNodeParams p{};
+            p.func = const_cast<void *>(v->fn);
+            p.gridDim = dim3((unsigned)g.order.size());
+            p.blockDim = dim3(g.bs);
+            p.sharedMemBytes = (unsigned)g.lds;
+            p.kernelParams = kp;
+            p.extra = nullptr;
+            HIPCHK(hipGraphExecKernelNodeSetParams(b->exec, b->nodes[k], &p));
+        }
+    }
+    HIPCHK(hipGraphLaunch(b->exec, s));
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_integrate_batch(psst_batch *b, float *states, const psst_stimulus *stim,
+                                            float dt, int64_t n_steps, int64_t step0,
+                                            const psst_record *rec, float *ckpt, int32_t K,
+                                            void *stream)
+{
+    if (!b) return fail(PSST_ERR_INVALID_ARGUMENT, "batch is NULL");
+    if (!states) return fail(PSST_ERR_INVALID_ARGUMENT, "states is NULL");
+    psst_status s = validate_common(dt, n_steps, step0, rec);
+    if (s != PSST_OK) return s;
+    if ((s = validate_stim(stim)) != PSST_OK) return s;
+    if (ckpt && K <= 0) return fail(PSST_ERR_INVALID_ARGUMENT, "checkpoints need K > 0");
+    if (b->stage_path)
+        return stage_batch_integrate(b->stage, states, stim, dt, n_steps, step0, rec, ckpt, K,
+                                     stream);
+    if (n_steps == 0) return PSST_OK;
+    std::vector<WGArgs> args;
+    for (auto &g : b->groups)
+        args.push_back(group_args(b, g, states, stim, dt, n_steps, step0, rec, ckpt, K));
+    return submit_graph(b, args, (hipStream_t)stream);
+}
+
+extern "C" psst_status psst_batch_poll(psst_batch *b, void *stream)
+{
+    if (!b) return fail(PSST_ERR_INVALID_ARGUMENT, "batch is NULL");
+    if (b->stage_path) return stage_batch_poll(b->stage, stream);
+    return poll_flag(b->d_flag, stream);
+}
+
+extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
+                                    const psst_stimulus *stim, float dt, int64_t n_steps,
+                                    int64_t step0, const float *dLdV, float *grad_g,
+                                    float *grad_gNa, float *grad_gK, float *grad_gL,
+                                    int32_t per_instance, void *stream)
+{
+    if (!b) return fail(PSST_ERR_INVALID_ARGUMENT, "batch is NULL");
+    if (!ckpt || !dLdV || !grad_g || !grad_gNa || !grad_gK || !grad_gL)
+        return fail(PSST_ERR_INVALID_ARGUMENT, "NULL buffer");
+    if (K <= 0) return fail(PSST_ERR_INVALID_ARGUMENT, "K must be > 0");
+    psst_status s = validate_common(dt, n_steps, step0, nullptr);
+    if (s != PSST_OK) return s;
+    if ((s = validate_stim(stim)) != PSST_OK) return s;
+    if (!per_instance && !b->shared)
+        return fail(PSST_ERR_INVALID_ARGUMENT, "summed gradients need every instance to share one network");
+    return fail(PSST_ERR_UNSUPPORTED, "adjoint not built yet");
+}
