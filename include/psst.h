@@ -34,11 +34,14 @@
  *     (intrinsic g).  With membrane area A (cm^2), 1 nS = 1e-6/A mS/cm^2 and
  *     1 nA = 1e-3/A uA/cm^2.
  *
- * Numerics: the per-neuron right-hand side (rate functions, currents, gating
- * ODEs) and the RK4 stage arithmetic run in float64; the synaptic products
- * sum_j g_ij x_j run in float32 (g in nS as given, x rounded to float32);
+ * Numerics: conductances are kept as the float32 values given; the
+ * per-neuron right-hand side (rate functions, currents, gating ODEs), the RK4
+ * stage arithmetic and the synaptic sums sum_j g_ij x_j run in float64 (each
+ * product of a float32 g and a float64 activation is exact before the sum);
  * each state variable is stored as a float32 pair (value, compensation) whose
- * sum is the float64-rounded state after every step.
+ * sum is the state after every step, rounded to 48 significant bits.  Large
+ * shared networks on the per-stage path (more than 1024 neurons) take the
+ * synaptic sums from a float32 matrix-core GEMM instead.
  */
 #ifndef PSST_H
 #define PSST_H

@@ -54,11 +54,11 @@ const WGVariant *wg_variants();
 const void *init_kernel();
 
 // LDS bytes a launch of the persistent kernel needs: two double-buffered
-// activation vectors of lds_ld floats, plus (G in LDS) the largest instance's
-// conductance floats n * ld (+ n_ln * ld with slow GABA).
+// float64 activation vectors of lds_ld entries, plus (G in LDS) the largest
+// instance's conductance floats n * ld (+ n_ln * ld with slow GABA).
 inline size_t wg_lds_bytes(bool glds, int lds_ld, int64_t max_g_floats)
 {
-    return sizeof(float) * (4 * (size_t)lds_ld + (glds ? (size_t)max_g_floats : 0));
+    return sizeof(double) * 4 * (size_t)lds_ld + sizeof(float) * (glds ? (size_t)max_g_floats : 0);
 }
 
 struct InitArgs {

@@ -4,21 +4,25 @@
 // Per step (paper, "Brain simulations as computational graphs": RK4 with four
 // evaluations of f; vectorised per-neuron equations) and per stage:
 //   1. stage input Y = y + c_q dt k_{q-1} (registers, float64);
-//   2. presynaptic activations x_j (float32) into a double-buffered LDS vector;
+//   2. presynaptic activations x_j (float64) into a double-buffered LDS vector;
 //   3. synaptic products sum_j g_ij x_j ("Circumventing memory constraints",
 //      item 1: the synaptic update is a matrix-vector product) with the
 //      transposed conductance matrix read row by row: thread i reads
 //      gt[j * ld + i], so each wavefront load is 256 contiguous bytes and x_j
 //      is an LDS broadcast; G comes from LDS when it fits, else from
-//      L2/MALL/HBM;
+//      L2/MALL/HBM.  G stays float32 (the given values); each product is
+//      widened and summed in float64 -- float32 sums over a few hundred
+//      synapses drift past 1e-3 mV within 50 ms, and on this chip a float64
+//      FMA issues at the float32 rate, so the LDS-fed loop stays bound by LDS
+//      bandwidth and the HBM-fed loop by HBM;
 //   4. per-neuron right-hand side (float64) and RK4 accumulation.
 // Then the combine y <- y + dt/6 (k1 + 2 k2 + 2 k3 + k4), stored as a float32
 // pair, spike detection and recording.  One barrier per stage.
 //
 // Instance b's arithmetic does not depend on the workgroup size, on the other
 // instances or on where its conductances live: the products are summed in
-// column order j = 0, 1, ... with fmaf, so every variant gives bitwise the
-// same trajectory.
+// column order j = 0, 1, ... with one float64 fma each, so every variant gives
+// bitwise the same trajectory.
 #include "kernels.h"
 
 namespace psst {
@@ -34,13 +38,13 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
     const bool gabab = (d.flags & DESC_GABAB) != 0;
     const int tid = threadIdx.x;
     const int LX = a.lds_ld;
-    float *xf = lds;               // [2][LX] fast activations (s_j)
-    float *xb = lds + 2 * LX;      // [2][LX] slow activations (G^n / (G^n + K_d))
+    double *xf = reinterpret_cast<double *>(lds);   // [2][LX] fast activations (s_j)
+    double *xb = xf + 2 * LX;                       // [2][LX] slow activations
 
     const float *G = d.gt;
     const float *GB = d.gtb;
     if (GLDS) {
-        float *gl = lds + 4 * LX;
+        float *gl = lds + 8 * LX;
         const int64_t nf = (int64_t)n * ld;
         for (int64_t e = tid; e < nf; e += BS) gl[e] = d.gt[e];
         if (gabab) {
@@ -119,44 +123,44 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
         }
 #pragma unroll 1
         for (int q = 0; q < 4; ++q) {
-            float *xfq = xf + (q & 1) * LX;
-            float *xbq = xb + (q & 1) * LX;
+            double *xfq = xf + (q & 1) * LX;
+            double *xbq = xb + (q & 1) * LX;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 const int i = tid + k * BS;
                 if (own[k]) {
-                    xfq[i] = (float)Y[k][YS];
-                    if (gabab && i >= n_pn) xbq[i - n_pn] = (float)gabab_act(Y[k][YG], K);
+                    xfq[i] = Y[k][YS];
+                    if (gabab && i >= n_pn) xbq[i - n_pn] = gabab_act(Y[k][YG], K);
                 }
             }
             __syncthreads();
-            float sa[NPT], sg[NPT], sb[NPT];
+            double sa[NPT], sg[NPT], sb[NPT];
 #pragma unroll
-            for (int k = 0; k < NPT; ++k) { sa[k] = 0.f; sg[k] = 0.f; sb[k] = 0.f; }
+            for (int k = 0; k < NPT; ++k) { sa[k] = 0.0; sg[k] = 0.0; sb[k] = 0.0; }
 #pragma unroll 4
             for (int j = 0; j < n_pn; ++j) {
-                const float x = xfq[j];
+                const double x = xfq[j];
                 const float *row = G + (int64_t)j * ld;
 #pragma unroll
                 for (int k = 0; k < NPT; ++k)
-                    if (k * BS < n) sa[k] = fmaf(row[ik[k]], x, sa[k]);
+                    if (k * BS < n) sa[k] = fma((double)row[ik[k]], x, sa[k]);
             }
 #pragma unroll 4
             for (int j = n_pn; j < n; ++j) {
-                const float x = xfq[j];
+                const double x = xfq[j];
                 const float *row = G + (int64_t)j * ld;
 #pragma unroll
                 for (int k = 0; k < NPT; ++k)
-                    if (k * BS < n) sg[k] = fmaf(row[ik[k]], x, sg[k]);
+                    if (k * BS < n) sg[k] = fma((double)row[ik[k]], x, sg[k]);
             }
             if (gabab) {
 #pragma unroll 4
                 for (int j = 0; j < n_ln; ++j) {
-                    const float x = xbq[j];
+                    const double x = xbq[j];
                     const float *row = GB + (int64_t)j * ld;
 #pragma unroll
                     for (int k = 0; k < NPT; ++k)
-                        if (k * BS < n) sb[k] = fmaf(row[ik[k]], x, sb[k]);
+                        if (k * BS < n) sb[k] = fma((double)row[ik[k]], x, sb[k]);
                 }
             }
 #pragma unroll
@@ -168,8 +172,8 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
                 P.gL = pr[k][P_GL]; P.ENa = pr[k][P_ENA]; P.EK = pr[k][P_EK];
                 P.EL = pr[k][P_EL];
                 double f[NVAR];
-                hh_rhs(Y[k], P, K, d.cg * (double)sa[k], d.cg * (double)sg[k],
-                       d.cg * (double)sb[k], Iu[k], i >= n_pn, gabab, f);
+                hh_rhs(Y[k], P, K, d.cg * sa[k], d.cg * sg[k], d.cg * sb[k], Iu[k],
+                       i >= n_pn, gabab, f);
                 const double w = (q == 0 || q == 3) ? 1.0 : 2.0;
                 const double c = (q == 2) ? dt : 0.5 * dt;
 #pragma unroll
