@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark: batched RK4 integration of 4096 independent antennal-lobe-shaped
+Hodgkin-Huxley networks on one MI355X, against the plain one-network-per-launch
+form and the FP64 CPU oracle.
+
+One bench step = one launch of the batched persistent kernel (a graph launch)
+advancing every instance by --chunk RK4 steps, with spike detection and a V
+trace every 100 steps.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (see the keys at the end of main()).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "neuron-RK4-steps/s batched vs plain at stated error; adjoint steps/s"
+HBM_PEAK_GBS = 8000.0
+DT = 0.01
+REC_STRIDE = 100
+SPIKE_CAP = 64
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stratified(sizes, k):
+    order = np.argsort(sizes, kind="stable")
+    return [int(b) for b in order[np.linspace(0, len(sizes) - 1, k).astype(int)]]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed bench steps")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--chunk", type=int, default=100, help="RK4 steps per bench step")
+    ap.add_argument("--instances", type=int, default=4096)
+    ap.add_argument("--plain-instances", type=int, default=256)
+    ap.add_argument("--plain-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=5000,
+                    help="RK4 steps of the oracle sample (also the parity window)")
+    ap.add_argument("--cpu-instances", type=int, default=128)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized float32 buffer 5 times (reference kernel "
+                         "for scaling HBM counters) and exit")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(instances are independent: a multi-GPU run would shard them with no "
+              "communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1906_03958_amd import psst
+    from paper_1906_03958_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "launches": 5}))
+        return
+
+    # ---------------- workload: batched config -----------------------------
+    t0 = time.time()
+    insts = W.config3(args.instances)
+    sizes = np.array([i.net.n for i in insts])
+    sum_n = int(sizes.sum())
+    sum_n2 = int((sizes.astype(np.int64) ** 2).sum())
+    log(f"generated {len(insts)} instances, sum N = {sum_n}, sum N^2 = {sum_n2} "
+        f"({time.time() - t0:.1f}s)")
+    t0 = time.time()
+    nets = [psst.network_create(i.net) for i in insts]
+    batch = psst.batch_create(nets)
+    log(f"networks + batch (tuned) in {time.time() - t0:.1f}s: {psst.batch_describe(batch)}")
+    v0 = torch.from_numpy(np.concatenate([i.v0 for i in insts])).to(dev)
+    stim = psst.pack_stimulus([i.stim for i in insts], dev)
+    states = torch.zeros(14 * sum_n, dtype=torch.float32, device=dev)
+    psst.batch_state_init(batch, v0, states)
+    rows = args.chunk // REC_STRIDE
+    vtrace = torch.zeros((max(rows, 1), sum_n), dtype=torch.float32, device=dev)
+    cnt = torch.zeros(sum_n, dtype=torch.int32, device=dev)
+    spk = torch.zeros((sum_n, SPIKE_CAP), dtype=torch.float32, device=dev)
+
+    step0 = 0
+
+    def bench_step():
+        nonlocal step0
+        rec = psst.DeviceRecord(vtrace if rows else None, REC_STRIDE, rows, cnt, spk, SPIKE_CAP)
+        psst.integrate_batch(batch, states, stim, DT, args.chunk, step0, rec)
+        step0 += args.chunk
+
+    for _ in range(args.warmup):
+        bench_step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    launch_ms = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ev0.record(stream)
+        bench_step()
+        ev1.record(stream)
+        ev1.synchronize()
+        launch_ms.append(ev0.elapsed_time(ev1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    psst.batch_poll(batch)
+    value = sum_n * args.chunk * args.steps / wall
+    ms_per_step = 1e3 * wall / args.steps
+    avg_launch_s = float(np.mean(launch_ms)) / 1e3
+    log(f"batched: {value:.3e} neuron-steps/s, {ms_per_step:.2f} ms per bench step "
+        f"({1e3 * ms_per_step / args.chunk:.1f} us per RK4 step)")
+
+    # algorithmic bytes per RK4 step: the conductances once per stage
+    # (16 sum N^2) plus state and compensation words in and out (80 sum N)
+    bytes_per_rk4 = 16 * sum_n2 + 80 * sum_n
+    bytes_per_launch = bytes_per_rk4 * args.chunk
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    src = os.path.join(ROOT, "paper_1906_03958_amd", "csrc", "rk4_wg.hip")
+    ksha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "rk4_batch_traffic.json")
+    if os.path.exists(tfile):
+        t = json.load(open(tfile))
+        if t.get("kernel_source_sha") == ksha and t.get("chunk") == args.chunk and \
+                t.get("instances") == args.instances:
+            traffic = t.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "rk4_wg_kernel (batched persistent RK4)",
+                "avg_launch_ms": round(1e3 * avg_launch_s, 3),
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    # ---------------- plain form: one network per launch ------------------
+    plain = None
+    if not args.no_plain:
+        pick = stratified(sizes, min(args.plain_instances, len(insts)))
+        tot_ns, tot_t = 0, 0.0
+        for b in pick:
+            inst, net = insts[b], nets[b]
+            st = torch.zeros(14 * inst.net.n, dtype=torch.float32, device=dev)
+            psst.state_init(net, torch.from_numpy(inst.v0).to(dev), st)
+            s1 = psst.pack_stimulus([inst.stim], dev)
+            psst.integrate(net, st, s1, DT, 10, 0)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            psst.integrate(net, st, s1, DT, args.plain_steps, 10)
+            ev1.record(stream)
+            ev1.synchronize()
+            tot_t += ev0.elapsed_time(ev1) / 1e3
+            tot_ns += inst.net.n * args.plain_steps
+        plain = {"value": tot_ns / tot_t, "unit": "neuron-steps/s",
+                 "sample": f"{len(pick)} instances stratified by size, {args.plain_steps} RK4 "
+                           "steps each, one psst_integrate launch per network"}
+        log(f"plain: {plain['value']:.3e} neuron-steps/s")
+
+    # ---------------- CPU baseline (oracle) and parity spot check ---------
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        import oracle
+        pick = stratified(sizes, min(args.cpu_instances, len(insts)))
+        sub = [insts[b] for b in pick]
+        threads = min(os.cpu_count() or 1, 16)
+        t0 = time.perf_counter()
+        res = oracle.run_many(sub, args.cpu_steps, dt=DT, rec_stride=10, threads=threads)
+        ct = time.perf_counter() - t0
+        ns = sum(i.net.n for i in sub) * args.cpu_steps
+        cpu = {"value": ns / ct, "unit": "neuron-steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(sub)} instances stratified by size, {args.cpu_steps} RK4 steps "
+                         f"each ({ct:.1f} s wall on {threads} threads)"}
+        log(f"cpu oracle: {cpu['value']:.3e} neuron-steps/s on {threads} threads")
+        # same instances from their initial state on the GPU, V every 10 steps
+        states2 = torch.zeros_like(states)
+        psst.batch_state_init(batch, v0, states2)
+        r2 = args.cpu_steps // 10
+        vt2 = torch.zeros((r2, sum_n), dtype=torch.float32, device=dev)
+        psst.integrate_batch(batch, states2, stim, DT, args.cpu_steps, 0,
+                             psst.DeviceRecord(vt2, 10, r2))
+        psst.batch_poll(batch)
+        vt2 = vt2.cpu().numpy()
+        worst = 0.0
+        for b, (r, _) in zip(pick, res):
+            a0, a1 = batch.offsets[b], batch.offsets[b + 1]
+            worst = max(worst, float(np.abs(vt2[:, a0:a1] - r["v"]).max()))
+        parity = {"max_abs_dV_mV": worst, "tolerance_mV": 1e-3,
+                  "window_ms": args.cpu_steps * DT, "instances": len(pick),
+                  "pass": bool(worst <= 1e-3)}
+        log(f"parity spot check: max|dV| = {worst:.3e} mV over {args.cpu_steps * DT} ms")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "neuron-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "storage": "f32 (state as value+compensation pairs; conductances as given)",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(insts)} independent antennal-lobe-shaped HH "
+                               "networks, 60-480 neurons (PN:LN 3:1), Bernoulli(0.5) ACh + "
+                               "fast-GABA synapses, g ~ U(0,0.5) nS x LogNormal(0,0.1), "
+                               "I ~ U(0,2) nA, dt 0.01 ms",
+                   "instances": len(insts), "neurons": sum_n, "rk4_steps_per_step": args.chunk,
+                   "dt_ms": DT, "recording": f"spikes + V every {REC_STRIDE} steps",
+                   "launch": psst.batch_describe(batch)},
+        "plain": plain,
+        "batched_over_plain": (value / plain["value"]) if plain else None,
+        "parity": parity,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

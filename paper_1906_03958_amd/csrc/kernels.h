@@ -36,16 +36,16 @@ struct WGArgs {
     int64_t n_steps, step0;
     float *ckpt;                // [ceil(n_steps / K)][14 * n_total] or null
     int32_t K;
-    int32_t lds_ld;             // activation buffer stride in LDS (max ld of the launch)
+    int64_t lds_bytes;          // dynamic LDS of the launch; instances whose
+                                // conductances fit keep them in LDS
     int32_t *flag;              // set to 1 when a state turns non-finite
 };
 
 typedef void (*wg_kernel_t)(WGArgs);
 
-// Kernel variant: threads per workgroup, neurons per thread, G in LDS.
+// Kernel variant: threads per workgroup, neurons per thread.
 struct WGVariant {
     int bs, npt;
-    bool glds;
     const void *fn;
 };
 
@@ -53,12 +53,24 @@ struct WGVariant {
 const WGVariant *wg_variants();
 const void *init_kernel();
 
-// LDS bytes a launch of the persistent kernel needs: two double-buffered
-// float64 activation vectors of lds_ld entries, plus (G in LDS) the largest
-// instance's conductance floats n * ld (+ n_ln * ld with slow GABA).
-inline size_t wg_lds_bytes(bool glds, int lds_ld, int64_t max_g_floats)
+// Column chunk width of the synaptic sums (fixed summation structure).
+constexpr int kChunkWidth = 64;
+
+// Column chunks of an instance: cholinergic, fast-GABA and slow-GABA columns.
+inline int n_chunks(int n, int n_pn, bool gabab)
 {
-    return sizeof(double) * 4 * (size_t)lds_ld + sizeof(float) * (glds ? (size_t)max_g_floats : 0);
+    const int na = (n_pn + kChunkWidth - 1) / kChunkWidth;
+    const int ng = (n - n_pn + kChunkWidth - 1) / kChunkWidth;
+    return na + ng + (gabab ? ng : 0);
+}
+
+// LDS bytes one instance needs: two float64 activation vectors and n_chunks
+// float64 partial-sum rows of ld entries, plus (G in LDS) its conductance
+// floats n * ld (+ n_ln * ld with slow GABA).
+inline size_t wg_lds_bytes(bool glds, int ld, int n_chunks, int64_t g_floats)
+{
+    return sizeof(double) * (2 + (size_t)n_chunks) * (size_t)ld +
+           sizeof(float) * (glds ? (size_t)g_floats : 0);
 }
 
 struct InitArgs {

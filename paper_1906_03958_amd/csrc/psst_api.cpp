@@ -99,6 +99,7 @@ struct psst_network {
     // host copies used for gradient scatter and sizing
     std::vector<float> h_kin;
     int64_t g_floats = 0;           // n * ld (+ n_ln * ld)
+    int nch = 0;                    // column chunks of the synaptic sums
 };
 
 static void net_free(psst_network *n)
@@ -226,6 +227,7 @@ extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t 
     }
     net->grad_entries = goff;
     net->g_floats = (int64_t)n * ld + (int64_t)gtb.size();
+    net->nch = n_chunks(n, p->n_pn, net->gabab);
 
     std::vector<float> prm((size_t)NPRM * ld, 0.f);
     const float *vecs[7] = {p->C_m, p->g_Na, p->g_K, p->g_L, p->E_Na, p->E_K, p->E_L};
@@ -322,10 +324,10 @@ extern "C" psst_status psst_state_init(const psst_network *net, const float *v0,
 // the per-instance persistent kernel: variant choice and launch
 // ---------------------------------------------------------------------------
 
-static const WGVariant *find_variant(int bs, int npt, bool glds)
+static const WGVariant *find_variant(int bs, int npt)
 {
     for (const WGVariant *v = wg_variants(); v->fn; ++v)
-        if (v->bs == bs && v->npt == npt && v->glds == glds) return v;
+        if (v->bs == bs && v->npt == npt) return v;
     return nullptr;
 }
 
@@ -348,17 +350,24 @@ static psst_status set_lds_attr(const void *fn, size_t bytes)
     return PSST_OK;
 }
 
-// Default variant for instances up to max_n neurons.
+// Default variant for instances up to max_n neurons (the synaptic product
+// needs bs >= ld / 4 threads: one per row quad).
 static void default_shape(int max_n, int *bs, int *npt)
 {
     if (max_n <= 64) { *bs = 64; *npt = 1; }
-    else if (max_n <= 128) { *bs = 128; *npt = 1; }
     else if (max_n <= 256) { *bs = 256; *npt = 1; }
-    else if (max_n <= 512) { *bs = 256; *npt = 2; }
+    else if (max_n <= 512) { *bs = 512; *npt = 1; }
     else { *bs = 256; *npt = 4; }
 }
 
 static const int kMaxWGNeurons = 1024;
+
+// Networks the per-instance kernel takes: at most 1024 neurons, and the
+// activation and partial-sum buffers fit the workgroup's LDS.
+static bool fits_wg(const psst_network *q)
+{
+    return q->n <= kMaxWGNeurons && wg_lds_bytes(false, q->ld, q->nch, 0) <= max_lds_per_block();
+}
 
 static psst_status validate_common(float dt, int64_t n_steps, int64_t step0, const psst_record *rec)
 {
@@ -418,17 +427,16 @@ extern "C" psst_status psst_integrate(psst_network *net, float *state, const pss
     psst_status s = validate_common(dt, n_steps, step0, rec);
     if (s != PSST_OK) return s;
     if ((s = validate_stim(stim)) != PSST_OK) return s;
-    if (net->n > kMaxWGNeurons)
+    if (!fits_wg(net))
         return stage_integrate_single(net, state, stim, dt, n_steps, step0, rec, stream);
     if (n_steps == 0) return PSST_OK;
     int bs, npt;
     default_shape(net->n, &bs, &npt);
-    const int lds_ld = net->ld;
-    size_t lds_g = wg_lds_bytes(true, lds_ld, net->g_floats);
-    const bool glds = lds_g <= max_lds_per_block();
-    const WGVariant *v = find_variant(bs, npt, glds);
+    const size_t lds_g = wg_lds_bytes(true, net->ld, net->nch, net->g_floats);
+    const size_t lds = lds_g <= max_lds_per_block() ? lds_g
+                                                    : wg_lds_bytes(false, net->ld, net->nch, 0);
+    const WGVariant *v = find_variant(bs, npt);
     if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant for n=%d", net->n);
-    const size_t lds = wg_lds_bytes(glds, lds_ld, net->g_floats);
     if ((s = set_lds_attr(v->fn, lds)) != PSST_OK) return s;
     WGArgs a{};
     a.desc = net->d_desc;
@@ -442,7 +450,7 @@ extern "C" psst_status psst_integrate(psst_network *net, float *state, const pss
     a.step0 = step0;
     a.ckpt = nullptr;
     a.K = 1;
-    a.lds_ld = lds_ld;
+    a.lds_bytes = (int64_t)lds;
     a.flag = net->d_flag;
     void *args[] = {&a};
     HIPCHK(hipLaunchKernel(v->fn, dim3(1), dim3(bs), args, lds, (hipStream_t)stream));
@@ -475,11 +483,9 @@ extern "C" psst_status psst_network_poll(psst_network *net, void *stream)
 struct Group {
     std::vector<int32_t> order;     // instance indices, largest first
     int32_t *d_order = nullptr;
-    int max_n = 0, lds_ld = 0;
-    int64_t max_g = 0;
-    bool glds = false;
+    int max_n = 0, max_ld = 0;
     int bs = 0, npt = 0;
-    size_t lds = 0;
+    size_t lds = 0;                 // dynamic LDS of the launch
 };
 
 struct psst_batch {
@@ -529,14 +535,14 @@ static WGArgs group_args(psst_batch *b, const Group &g, float *states, const pss
     a.step0 = step0;
     a.ckpt = ckpt;
     a.K = K > 0 ? K : 1;
-    a.lds_ld = g.lds_ld;
+    a.lds_bytes = (int64_t)g.lds;
     a.flag = b->d_flag;
     return a;
 }
 
 static psst_status launch_group(const Group &g, WGArgs &a, hipStream_t s)
 {
-    const WGVariant *v = find_variant(g.bs, g.npt, g.glds);
+    const WGVariant *v = find_variant(g.bs, g.npt);
     if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant bs=%d npt=%d", g.bs, g.npt);
     psst_status st = set_lds_attr(v->fn, g.lds);
     if (st != PSST_OK) return st;
@@ -551,9 +557,9 @@ static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream
 {
     std::vector<std::pair<int, int>> cands;
     for (const WGVariant *v = wg_variants(); v->fn; ++v) {
-        if (v->glds != g.glds) continue;
         const int cap = v->bs * v->npt;
         if (cap < g.max_n || cap >= 4 * std::max(g.max_n, 64)) continue;
+        if (4 * v->bs < g.max_ld) continue;     // every row quad needs a thread
         cands.push_back({v->bs, v->npt});
     }
     if (cands.size() <= 1) return PSST_OK;
@@ -630,9 +636,9 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     BCHK(hipMalloc(&b->d_desc, sizeof(InstDesc) * n));
     BCHK(hipMemcpy(b->d_desc, desc.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
 
-    int max_n = 0;
-    for (auto *q : b->nets) max_n = std::max(max_n, q->n);
-    if (max_n > kMaxWGNeurons) {
+    bool all_wg = true;
+    for (auto *q : b->nets) all_wg &= fits_wg(q);
+    if (!all_wg) {
         if (!b->shared) {
             batch_free(b);
             return fail(PSST_ERR_UNSUPPORTED,
@@ -650,39 +656,34 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
         return PSST_OK;
     }
 
-    // Largest-first (LPT) order by cost ~ n^2, then tiers by where G lives:
-    // G in LDS when the instance's conductances fit, with the LDS request
-    // sized per tier so small instances keep several workgroups per CU.
+    // One launch, workgroups in largest-first (LPT) order of cost ~ n^2; the
+    // LDS request is the full per-workgroup LDS whenever some instance's
+    // conductances fit in it (those instances then read G from LDS, the
+    // others stream it from L2/MALL/HBM).
     std::vector<int32_t> idx(n);
     for (int32_t k = 0; k < n; ++k) idx[k] = k;
     std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
         return nets[x]->g_floats > nets[y]->g_floats;
     });
     const size_t lmax = max_lds_per_block();
-    const size_t tiers[3] = {lmax / 4, lmax / 2, lmax};
     const char *env = std::getenv("PSST_LDS_G");
     const bool allow_lds = !(env && env[0] == '0');
-    std::vector<Group> groups(4);     // tiers 0..2 in LDS, 3 = G from global memory
+    Group g;
+    size_t need = 0;
+    bool any_fit = false;
     for (int32_t k : idx) {
         const psst_network *q = nets[k];
-        int t = 3;
-        for (int c = 0; c < 3 && allow_lds; ++c)
-            if (wg_lds_bytes(true, q->ld, q->g_floats) <= tiers[c]) { t = c; break; }
-        Group &g = groups[t];
         g.order.push_back(k);
         g.max_n = std::max(g.max_n, q->n);
-        g.lds_ld = std::max(g.lds_ld, q->ld);
-        g.max_g = std::max(g.max_g, q->g_floats);
-        g.glds = t < 3;
+        g.max_ld = std::max(g.max_ld, q->ld);
+        need = std::max(need, wg_lds_bytes(false, q->ld, q->nch, 0));
+        any_fit |= wg_lds_bytes(true, q->ld, q->nch, q->g_floats) <= lmax;
     }
-    for (auto &g : groups) {
-        if (g.order.empty()) continue;
-        default_shape(g.max_n, &g.bs, &g.npt);
-        g.lds = wg_lds_bytes(g.glds, g.lds_ld, g.max_g);
-        BCHK(hipMalloc(&g.d_order, sizeof(int32_t) * g.order.size()));
-        BCHK(hipMemcpy(g.d_order, g.order.data(), sizeof(int32_t) * g.order.size(), hipMemcpyHostToDevice));
-        b->groups.push_back(g);
-    }
+    g.lds = (allow_lds && any_fit) ? lmax : need;
+    default_shape(g.max_n, &g.bs, &g.npt);
+    BCHK(hipMalloc(&g.d_order, sizeof(int32_t) * g.order.size()));
+    BCHK(hipMemcpy(g.d_order, g.order.data(), sizeof(int32_t) * g.order.size(), hipMemcpyHostToDevice));
+    b->groups.push_back(g);
     // launch-shape tuning on a scratch state
     const char *tenv = std::getenv("PSST_TUNE");
     if (!(tenv && tenv[0] == '0')) {
@@ -710,8 +711,8 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
 #undef BCHK
     char buf[256];
     for (auto &g : b->groups) {
-        snprintf(buf, sizeof buf, "[%zu inst, n<=%d, G in %s, %d thr x %d, lds %zu B] ",
-                 g.order.size(), g.max_n, g.glds ? "LDS" : "global", g.bs, g.npt, g.lds);
+        snprintf(buf, sizeof buf, "[%zu inst, n<=%d, %d thr x %d neurons, lds %zu B] ",
+                 g.order.size(), g.max_n, g.bs, g.npt, g.lds);
         b->describe += buf;
     }
     *out = b;
@@ -750,7 +751,7 @@ extern "C" psst_status psst_batch_state_init(const psst_batch *b, const float *v
 }
 
 // Build (first call) or update the graph holding one kernel node per group;
-// the nodes are independent, so tiers may run side by side.
+// (one node per launch group; a batch currently forms one group).
 static psst_status submit_graph(psst_batch *b, std::vector<WGArgs> &args, hipStream_t s)
 {
     const size_t G = b->groups.size();
@@ -760,7 +761,7 @@ static psst_status submit_graph(psst_batch *b, std::vector<WGArgs> &args, hipStr
         b->node_args = args;
         for (size_t k = 0; k < G; ++k) {
             const Group &g = b->groups[k];
-            const WGVariant *v = find_variant(g.bs, g.npt, g.glds);
+            const WGVariant *v = find_variant(g.bs, g.npt);
             if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant");
             psst_status st = set_lds_attr(v->fn, g.lds);
             if (st != PSST_OK) return st;
@@ -780,7 +781,7 @@ static psst_status submit_graph(psst_batch *b, std::vector<WGArgs> &args, hipStr
             if (std::memcmp(&b->node_args[k], &args[k], sizeof(WGArgs)) == 0) continue;
             b->node_args[k] = args[k];
             const Group &g = b->groups[k];
-            const WGVariant *v = find_variant(g.bs, g.npt, g.glds);
+            const WGVariant *v = find_variant(g.bs, g.npt);
             void *kp[] = {&b->node_args[k]};
             hipKernelNodeParams p{};
             p.func = const_cast<void *>(v->fn);
