@@ -50,7 +50,12 @@ __device__ inline Chunks chunks_of(int n, int n_pn, bool gabab)
     return c;
 }
 
-// Partial sums of one chunk for rows 4 r4 .. 4 r4 + 3.
+// Partial sums of one chunk for rows 4 r4 .. 4 r4 + 3.  Columns go in
+// batches of U: all U loads are issued before the first is consumed, so each
+// wavefront keeps U 16-byte loads in flight.  Past the chunk end the row
+// index is clamped and the activation taken as 0, which adds exact zeros and
+// leaves the column-order sum unchanged.
+template <int U>
 __device__ __forceinline__ void chunk_rows4(const float *G, int ld, const double *x, int j0,
                                             int j1, int r4, double &s0, double &s1, double &s2,
                                             double &s3)
@@ -58,14 +63,23 @@ __device__ __forceinline__ void chunk_rows4(const float *G, int ld, const double
     const float4 *G4 = reinterpret_cast<const float4 *>(G);
     const int q = ld >> 2;
     s0 = s1 = s2 = s3 = 0.0;
-#pragma unroll 8
-    for (int j = j0; j < j1; ++j) {
-        const float4 g = G4[(int64_t)j * q + r4];
-        const double xj = x[j];
-        s0 = fma((double)g.x, xj, s0);
-        s1 = fma((double)g.y, xj, s1);
-        s2 = fma((double)g.z, xj, s2);
-        s3 = fma((double)g.w, xj, s3);
+    for (int j = j0; j < j1; j += U) {
+        float4 g[U];
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int jj = min(j + u, j1 - 1);
+            g[u] = G4[(int64_t)jj * q + r4];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = (j + u < j1) ? x[j + u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s0 = fma((double)g[u].x, xv[u], s0);
+            s1 = fma((double)g[u].y, xv[u], s1);
+            s2 = fma((double)g[u].z, xv[u], s2);
+            s3 = fma((double)g[u].w, xv[u], s3);
+        }
     }
 }
 
@@ -88,7 +102,7 @@ __device__ __forceinline__ void stage_partials(const float *G, const float *GB, 
             M = GB; X = xb; j0 = (c - ch.na - ch.ng) * CW; j1 = min(j0 + CW, n - n_pn);
         }
         double s0, s1, s2, s3;
-        chunk_rows4(M, ld, X, j0, j1, r4, s0, s1, s2, s3);
+        chunk_rows4<8>(M, ld, X, j0, j1, r4, s0, s1, s2, s3);
         double *pc = part + (size_t)c * ld + 4 * r4;
         pc[0] = s0; pc[1] = s1; pc[2] = s2; pc[3] = s3;
     }
