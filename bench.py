@@ -37,6 +37,50 @@ def stratified(sizes, k):
     return [int(b) for b in order[np.linspace(0, len(sizes) - 1, k).astype(int)]]
 
 
+def _counter_rows(path, kernel_substr, counter):
+    import csv
+    out = []
+    for r in csv.DictReader(open(path)):
+        if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter:
+            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            out.append((dur, float(r["Counter_Value"])))
+    return out
+
+
+def write_traffic(args):
+    """Per-launch HBM bytes of the batched kernel from rocprofv3 counters.
+
+    FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by the
+    ratio of the known byte count of a plain device copy to what the same
+    counter reads for that copy.  Only the longest dispatches (the timed bench
+    launches, not the short tuning runs) are used."""
+    f_csv, w_csv, cf_csv, cw_csv = args.write_traffic
+    ref = args.copy_calibration * (1 << 20) if args.copy_calibration else (1 << 30)
+    cf = [v for _, v in _counter_rows(cf_csv, "copyBuffer", "FETCH_SIZE")]
+    cw = [v for _, v in _counter_rows(cw_csv, "copyBuffer", "WRITE_SIZE")]
+    kf = float(ref) / (1024.0 * float(np.median(cf)))
+    kw = float(ref) / (1024.0 * float(np.median(cw)))
+    f = _counter_rows(f_csv, "rk4_wg_kernel", "FETCH_SIZE")
+    w = _counter_rows(w_csv, "rk4_wg_kernel", "WRITE_SIZE")
+    longest = max(d for d, _ in f)
+    f = [v for d, v in f if d > 0.5 * longest]
+    longest = max(d for d, _ in w)
+    w = [v for d, v in w if d > 0.5 * longest]
+    fetch = float(np.mean(f)) * 1024 * kf
+    write = float(np.mean(w)) * 1024 * kw
+    src = os.path.join(ROOT, "paper_1906_03958_amd", "csrc", "rk4_wg.hip")
+    out = {"kernel_source_sha": hashlib.sha256(open(src, "rb").read()).hexdigest()[:16],
+           "chunk": args.chunk, "instances": args.instances,
+           "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+           "hbm_bytes_per_launch": fetch + write,
+           "fetch_scale": kf, "write_scale": kw, "launches": len(f),
+           "copy_reference_bytes": ref}
+    path = os.path.join(ROOT, "profiles", "rk4_batch_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,9 +96,18 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float32 buffer 5 times (reference kernel "
                          "for scaling HBM counters) and exit")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV",
+                                                          "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter files of a "
+                         "bench run and of a --copy-calibration run into "
+                         "profiles/rk4_batch_traffic.json and exit")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
+
+    if args.write_traffic:
+        write_traffic(args)
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "

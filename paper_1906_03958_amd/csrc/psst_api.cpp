@@ -681,12 +681,24 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     }
     g.lds = (allow_lds && any_fit) ? lmax : need;
     default_shape(g.max_n, &g.bs, &g.npt);
+    // PSST_WG_SHAPE="<threads>x<neurons per thread>" fixes the launch shape
+    // (and skips tuning) when that variant can take every instance.
+    bool fixed = false;
+    if (const char *shp = std::getenv("PSST_WG_SHAPE")) {
+        int bs = 0, npt = 0;
+        if (std::sscanf(shp, "%dx%d", &bs, &npt) == 2 && find_variant(bs, npt) &&
+            bs * npt >= g.max_n && 4 * bs >= g.max_ld) {
+            g.bs = bs;
+            g.npt = npt;
+            fixed = true;
+        }
+    }
     BCHK(hipMalloc(&g.d_order, sizeof(int32_t) * g.order.size()));
     BCHK(hipMemcpy(g.d_order, g.order.data(), sizeof(int32_t) * g.order.size(), hipMemcpyHostToDevice));
     b->groups.push_back(g);
     // launch-shape tuning on a scratch state
     const char *tenv = std::getenv("PSST_TUNE");
-    if (!(tenv && tenv[0] == '0')) {
+    if (!fixed && !(tenv && tenv[0] == '0')) {
         float *scratch = nullptr;
         float *v0 = nullptr;
         BCHK(hipMalloc(&scratch, sizeof(float) * 14 * b->nt));
