@@ -13,18 +13,18 @@
 #include <vector>
 
 #include "../../include/psst.h"
-#include "kernels.h"
+#include "runtime.h"
 #include "stage.h"
 
 using namespace psst;
+
+static thread_local std::string g_err;
 
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
 
-static thread_local std::string g_err;
-
-static psst_status fail(psst_status s, const char *fmt, ...)
+psst_status psst::fail(psst_status s, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -34,15 +34,6 @@ static psst_status fail(psst_status s, const char *fmt, ...)
     g_err = buf;
     return s;
 }
-
-#define HIPCHK(call)                                                              \
-    do {                                                                          \
-        hipError_t e_ = (call);                                                   \
-        if (e_ != hipSuccess)                                                     \
-            return fail(e_ == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY        \
-                                                  : PSST_ERR_DEVICE,              \
-                        "%s failed: %s", #call, hipGetErrorString(e_));           \
-    } while (0)
 
 extern "C" const char *psst_last_error(void) { return g_err.c_str(); }
 extern "C" const char *psst_version(void) { return "psst-mi355x 0.1 (gfx950)"; }
@@ -72,35 +63,12 @@ static psst_status check_device(int *dev_out)
 
 static bool is_finite_f(float x) { return std::isfinite(x); }
 
+static size_t max_lds_per_block();
+static bool fits_wg(const psst_network *q);
+
 // ---------------------------------------------------------------------------
 // networks
 // ---------------------------------------------------------------------------
-
-struct PathInfo {
-    int32_t type, pre0, pre1, post0, post1;
-    int64_t grad_off;   // offset of this block in a grad_g copy
-};
-
-struct psst_network {
-    int device = 0;
-    int32_t n = 0, n_pn = 0, ld = 0;
-    bool gabab = false;
-    float area = 0.f;
-    double cg = 0, ci = 0;
-    std::vector<PathInfo> paths;
-    int64_t grad_entries = 0;
-    // device
-    float *d_gt = nullptr, *d_gtb = nullptr, *d_prm = nullptr, *d_kin = nullptr;
-    uint8_t *d_maskt = nullptr;     // fast/slow mask transposed like gt (1 = synapse)
-    InstDesc desc{};
-    InstDesc *d_desc = nullptr;
-    int32_t *d_order = nullptr;
-    int32_t *d_flag = nullptr;
-    // host copies used for gradient scatter and sizing
-    std::vector<float> h_kin;
-    int64_t g_floats = 0;           // n * ld (+ n_ln * ld)
-    int nch = 0;                    // column chunks of the synaptic sums
-};
 
 static void net_free(psst_network *n)
 {
@@ -113,6 +81,8 @@ static void net_free(psst_network *n)
     hipFree(n->d_desc);
     hipFree(n->d_order);
     hipFree(n->d_flag);
+    stage_batch_free(n->single);
+    stage_net_free(n->stage);
     delete n;
 }
 
@@ -200,15 +170,24 @@ extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t 
     const int ld = net->ld, n_ln = n - p->n_pn;
     for (int q = 0; q < np; ++q) net->gabab |= paths[q].type == PSST_SYN_GABA_B;
 
-    // transposed conductance matrices, padded rows: gt[j * ld + i]
-    std::vector<float> gt((size_t)n * ld, 0.f);
-    std::vector<float> gtb(net->gabab ? (size_t)n_ln * ld : 0, 0.f);
-    std::vector<uint8_t> mt((size_t)n * ld + gtb.size(), 0);
     int64_t goff = 0;
     for (int q = 0; q < np; ++q) {
         const psst_pathway &w = paths[q];
-        PathInfo pi{w.type, w.pre_begin, w.pre_end, w.post_begin, w.post_end, goff};
-        net->paths.push_back(pi);
+        net->paths.push_back(PathInfo{w.type, w.pre_begin, w.pre_end, w.post_begin, w.post_end, goff});
+        goff += (int64_t)(w.post_end - w.post_begin) * (w.pre_end - w.pre_begin);
+    }
+    net->grad_entries = goff;
+    net->g_floats = (int64_t)n * ld + (net->gabab ? (int64_t)n_ln * ld : 0);
+    net->nch = n_chunks(n, p->n_pn, net->gabab);
+    const bool wg = fits_wg(net);
+
+    // per-instance kernel layout: transposed conductance matrices with padded
+    // rows, gt[j * ld + i] (pre j, post i), and the synapse mask alike
+    std::vector<float> gt(wg ? (size_t)n * ld : 0, 0.f);
+    std::vector<float> gtb(wg && net->gabab ? (size_t)n_ln * ld : 0, 0.f);
+    std::vector<uint8_t> mt(wg ? (size_t)n * ld + gtb.size() : 0, 0);
+    for (int q = 0; q < np && wg; ++q) {
+        const psst_pathway &w = paths[q];
         const int npre = w.pre_end - w.pre_begin;
         for (int i = w.post_begin; i < w.post_end; ++i)
             for (int j = w.pre_begin; j < w.pre_end; ++j) {
@@ -223,12 +202,7 @@ extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t 
                     mt[(size_t)j * ld + i] = present;
                 }
             }
-        goff += (int64_t)(w.post_end - w.post_begin) * npre;
     }
-    net->grad_entries = goff;
-    net->g_floats = (int64_t)n * ld + (int64_t)gtb.size();
-    net->nch = n_chunks(n, p->n_pn, net->gabab);
-
     std::vector<float> prm((size_t)NPRM * ld, 0.f);
     const float *vecs[7] = {p->C_m, p->g_Na, p->g_K, p->g_L, p->E_Na, p->E_K, p->E_L};
     for (int k = 0; k < 7; ++k)
@@ -246,14 +220,22 @@ extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t 
         }                                                                         \
     } while (0)
 
-    NETCHK(hipMalloc(&net->d_gt, sizeof(float) * gt.size()));
-    NETCHK(hipMemcpy(net->d_gt, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice));
-    if (!gtb.empty()) {
-        NETCHK(hipMalloc(&net->d_gtb, sizeof(float) * gtb.size()));
-        NETCHK(hipMemcpy(net->d_gtb, gtb.data(), sizeof(float) * gtb.size(), hipMemcpyHostToDevice));
+    if (wg) {
+        NETCHK(hipMalloc(&net->d_gt, sizeof(float) * gt.size()));
+        NETCHK(hipMemcpy(net->d_gt, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice));
+        if (!gtb.empty()) {
+            NETCHK(hipMalloc(&net->d_gtb, sizeof(float) * gtb.size()));
+            NETCHK(hipMemcpy(net->d_gtb, gtb.data(), sizeof(float) * gtb.size(), hipMemcpyHostToDevice));
+        }
+        NETCHK(hipMalloc(&net->d_maskt, mt.size()));
+        NETCHK(hipMemcpy(net->d_maskt, mt.data(), mt.size(), hipMemcpyHostToDevice));
+    } else {
+        psst_status st = stage_net_create(net, paths, np);
+        if (st != PSST_OK) {
+            net_free(net);
+            return st;
+        }
     }
-    NETCHK(hipMalloc(&net->d_maskt, mt.size()));
-    NETCHK(hipMemcpy(net->d_maskt, mt.data(), mt.size(), hipMemcpyHostToDevice));
     NETCHK(hipMalloc(&net->d_prm, sizeof(float) * prm.size()));
     NETCHK(hipMemcpy(net->d_prm, prm.data(), sizeof(float) * prm.size(), hipMemcpyHostToDevice));
     NETCHK(hipMalloc(&net->d_kin, sizeof(float) * 3 * NKIN));
@@ -479,33 +461,6 @@ extern "C" psst_status psst_network_poll(psst_network *net, void *stream)
 // ---------------------------------------------------------------------------
 // batches
 // ---------------------------------------------------------------------------
-
-struct Group {
-    std::vector<int32_t> order;     // instance indices, largest first
-    int32_t *d_order = nullptr;
-    int max_n = 0, max_ld = 0;
-    int bs = 0, npt = 0;
-    size_t lds = 0;                 // dynamic LDS of the launch
-};
-
-struct psst_batch {
-    std::vector<psst_network *> nets;
-    int32_t n = 0;
-    int64_t nt = 0;
-    std::vector<int64_t> offsets;
-    InstDesc *d_desc = nullptr;
-    std::vector<Group> groups;
-    int32_t *d_flag = nullptr;
-    bool shared = false;            // every instance is the same network
-    bool stage_path = false;        // large shared network: per-stage kernels
-    StageBatch *stage = nullptr;
-    std::string describe;
-    // graph of the persistent launches
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    std::vector<hipGraphNode_t> nodes;
-    std::vector<WGArgs> node_args;
-};
 
 static void batch_free(psst_batch *b)
 {

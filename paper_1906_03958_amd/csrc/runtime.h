@@ -1,0 +1,90 @@
+// runtime.h -- library-internal handle types and error helpers shared by the
+// host files of the runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "../../include/psst.h"
+#include "kernels.h"
+
+namespace psst {
+// Record a thread-local error message and return the status.
+psst_status fail(psst_status s, const char *fmt, ...);
+}  // namespace psst
+
+#define HIPCHK(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return psst::fail(e_ == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY  \
+                                                        : PSST_ERR_DEVICE,        \
+                              "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+struct StageNet;
+struct StageBatch;
+
+using psst::InstDesc;
+using psst::WGArgs;
+
+struct PathInfo {
+    int32_t type, pre0, pre1, post0, post1;
+    int64_t grad_off;   // offset of this block in a grad_g copy
+};
+
+struct psst_network {
+    int device = 0;
+    int32_t n = 0, n_pn = 0, ld = 0;
+    bool gabab = false;
+    float area = 0.f;
+    double cg = 0, ci = 0;
+    std::vector<PathInfo> paths;
+    int64_t grad_entries = 0;
+    // device
+    float *d_gt = nullptr, *d_gtb = nullptr, *d_prm = nullptr, *d_kin = nullptr;
+    uint8_t *d_maskt = nullptr;     // fast/slow mask transposed like gt (1 = synapse)
+    InstDesc desc{};
+    InstDesc *d_desc = nullptr;
+    int32_t *d_order = nullptr;
+    int32_t *d_flag = nullptr;
+    // host copies used for gradient scatter and sizing
+    std::vector<float> h_kin;
+    int64_t g_floats = 0;           // n * ld (+ n_ln * ld)
+    int nch = 0;                    // column chunks of the synaptic sums
+    // per-stage path (networks too large for one workgroup)
+    StageNet *stage = nullptr;
+    StageBatch *single = nullptr;   // one-trial stage batch for psst_integrate
+};
+
+
+struct Group {
+    std::vector<int32_t> order;     // instance indices, largest first
+    int32_t *d_order = nullptr;
+    int max_n = 0, max_ld = 0;
+    int bs = 0, npt = 0;
+    size_t lds = 0;                 // dynamic LDS of the launch
+};
+
+struct psst_batch {
+    std::vector<psst_network *> nets;
+    int32_t n = 0;
+    int64_t nt = 0;
+    std::vector<int64_t> offsets;
+    InstDesc *d_desc = nullptr;
+    std::vector<Group> groups;
+    int32_t *d_flag = nullptr;
+    bool shared = false;            // every instance is the same network
+    bool stage_path = false;        // large shared network: per-stage kernels
+    StageBatch *stage = nullptr;
+    std::string describe;
+    // graph of the persistent launches
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> nodes;
+    std::vector<WGArgs> node_args;
+};
+

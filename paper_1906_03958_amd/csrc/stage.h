@@ -1,12 +1,26 @@
-// stage.h -- per-stage kernels for networks too large for one workgroup:
-// every RK4 stage is one launch over the whole chip, the synaptic product a
-// float32 MFMA GEMM over the trials of a shared network.
+// stage.h -- per-stage path for networks too large for one workgroup: each
+// RK4 stage is one launch over the whole chip whose synaptic product is a
+// float32 matrix-core GEMM over the trials of a shared network
+// ("Circumventing memory constraints", item 1: synaptic coupling as a matrix
+// multiplication), with the per-neuron right-hand side and the RK4 update
+// fused into the GEMM epilogue.
 #pragma once
 
-#include "../../include/psst.h"
-#include "kernels.h"
+#include "runtime.h"
 
-struct StageBatch;
+// Device layout of a large network: conductances row-major [Mp][Kp] (post
+// row i, presynaptic column k) in nS, the presynaptic axis cut into padded
+// blocks: cholinergic PN columns [0, ka), fast-GABA LN columns [ka, ka + kg),
+// slow-GABA LN columns [ka + kg, Kp).  Padding rows and columns are zero.
+struct StageNet {
+    float *G = nullptr;
+    int n = 0, n_pn = 0, Mp = 0, Kp = 0, ka = 0, kg = 0, kb = 0;
+    bool gabab = false;
+};
+
+// Build the layout on the device from the (validated) pathways.
+psst_status stage_net_create(psst_network *net, const psst_pathway *paths, int32_t np);
+void stage_net_free(StageNet *sn);
 
 psst_status stage_integrate_single(psst_network *net, float *state, const psst_stimulus *stim,
                                    float dt, int64_t n_steps, int64_t step0,

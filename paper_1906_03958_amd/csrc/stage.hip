@@ -1,26 +1,520 @@
-// stage.hip -- per-stage launches for large shared networks (placeholder
-// until the MFMA stage kernel lands).
+// stage.hip -- one launch per RK4 stage for large shared networks.
+//
+// Stage q of step g (paper, "Brain simulations as computational graphs": RK4;
+// "Circumventing memory constraints", item 1: the synaptic update as a
+// matrix multiplication):
+//   A[i][b] = sum_k G[i][k] X_q[b][k]      float32 GEMM on the matrix cores,
+//                                          one accumulator set per synapse class
+//   f = rhs(Y_q, cg * A, I(g))             float64, fused epilogue
+//   acc += w_q f; Y_{q+1} = y + c_{q+1} dt f; X_{q+1} = x(Y_{q+1})
+// and at q = 3 the combine y <- y + dt/6 acc, spikes and records.
+//
+// GEMM tiling: a workgroup (4 wavefronts) owns 64 postsynaptic rows x NTILE
+// trials over the whole presynaptic axis, so each conductance is read from
+// HBM once per stage.  Tiles of 32 presynaptic columns are staged through LDS
+// with one tile loaded into registers while the previous one feeds
+// v_mfma_f32_16x16x4f32.  Within a 16-column group, lane l at sub-step s
+// takes column 4 (l / 16) + s, so each lane reads its four A and four B
+// values with one 16-byte LDS load; the column order of the sum is fixed, so
+// results are deterministic.
+//
+// Between launches the per-(neuron, trial) stage input Y and accumulator acc
+// live in a float64 workspace; activations X are double-buffered float32.
+#include <cstdio>
+#include <cstring>
+
 #include "stage.h"
 
-struct StageBatch {
-    int dummy;
+using namespace psst;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int KT = 32;        // presynaptic columns per LDS tile
+constexpr int MT = 64;        // postsynaptic rows per workgroup
+constexpr int LDK = KT + 4;   // LDS row stride in floats
+constexpr int NVS = NVAR;
+
+struct StageFixed {
+    const float *G;
+    int Kp, ka, kg;           // K blocks [0,ka) ACh, [ka,ka+kg) fast GABA, [ka+kg,Kp) slow GABA
+    float *X0, *X1;           // [Bp][Kp] activations (double-buffered by stage parity)
+    double *Yw, *accw;        // [NVAR][nt] stage input and RK4 accumulator
+    const float *prm;         // [NPRM][ld]
+    const float *kin;
+    int ld, n, n_pn, B, Bp;
+    int64_t nt;               // B * n
+    int gabab;
+    double cg, ci;
 };
 
-psst_status stage_integrate_single(psst_network *, float *, const psst_stimulus *, float, int64_t,
-                                   int64_t, const psst_record *, void *)
+struct StageCtl {
+    float *state;
+    StimDev stim;
+    RecDev rec;
+    double dt;
+    int64_t step0, g;
+    int32_t *flag;
+};
+
+__device__ __forceinline__ int k_fast(const StageFixed &fx, int i)
 {
-    return PSST_ERR_UNSUPPORTED;
+    return i < fx.n_pn ? i : fx.ka + (i - fx.n_pn);
 }
-psst_status stage_batch_create(psst_network *, int32_t, StageBatch **out)
+
+__device__ __forceinline__ void write_x(const StageFixed &fx, float *X, int b, int i,
+                                        const double *Y, const Kin &K)
+{
+    float *xr = X + (int64_t)b * fx.Kp;
+    xr[k_fast(fx, i)] = (float)Y[YS];
+    if (fx.gabab && i >= fx.n_pn) xr[fx.ka + fx.kg + (i - fx.n_pn)] = (float)gabab_act(Y[YG], K);
+}
+
+// Per call: publish the call's control block, then stage-0 inputs from the
+// carried state.
+__global__ __launch_bounds__(256) void stage_prologue(StageFixed fx, StageCtl c, StageCtl *dctl)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dctl = c;
+    const Kin K = load_kin(fx.kin);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < fx.nt;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(p / fx.n), i = (int)(p % fx.n);
+        double y[NVS];
+#pragma unroll
+        for (int v = 0; v < NVS; ++v) {
+            y[v] = (double)c.state[(2 * v) * fx.nt + p] + (double)c.state[(2 * v + 1) * fx.nt + p];
+            fx.Yw[v * fx.nt + p] = y[v];
+            fx.accw[v * fx.nt + p] = 0.0;
+        }
+        write_x(fx, fx.X0, b, i, y, K);
+    }
+}
+
+__global__ void stage_advance(StageCtl *dctl) { dctl->g += 1; }
+
+template <int WR, int WC, int BR, int BC>
+__global__ __launch_bounds__(256) void stage_kernel(StageFixed fx, const StageCtl *__restrict__ dctl,
+                                                    int q)
+{
+    constexpr int NTILE = WC * BC * 16;
+    static_assert(WR * BR * 16 == MT, "tile rows");
+    constexpr int TILE_F = 2 * (MT + NTILE) * LDK;
+    constexpr int ACC_F = 3 * MT * (NTILE + 1);
+    __shared__ float smem[TILE_F > ACC_F ? TILE_F : ACC_F];
+    float *sG = smem;                       // [2][MT * LDK]
+    float *sX = smem + 2 * MT * LDK;        // [2][NTILE * LDK]
+
+    const int m0 = blockIdx.x * MT, n0 = blockIdx.y * NTILE;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WC, wc = wave % WC;
+    const float *X = (q & 1) ? fx.X1 : fx.X0;
+    float *Xn = (q & 1) ? fx.X0 : fx.X1;
+
+    floatx4 acc[3][BR][BC];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int br = 0; br < BR; ++br)
+#pragma unroll
+            for (int bc = 0; bc < BC; ++bc) acc[t][br][bc] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    // tile loaders: G tile MT x KT = 512 float4 (2 per thread), X tile
+    // NTILE x KT = NTILE * 8 float4
+    const int lr = tid >> 3, lk = (tid & 7) * 4;
+    constexpr int XV = NTILE * KT / 4;       // float4 per X tile
+#pragma unroll
+    for (int blk = 0; blk < 3; ++blk) {
+        const int kbeg = blk == 0 ? 0 : (blk == 1 ? fx.ka : fx.ka + fx.kg);
+        const int kend = blk == 0 ? fx.ka : (blk == 1 ? fx.ka + fx.kg : fx.Kp);
+        const int ntile = (kend - kbeg) / KT;
+        if (ntile == 0) continue;
+        float4 rg0, rg1, rx0 = float4{0.f, 0.f, 0.f, 0.f}, rx1 = rx0;
+#define STAGE_LOAD(k0)                                                                   \
+    do {                                                                                 \
+        rg0 = *reinterpret_cast<const float4 *>(fx.G + (int64_t)(m0 + lr) * fx.Kp + (k0) + lk); \
+        rg1 = *reinterpret_cast<const float4 *>(fx.G + (int64_t)(m0 + lr + 32) * fx.Kp + (k0) + lk); \
+        if (tid < XV)                                                                    \
+            rx0 = *reinterpret_cast<const float4 *>(X + (int64_t)(n0 + (tid >> 3)) * fx.Kp + \
+                                                    (k0) + (tid & 7) * 4);               \
+        if (tid + 256 < XV)                                                              \
+            rx1 = *reinterpret_cast<const float4 *>(X + (int64_t)(n0 + ((tid + 256) >> 3)) * \
+                                                    fx.Kp + (k0) + (tid & 7) * 4);       \
+    } while (0)
+        STAGE_LOAD(kbeg);
+        __syncthreads();     // previous users of the tile buffers are done
+        for (int t = 0; t < ntile; ++t) {
+            float *g = sG + (t & 1) * MT * LDK;
+            float *x = sX + (t & 1) * NTILE * LDK;
+            *reinterpret_cast<float4 *>(g + lr * LDK + lk) = rg0;
+            *reinterpret_cast<float4 *>(g + (lr + 32) * LDK + lk) = rg1;
+            if (tid < XV) *reinterpret_cast<float4 *>(x + (tid >> 3) * LDK + (tid & 7) * 4) = rx0;
+            if (tid + 256 < XV)
+                *reinterpret_cast<float4 *>(x + ((tid + 256) >> 3) * LDK + (tid & 7) * 4) = rx1;
+            __syncthreads();
+            if (t + 1 < ntile) STAGE_LOAD(kbeg + (t + 1) * KT);
+#pragma unroll
+            for (int kk = 0; kk < KT / 16; ++kk) {
+                floatx4 a[BR], bv[BC];
+                const int kq = kk * 16 + 4 * (lane >> 4);
+#pragma unroll
+                for (int br = 0; br < BR; ++br) {
+                    const int row = (wr * BR + br) * 16 + (lane & 15);
+                    const float4 v = *reinterpret_cast<const float4 *>(g + row * LDK + kq);
+                    a[br] = floatx4{v.x, v.y, v.z, v.w};
+                }
+#pragma unroll
+                for (int bc = 0; bc < BC; ++bc) {
+                    const int col = (wc * BC + bc) * 16 + (lane & 15);
+                    const float4 v = *reinterpret_cast<const float4 *>(x + col * LDK + kq);
+                    bv[bc] = floatx4{v.x, v.y, v.z, v.w};
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int br = 0; br < BR; ++br)
+#pragma unroll
+                        for (int bc = 0; bc < BC; ++bc)
+                            acc[blk][br][bc] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                a[br][s], bv[bc][s], acc[blk][br][bc], 0, 0, 0);
+            }
+        }
+    }
+#undef STAGE_LOAD
+    __syncthreads();
+    // accumulators to LDS: lane holds rows 4 (lane / 16) + r, column lane % 16
+    float *sA = smem;                       // [3][MT][NTILE + 1]
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int br = 0; br < BR; ++br)
+#pragma unroll
+            for (int bc = 0; bc < BC; ++bc)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = (wr * BR + br) * 16 + 4 * (lane >> 4) + r;
+                    const int nn = (wc * BC + bc) * 16 + (lane & 15);
+                    sA[(t * MT + m) * (NTILE + 1) + nn] = acc[t][br][bc][r];
+                }
+    __syncthreads();
+
+    // fused epilogue: right-hand side and RK4 bookkeeping per (neuron, trial)
+    const Kin K = load_kin(fx.kin);
+    const StageCtl c = *dctl;
+    const double dt = c.dt;
+    const int64_t g = c.g;
+    const int64_t nt = fx.nt;
+    bool bad = false;
+    for (int p = tid; p < MT * NTILE; p += 256) {
+        const int il = p % MT, bl = p / MT;
+        const int i = m0 + il, b = n0 + bl;
+        if (i >= fx.n || b >= fx.B) continue;
+        const int64_t gi = (int64_t)b * fx.n + i;
+        double Y[NVS], a[NVS];
+#pragma unroll
+        for (int v = 0; v < NVS; ++v) {
+            Y[v] = fx.Yw[v * nt + gi];
+            a[v] = fx.accw[v * nt + gi];
+        }
+        Prm P = load_prm(fx.prm, fx.ld, i);
+        double I = c.stim.i_const ? (double)c.stim.i_const[gi] : 0.0;
+        if (c.stim.pulse_ptr)
+            for (int k = c.stim.pulse_ptr[gi]; k < c.stim.pulse_ptr[gi + 1]; ++k)
+                if (c.stim.on_step[k] <= g && g < c.stim.off_step[k]) I += (double)c.stim.amp[k];
+        const double sa = sA[(0 * MT + il) * (NTILE + 1) + bl];
+        const double sg = sA[(1 * MT + il) * (NTILE + 1) + bl];
+        const double sb = sA[(2 * MT + il) * (NTILE + 1) + bl];
+        double f[NVS];
+        hh_rhs(Y, P, K, fx.cg * sa, fx.cg * sg, fx.cg * sb, fx.ci * I, i >= fx.n_pn,
+               fx.gabab != 0, f);
+        const double w = (q == 0 || q == 3) ? 1.0 : 2.0;
+        double y[NVS];
+#pragma unroll
+        for (int v = 0; v < NVS; ++v) {
+            a[v] += w * f[v];
+            y[v] = (double)c.state[(2 * v) * nt + gi] + (double)c.state[(2 * v + 1) * nt + gi];
+        }
+        if (q < 3) {
+            const double cq = (q == 2) ? dt : 0.5 * dt;
+#pragma unroll
+            for (int v = 0; v < NVS; ++v) {
+                Y[v] = y[v] + cq * f[v];
+                fx.Yw[v * nt + gi] = Y[v];
+                fx.accw[v * nt + gi] = a[v];
+            }
+            write_x(fx, Xn, b, i, Y, K);
+        } else {
+            const double vold = y[YV];
+            double chk = 0.0;
+#pragma unroll
+            for (int v = 0; v < NVS; ++v) {
+                float hi, lo;
+                y[v] = split_store(y[v] + (dt / 6.0) * a[v], hi, lo);
+                c.state[(2 * v) * nt + gi] = hi;
+                c.state[(2 * v + 1) * nt + gi] = lo;
+                fx.Yw[v * nt + gi] = y[v];
+                fx.accw[v * nt + gi] = 0.0;
+                chk += y[v];
+            }
+            bad |= !finite_d(chk);
+            write_x(fx, Xn, b, i, y, K);
+            const double vnew = y[YV];
+            if (c.rec.spike_count && vold < 0.0 && vnew >= 0.0) {
+                const int32_t cnt = c.rec.spike_count[gi];
+                if (cnt < c.rec.spike_cap)
+                    c.rec.spike_t[gi * c.rec.spike_cap + cnt] =
+                        (float)(((double)g + (0.0 - vold) / (vnew - vold)) * dt);
+                c.rec.spike_count[gi] = cnt + 1;
+            }
+            if (c.rec.v_out && c.rec.stride > 0 && (g + 1) % c.rec.stride == 0) {
+                const int64_t row = (g + 1) / c.rec.stride - c.step0 / c.rec.stride - 1;
+                if (row < c.rec.capacity) c.rec.v_out[row * nt + gi] = (float)vnew;
+            }
+        }
+    }
+    if (bad) atomicOr(c.flag, 1);
+}
+
+}  // namespace
+
+struct StageBatch {
+    psst_network *net = nullptr;
+    int B = 0, Bp = 0, ntile = 0;
+    StageFixed fx{};
+    StageCtl *d_ctl = nullptr;
+    int32_t *d_flag = nullptr;
+    float *X = nullptr;
+    double *work = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int q_arg[4] = {0, 1, 2, 3};
+    std::string desc;
+};
+
+static int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+psst_status stage_net_create(psst_network *net, const psst_pathway *paths, int32_t np)
+{
+    StageNet *sn = new StageNet();
+    sn->n = net->n;
+    sn->n_pn = net->n_pn;
+    sn->gabab = net->gabab;
+    const int n_ln = net->n - net->n_pn;
+    sn->Mp = round_up(net->n, MT);
+    sn->ka = round_up(net->n_pn, KT);
+    sn->kg = round_up(n_ln, KT);
+    sn->kb = net->gabab ? round_up(n_ln, KT) : 0;
+    sn->Kp = sn->ka + sn->kg + sn->kb;
+    std::vector<float> G((size_t)sn->Mp * sn->Kp, 0.f);
+    for (int q = 0; q < np; ++q) {
+        const psst_pathway &w = paths[q];
+        const int npre = w.pre_end - w.pre_begin;
+        for (int i = w.post_begin; i < w.post_end; ++i) {
+            float *row = G.data() + (size_t)i * sn->Kp;
+            const float *src = w.g_nS + (size_t)(i - w.post_begin) * npre;
+            const uint8_t *msk = w.mask ? w.mask + (size_t)(i - w.post_begin) * npre : nullptr;
+            for (int j = w.pre_begin; j < w.pre_end; ++j) {
+                int k;
+                if (w.type == PSST_SYN_ACH) k = j;
+                else if (w.type == PSST_SYN_GABA_A) k = sn->ka + (j - net->n_pn);
+                else k = sn->ka + sn->kg + (j - net->n_pn);
+                const int e = j - w.pre_begin;
+                row[k] = (!msk || msk[e]) ? src[e] : 0.f;
+            }
+        }
+    }
+    hipError_t e = hipMalloc(&sn->G, sizeof(float) * G.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(sn->G, G.data(), sizeof(float) * G.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        stage_net_free(sn);
+        return fail(e == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY : PSST_ERR_DEVICE,
+                    "stage layout upload failed: %s", hipGetErrorString(e));
+    }
+    net->stage = sn;
+    return PSST_OK;
+}
+
+void stage_net_free(StageNet *sn)
+{
+    if (!sn) return;
+    (void)hipFree(sn->G);
+    delete sn;
+}
+
+psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch **out)
 {
     *out = nullptr;
-    return PSST_ERR_UNSUPPORTED;
+    if (!net->stage) return fail(PSST_ERR_UNSUPPORTED, "network has no per-stage layout");
+    StageNet *sn = net->stage;
+    StageBatch *sb = new StageBatch();
+    sb->net = net;
+    sb->B = n_trials;
+    sb->ntile = n_trials <= 16 ? 16 : 64;
+    sb->Bp = round_up(n_trials, sb->ntile);
+    const int64_t nt = (int64_t)n_trials * net->n;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(hipMalloc(&sb->X, sizeof(float) * 2 * (size_t)sb->Bp * sn->Kp));
+    chk(hipMemset(sb->X, 0, sizeof(float) * 2 * (size_t)sb->Bp * sn->Kp));
+    chk(hipMalloc(&sb->work, sizeof(double) * 2 * NVAR * (size_t)nt));
+    chk(hipMalloc(&sb->d_ctl, sizeof(StageCtl)));
+    chk(hipMalloc(&sb->d_flag, sizeof(int32_t)));
+    chk(hipMemset(sb->d_flag, 0, sizeof(int32_t)));
+    if (e != hipSuccess) {
+        stage_batch_free(sb);
+        return fail(e == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY : PSST_ERR_DEVICE,
+                    "stage batch allocation failed: %s", hipGetErrorString(e));
+    }
+    StageFixed &fx = sb->fx;
+    fx.G = sn->G;
+    fx.Kp = sn->Kp;
+    fx.ka = sn->ka;
+    fx.kg = sn->kg;
+    fx.X0 = sb->X;
+    fx.X1 = sb->X + (size_t)sb->Bp * sn->Kp;
+    fx.Yw = sb->work;
+    fx.accw = sb->work + (size_t)NVAR * nt;
+    fx.prm = net->d_prm;
+    fx.kin = net->d_kin;
+    fx.ld = net->ld;
+    fx.n = net->n;
+    fx.n_pn = net->n_pn;
+    fx.B = n_trials;
+    fx.Bp = sb->Bp;
+    fx.nt = nt;
+    fx.gabab = net->gabab ? 1 : 0;
+    fx.cg = net->cg;
+    fx.ci = net->ci;
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "[per-stage fp32 MFMA GEMM: %d rows x %d trials (tile 64 x %d), K %d, 4 launches per step]",
+             sn->Mp, sb->Bp, sb->ntile, sn->Kp);
+    sb->desc = buf;
+    *out = sb;
+    return PSST_OK;
 }
-void stage_batch_free(StageBatch *sb) { delete sb; }
-const char *stage_batch_describe(const StageBatch *) { return ""; }
-psst_status stage_batch_integrate(StageBatch *, float *, const psst_stimulus *, float, int64_t,
-                                  int64_t, const psst_record *, float *, int32_t, void *)
+
+void stage_batch_free(StageBatch *sb)
 {
-    return PSST_ERR_UNSUPPORTED;
+    if (!sb) return;
+    if (sb->exec) (void)hipGraphExecDestroy(sb->exec);
+    if (sb->graph) (void)hipGraphDestroy(sb->graph);
+    (void)hipFree(sb->X);
+    (void)hipFree(sb->work);
+    (void)hipFree(sb->d_ctl);
+    (void)hipFree(sb->d_flag);
+    delete sb;
 }
-psst_status stage_batch_poll(StageBatch *, void *) { return PSST_ERR_UNSUPPORTED; }
+
+const char *stage_batch_describe(const StageBatch *sb) { return sb ? sb->desc.c_str() : ""; }
+
+static const void *stage_fn(int ntile)
+{
+    return ntile == 16 ? (const void *)stage_kernel<4, 1, 1, 1>
+                       : (const void *)stage_kernel<2, 2, 2, 2>;
+}
+
+// One RK4 step as a graph: stages 0..3 then the step-counter advance.
+static psst_status build_graph(StageBatch *sb)
+{
+    HIPCHK(hipGraphCreate(&sb->graph, 0));
+    hipGraphNode_t prev = nullptr;
+    const dim3 grid(sb->net->stage->Mp / MT, sb->Bp / sb->ntile);
+    for (int q = 0; q < 4; ++q) {
+        void *kp[] = {&sb->fx, &sb->d_ctl, &sb->q_arg[q]};
+        hipKernelNodeParams p{};
+        p.func = const_cast<void *>(stage_fn(sb->ntile));
+        p.gridDim = grid;
+        p.blockDim = dim3(256);
+        p.sharedMemBytes = 0;
+        p.kernelParams = kp;
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        HIPCHK(hipGraphAddKernelNode(&node, sb->graph, prev ? &prev : nullptr, prev ? 1 : 0, &p));
+        prev = node;
+    }
+    void *kp[] = {&sb->d_ctl};
+    hipKernelNodeParams p{};
+    p.func = (void *)stage_advance;
+    p.gridDim = dim3(1);
+    p.blockDim = dim3(1);
+    p.kernelParams = kp;
+    hipGraphNode_t node;
+    HIPCHK(hipGraphAddKernelNode(&node, sb->graph, &prev, 1, &p));
+    HIPCHK(hipGraphInstantiate(&sb->exec, sb->graph, nullptr, nullptr, 0));
+    return PSST_OK;
+}
+
+psst_status stage_batch_integrate(StageBatch *sb, float *states, const psst_stimulus *stim,
+                                  float dt, int64_t n_steps, int64_t step0,
+                                  const psst_record *rec, float *ckpt, int32_t K, void *stream)
+{
+    (void)K;
+    if (ckpt) return fail(PSST_ERR_UNSUPPORTED, "checkpoints are not supported on the per-stage path");
+    if (n_steps == 0) return PSST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (!sb->exec) {
+        psst_status st = build_graph(sb);
+        if (st != PSST_OK) return st;
+    }
+    StageCtl c{};
+    c.state = states;
+    if (stim) {
+        c.stim.i_const = stim->i_const_nA;
+        c.stim.pulse_ptr = stim->pulse_ptr;
+        c.stim.on_step = stim->on_step;
+        c.stim.off_step = stim->off_step;
+        c.stim.amp = stim->amp_nA;
+    }
+    if (rec) {
+        c.rec.v_out = rec->v_out;
+        c.rec.stride = rec->stride;
+        c.rec.capacity = rec->capacity;
+        c.rec.spike_count = rec->spike_count;
+        c.rec.spike_t = rec->spike_t_ms;
+        c.rec.spike_cap = rec->spike_cap;
+    }
+    c.dt = (double)dt;
+    c.step0 = step0;
+    c.g = step0;
+    c.flag = sb->d_flag;
+    void *args[] = {&sb->fx, &c, &sb->d_ctl};
+    HIPCHK(hipLaunchKernel((const void *)stage_prologue, dim3(1024), dim3(256), args, 0, s));
+    for (int64_t k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(sb->exec, s));
+    return PSST_OK;
+}
+
+psst_status stage_batch_poll(StageBatch *sb, void *stream)
+{
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    int32_t f = 0;
+    HIPCHK(hipMemcpy(&f, sb->d_flag, sizeof f, hipMemcpyDeviceToHost));
+    if (f) {
+        int32_t z = 0;
+        HIPCHK(hipMemcpy(sb->d_flag, &z, sizeof z, hipMemcpyHostToDevice));
+        return fail(PSST_ERR_NONFINITE, "a state variable became non-finite");
+    }
+    return PSST_OK;
+}
+
+psst_status stage_integrate_single(psst_network *net, float *state, const psst_stimulus *stim,
+                                   float dt, int64_t n_steps, int64_t step0,
+                                   const psst_record *rec, void *stream)
+{
+    if (!net->single) {
+        psst_status st = stage_batch_create(net, 1, &net->single);
+        if (st != PSST_OK) return st;
+        net->single->fx.B = 1;
+        // the network's own non-finite flag is the one its poll reads
+        (void)hipFree(net->single->d_flag);
+        net->single->d_flag = nullptr;
+    }
+    StageBatch *sb = net->single;
+    const int32_t *saved = sb->d_flag;
+    sb->d_flag = net->d_flag;
+    psst_status st = stage_batch_integrate(sb, state, stim, dt, n_steps, step0, rec, nullptr, 0,
+                                           stream);
+    sb->d_flag = const_cast<int32_t *>(saved);
+    return st;
+}

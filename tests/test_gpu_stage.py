@@ -1,0 +1,130 @@
+"""GPU parity of the per-stage path (networks above 1024 neurons, shared by
+many trials; float32 matrix-core GEMM for the synaptic product) against the
+FP64 oracle, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1906_03958_amd import workloads as W
+from tests import _runs as R
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _trials(net, cfg, n_trials, first=0):
+    i_nA, v0 = W.trial_inputs(cfg, net.n, n_trials, first)
+    return [W.Instance(net, v0[t], W.Stimulus(i_nA[t])) for t in range(n_trials)]
+
+
+def _gpu_trials(net, insts, n_steps, rec_stride=1, spike_cap=0):
+    """One shared network, len(insts) trials, one psst_batch."""
+    from paper_1906_03958_amd import psst
+    h = psst.network_create(net)
+    return R.gpu_run(insts, n_steps, rec_stride=rec_stride, spike_cap=spike_cap,
+                     nets=[h] * len(insts))
+
+
+def test_stage_path_2048_neurons_8_trials():
+    net = W.all_pairs_network(40, 0, 1536, 512, g_max=0.1)
+    insts = _trials(net, 40, 8)
+    n = 300
+    _say("stage path: 2048 neurons x 8 trials,", n, "steps")
+    g = _gpu_trials(net, insts, n, rec_stride=1, spike_cap=16)
+    o = R.oracle_run(insts, n, rec_stride=1, spike_cap=16)
+    dv = np.abs(g["v"] - o["v"]).max()
+    _say("  max|dV|", dv)
+    assert dv <= 1e-3
+    np.testing.assert_array_equal(g["spike_count"], o["spike_count"])
+    y = R.state_value(g["state"])
+    assert np.abs(y[1:5] - o["state"][1:5]).max() < 1e-5
+
+
+def test_stage_path_slow_gaba_and_pulses():
+    # an AL-shaped network above the per-workgroup limit: 900 PN + 300 LN with
+    # cholinergic, fast-GABA and slow-GABA pathways and pulse stimuli
+    base = W.config2(3, t_ms=10.0)
+    rm = W.rng_for(41, 0, W.S_MASK)
+    rg = W.rng_for(41, 0, W.S_G)
+    n_pn, n_ln = 900, 300
+    n = n_pn + n_ln
+    paths = []
+    g_, m_ = W._bernoulli_block(rm, rg, (n_ln, n_pn), 0.5, 0.05)
+    paths.append(W.Pathway(W.ACH, 0, n_pn, n_pn, n, g_, m_))
+    for typ in (W.GABA_A, W.GABA_B):
+        g_, m_ = W._bernoulli_block(rm, rg, (n_pn, n_ln), 0.5, 0.05)
+        paths.append(W.Pathway(typ, n_pn, n, 0, n_pn, g_, m_))
+        g_, m_ = W._bernoulli_block(rm, rg, (n_ln, n_ln), 0.5, 0.05, (0, 0))
+        paths.append(W.Pathway(typ, n_pn, n, n_pn, n, g_, m_))
+    net = W.Network(n, n_pn, W.hh_params(n), paths)
+    del base
+    rs = W.rng_for(41, 0, W.S_PULSE)
+    amp = rs.uniform(1.0, 10.0, n).astype(np.float32)
+    on = np.zeros(n, np.int64)
+    off = np.full(n, 500, np.int64)
+    stim = W.Stimulus(np.zeros(n, np.float32), np.arange(n + 1, dtype=np.int32), on, off, amp)
+    v0 = W.rng_for(41, 0, W.S_V0).uniform(-70, -60, n).astype(np.float32)
+    insts = [W.Instance(net, v0, stim), W.Instance(net, v0[::-1].copy(), stim)]
+    steps = 800
+    _say("stage path with slow GABA: 1200 neurons x 2 trials,", steps, "steps")
+    g = _gpu_trials(net, insts, steps, rec_stride=1, spike_cap=16)
+    o = R.oracle_run(insts, steps, rec_stride=1, spike_cap=16)
+    dv = np.abs(g["v"] - o["v"]).max()
+    _say("  max|dV|", dv, "spikes", int(o["spike_count"].sum()))
+    assert dv <= 1e-3
+    assert o["spike_count"].sum() > 0
+    np.testing.assert_array_equal(g["spike_count"], o["spike_count"])
+    y = R.state_value(g["state"])
+    assert np.abs(y[5:7] - o["state"][5:7]).max() < 1e-6
+
+
+def test_stage_path_single_network_integrate_and_chunking():
+    from paper_1906_03958_amd import psst
+    net = W.all_pairs_network(42, 0, 1200, 400, g_max=0.1)
+    inst = _trials(net, 42, 1)[0]
+    n = 400
+    h = psst.network_create(net)
+    g1 = R.gpu_run([inst], n, rec_stride=1, batched=False, nets=[h])
+    g2 = R.gpu_run([inst], n, rec_stride=1, batched=False, nets=[h], chunks=[150, 250])
+    np.testing.assert_array_equal(g1["state"], g2["state"])
+    np.testing.assert_array_equal(g1["v"], g2["v"])
+    o = R.oracle_run([inst], n, rec_stride=1)
+    dv = np.abs(g1["v"] - o["v"]).max()
+    _say("single 1600-neuron network: max|dV|", dv)
+    assert dv <= 1e-3
+
+
+def test_config4_full_size_sampled_trials():
+    # the full 16384-neuron network, 64 trials on the GPU; the oracle follows
+    # two of the trials for a few steps
+    from paper_1906_03958_amd import psst
+    import torch
+    net = W.config4_network()
+    insts = _trials(net, 4, W.CONFIG4_TRIALS)
+    steps = 3
+    _say("config4: 16384 neurons x 64 trials,", steps, "steps")
+    h = psst.network_create(net)
+    g = R.gpu_run(insts, steps, rec_stride=1, nets=[h] * len(insts))
+    del h
+    torch.cuda.empty_cache()
+    pick = [0, 37]
+    o = R.oracle_run([insts[t] for t in pick], steps, rec_stride=1, threads=2)
+    n = net.n
+    for k, t in enumerate(pick):
+        gv = g["v"][:, t * n:(t + 1) * n]
+        ov = o["v"][:, k * n:(k + 1) * n]
+        dv = np.abs(gv - ov).max()
+        _say(f"  trial {t}: max|dV| over {steps} steps = {dv:.3e}")
+        assert dv <= 1e-3
