@@ -81,6 +81,74 @@ def write_traffic(args):
     print(json.dumps(out))
 
 
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def bench_large(args, torch, psst, W, dev, stream):
+    """16384 neurons (12288 PN, 4096 LN), dense Bernoulli(0.5) g ~ U(0,0.1) nS,
+    64 stimulus trials; one bench step = --chunk RK4 steps (4 GEMM launches
+    each, one graph per step)."""
+    t0 = time.time()
+    net = W.config4_network()
+    B = W.CONFIG4_TRIALS
+    i_nA, v0 = W.trial_inputs(4, net.n, B)
+    h = psst.network_create(net)
+    batch = psst.batch_create([h] * B)
+    log(f"large network ready in {time.time() - t0:.1f}s: {psst.batch_describe(batch)}")
+    nt = net.n * B
+    states = torch.zeros(14 * nt, dtype=torch.float32, device=dev)
+    psst.batch_state_init(batch, torch.from_numpy(v0.ravel()).to(dev), states)
+    stim = psst.DeviceStimulus(torch.from_numpy(i_nA.ravel()).to(dev))
+    cnt = torch.zeros(nt, dtype=torch.int32, device=dev)
+    spk = torch.zeros((nt, SPIKE_CAP), dtype=torch.float32, device=dev)
+    rows = args.chunk // REC_STRIDE
+    vtrace = torch.zeros((max(rows, 1), nt), dtype=torch.float32, device=dev)
+    step0 = 0
+
+    def bench_step():
+        nonlocal step0
+        rec = psst.DeviceRecord(vtrace if rows else None, REC_STRIDE, rows, cnt, spk, SPIKE_CAP)
+        psst.integrate_batch(batch, states, stim, DT, args.chunk, step0, rec)
+        step0 += args.chunk
+
+    for _ in range(args.warmup):
+        bench_step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t_start = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        bench_step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    psst.batch_poll(batch)
+    rk4_steps = args.chunk * args.steps
+    value = nt * rk4_steps / wall
+    stage_s = ev0.elapsed_time(ev1) / 1e3 / (4 * rk4_steps)
+    flops_stage = 2.0 * net.n * net.n * B
+    achieved = flops_stage / stage_s / 1e12
+    out = {"metric": METRIC, "value": value, "unit": "neuron-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 (GEMM) / f64 (RHS)",
+           "data": "synthetic",
+           "config": {"workload": "large dense network: 16384 HH neurons (12288 PN, 4096 LN), "
+                                  "Bernoulli(0.5) g ~ U(0,0.1) nS, 64 stimulus trials, "
+                                  "dt 0.01 ms", "rk4_steps_per_step": args.chunk,
+                      "launch": psst.batch_describe(batch)},
+           "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
+                        "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4), "traffic": None,
+                        "kernel": "stage_kernel<2,2,2,2> (fp32 MFMA GEMM + fused RK4 stage)",
+                        "avg_launch_ms": round(1e3 * stage_s, 4),
+                        "algorithmic_flops_per_launch": flops_stage,
+                        "note": "launch time = graph time per RK4 step / 4 (the step's 4 "
+                                "stage launches plus a one-thread counter kernel)"}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +169,9 @@ def main():
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter files of a "
                          "bench run and of a --copy-calibration run into "
                          "profiles/rk4_batch_traffic.json and exit")
+    ap.add_argument("--workload", choices=("batched", "large"), default="batched",
+                    help="batched: the 4096-network batch (the default line); large: the "
+                         "16384-neuron network x 64 trials on the per-stage MFMA path")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
@@ -131,6 +202,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "launches": 5}))
+        return
+
+    if args.workload == "large":
+        bench_large(args, torch, psst, W, dev, stream)
         return
 
     # ---------------- workload: batched config -----------------------------

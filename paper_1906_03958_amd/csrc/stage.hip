@@ -11,9 +11,9 @@
 //
 // GEMM tiling: a workgroup (4 wavefronts) owns 64 postsynaptic rows x NTILE
 // trials over the whole presynaptic axis, so each conductance is read from
-// HBM once per stage.  Tiles of 32 presynaptic columns are staged through LDS
-// with one tile loaded into registers while the previous one feeds
-// v_mfma_f32_16x16x4f32.  Within a 16-column group, lane l at sub-step s
+// HBM once per stage.  Tiles of 128 presynaptic columns are staged through
+// LDS (double-buffered) with the next tile loaded into registers -- 64 KiB in
+// flight per workgroup -- while the current one feeds v_mfma_f32_16x16x4f32.  Within a 16-column group, lane l at sub-step s
 // takes column 4 (l / 16) + s, so each lane reads its four A and four B
 // values with one 16-byte LDS load; the column order of the sum is fixed, so
 // results are deterministic.
@@ -27,11 +27,11 @@
 
 using namespace psst;
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
 namespace {
 
-constexpr int KT = 32;        // presynaptic columns per LDS tile
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int KT = 128;       // presynaptic columns per LDS tile
 constexpr int MT = 64;        // postsynaptic rows per workgroup
 constexpr int LDK = KT + 4;   // LDS row stride in floats
 constexpr int NVS = NVAR;
@@ -93,15 +93,31 @@ __global__ __launch_bounds__(256) void stage_prologue(StageFixed fx, StageCtl c,
 
 __global__ void stage_advance(StageCtl *dctl) { dctl->g += 1; }
 
+// Global -> register part of the tile pipeline.
+template <int GV, int XVT, int RPP>
+__device__ __forceinline__ void tile_load(floatx4 (&rg)[GV], floatx4 (&rx)[XVT], const float *G,
+                                          const float *X, int Kp, int m0, int n0, int lr, int lk,
+                                          int k0)
+{
+#pragma unroll
+    for (int u = 0; u < GV; ++u)
+        rg[u] = *reinterpret_cast<const floatx4 *>(G + (int64_t)(m0 + lr + RPP * u) * Kp + k0 + lk);
+#pragma unroll
+    for (int u = 0; u < XVT; ++u)
+        rx[u] = *reinterpret_cast<const floatx4 *>(X + (int64_t)(n0 + lr + RPP * u) * Kp + k0 + lk);
+}
+
+// One workgroup per CU (its LDS tiles take most of the CU's LDS), so each
+// wavefront may use the whole register file of its SIMD.
 template <int WR, int WC, int BR, int BC>
-__global__ __launch_bounds__(256) void stage_kernel(StageFixed fx, const StageCtl *__restrict__ dctl,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void stage_kernel(StageFixed fx, const StageCtl *__restrict__ dctl,
                                                     int q)
 {
     constexpr int NTILE = WC * BC * 16;
     static_assert(WR * BR * 16 == MT, "tile rows");
     constexpr int TILE_F = 2 * (MT + NTILE) * LDK;
     constexpr int ACC_F = 3 * MT * (NTILE + 1);
-    __shared__ float smem[TILE_F > ACC_F ? TILE_F : ACC_F];
+    extern __shared__ float smem[];                 // max(TILE_F, ACC_F) floats
     float *sG = smem;                       // [2][MT * LDK]
     float *sX = smem + 2 * MT * LDK;        // [2][NTILE * LDK]
 
@@ -119,40 +135,35 @@ __global__ __launch_bounds__(256) void stage_kernel(StageFixed fx, const StageCt
 #pragma unroll
             for (int bc = 0; bc < BC; ++bc) acc[t][br][bc] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    // tile loaders: G tile MT x KT = 512 float4 (2 per thread), X tile
-    // NTILE x KT = NTILE * 8 float4
-    const int lr = tid >> 3, lk = (tid & 7) * 4;
-    constexpr int XV = NTILE * KT / 4;       // float4 per X tile
+    // tile loaders: a G tile is MT x KT floats = 8 float4 per thread, an X
+    // tile NTILE x KT floats = NTILE / 8 float4 per thread; the next tile is
+    // loaded into registers while the current one feeds the matrix cores
+    constexpr int K4 = KT / 4;                 // float4 per tile row
+    constexpr int RPP = 256 / K4;              // rows per pass of the workgroup
+    constexpr int GV = MT / RPP;               // G float4 per thread
+    constexpr int XVT = NTILE / RPP;           // X float4 per thread
+    const int lr = tid / K4, lk = (tid % K4) * 4;
 #pragma unroll
     for (int blk = 0; blk < 3; ++blk) {
         const int kbeg = blk == 0 ? 0 : (blk == 1 ? fx.ka : fx.ka + fx.kg);
         const int kend = blk == 0 ? fx.ka : (blk == 1 ? fx.ka + fx.kg : fx.Kp);
         const int ntile = (kend - kbeg) / KT;
         if (ntile == 0) continue;
-        float4 rg0, rg1, rx0 = float4{0.f, 0.f, 0.f, 0.f}, rx1 = rx0;
-#define STAGE_LOAD(k0)                                                                   \
-    do {                                                                                 \
-        rg0 = *reinterpret_cast<const float4 *>(fx.G + (int64_t)(m0 + lr) * fx.Kp + (k0) + lk); \
-        rg1 = *reinterpret_cast<const float4 *>(fx.G + (int64_t)(m0 + lr + 32) * fx.Kp + (k0) + lk); \
-        if (tid < XV)                                                                    \
-            rx0 = *reinterpret_cast<const float4 *>(X + (int64_t)(n0 + (tid >> 3)) * fx.Kp + \
-                                                    (k0) + (tid & 7) * 4);               \
-        if (tid + 256 < XV)                                                              \
-            rx1 = *reinterpret_cast<const float4 *>(X + (int64_t)(n0 + ((tid + 256) >> 3)) * \
-                                                    fx.Kp + (k0) + (tid & 7) * 4);       \
-    } while (0)
-        STAGE_LOAD(kbeg);
+        floatx4 rg[GV], rx[XVT];
+        tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, kbeg);
         __syncthreads();     // previous users of the tile buffers are done
         for (int t = 0; t < ntile; ++t) {
             float *g = sG + (t & 1) * MT * LDK;
             float *x = sX + (t & 1) * NTILE * LDK;
-            *reinterpret_cast<float4 *>(g + lr * LDK + lk) = rg0;
-            *reinterpret_cast<float4 *>(g + (lr + 32) * LDK + lk) = rg1;
-            if (tid < XV) *reinterpret_cast<float4 *>(x + (tid >> 3) * LDK + (tid & 7) * 4) = rx0;
-            if (tid + 256 < XV)
-                *reinterpret_cast<float4 *>(x + ((tid + 256) >> 3) * LDK + (tid & 7) * 4) = rx1;
+#pragma unroll
+            for (int u = 0; u < GV; ++u)
+                *reinterpret_cast<floatx4 *>(g + (lr + RPP * u) * LDK + lk) = rg[u];
+#pragma unroll
+            for (int u = 0; u < XVT; ++u)
+                *reinterpret_cast<floatx4 *>(x + (lr + RPP * u) * LDK + lk) = rx[u];
             __syncthreads();
-            if (t + 1 < ntile) STAGE_LOAD(kbeg + (t + 1) * KT);
+            if (t + 1 < ntile)
+                tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, kbeg + (t + 1) * KT);
 #pragma unroll
             for (int kk = 0; kk < KT / 16; ++kk) {
                 floatx4 a[BR], bv[BC];
@@ -160,14 +171,12 @@ __global__ __launch_bounds__(256) void stage_kernel(StageFixed fx, const StageCt
 #pragma unroll
                 for (int br = 0; br < BR; ++br) {
                     const int row = (wr * BR + br) * 16 + (lane & 15);
-                    const float4 v = *reinterpret_cast<const float4 *>(g + row * LDK + kq);
-                    a[br] = floatx4{v.x, v.y, v.z, v.w};
+                    a[br] = *reinterpret_cast<const floatx4 *>(g + row * LDK + kq);
                 }
 #pragma unroll
                 for (int bc = 0; bc < BC; ++bc) {
                     const int col = (wc * BC + bc) * 16 + (lane & 15);
-                    const float4 v = *reinterpret_cast<const float4 *>(x + col * LDK + kq);
-                    bv[bc] = floatx4{v.x, v.y, v.z, v.w};
+                    bv[bc] = *reinterpret_cast<const floatx4 *>(x + col * LDK + kq);
                 }
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
@@ -180,7 +189,6 @@ __global__ __launch_bounds__(256) void stage_kernel(StageFixed fx, const StageCt
             }
         }
     }
-#undef STAGE_LOAD
     __syncthreads();
     // accumulators to LDS: lane holds rows 4 (lane / 16) + r, column lane % 16
     float *sA = smem;                       // [3][MT][NTILE + 1]
@@ -415,9 +423,19 @@ static const void *stage_fn(int ntile)
                        : (const void *)stage_kernel<2, 2, 2, 2>;
 }
 
+static size_t stage_lds_bytes(int ntile)
+{
+    const size_t tile = 2 * (size_t)(MT + ntile) * LDK;
+    const size_t accf = 3 * (size_t)MT * (ntile + 1);
+    return sizeof(float) * (tile > accf ? tile : accf);
+}
+
 // One RK4 step as a graph: stages 0..3 then the step-counter advance.
 static psst_status build_graph(StageBatch *sb)
 {
+    const size_t lds = stage_lds_bytes(sb->ntile);
+    HIPCHK(hipFuncSetAttribute(stage_fn(sb->ntile), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
     HIPCHK(hipGraphCreate(&sb->graph, 0));
     hipGraphNode_t prev = nullptr;
     const dim3 grid(sb->net->stage->Mp / MT, sb->Bp / sb->ntile);
@@ -427,7 +445,7 @@ static psst_status build_graph(StageBatch *sb)
         p.func = const_cast<void *>(stage_fn(sb->ntile));
         p.gridDim = grid;
         p.blockDim = dim3(256);
-        p.sharedMemBytes = 0;
+        p.sharedMemBytes = (unsigned)lds;
         p.kernelParams = kp;
         p.extra = nullptr;
         hipGraphNode_t node;
