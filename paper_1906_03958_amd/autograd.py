@@ -1,0 +1,93 @@
+"""torch.autograd.Function over the C ABI: a batch of stimulus trials of one
+network, its recorded membrane-potential traces as a differentiable function
+of the synaptic conductances (per pathway block, nS) and the intrinsic
+conductances g_Na, g_K, g_L (mS/cm^2).
+
+forward  -> psst_integrate_batch with checkpoints every K steps, V every step
+backward -> psst_adjoint (discrete adjoint of the RK4 map, summed over trials)
+
+All arithmetic happens in the HIP library; this module only marshals tensors.
+"""
+from __future__ import annotations
+
+import copy
+from typing import List
+
+import numpy as np
+import torch
+
+from . import psst
+
+
+class TraceSimulation:
+    """Trials of one network.  net: a workload Network (its g values are
+    replaced by the tensors passed to __call__); i_nA, v0: [B, n] arrays."""
+
+    def __init__(self, net, i_nA, v0, dt: float, n_steps: int, K: int = 100,
+                 device: str = "cuda:0"):
+        self.template = net
+        self.dev = torch.device(device)
+        self.B = int(i_nA.shape[0])
+        self.n = int(net.n)
+        self.dt = float(dt)
+        self.n_steps = int(n_steps)
+        self.K = int(K)
+        self.shapes = [tuple(p.g_nS.shape) for p in net.pathways]
+        self.stim = psst.DeviceStimulus(
+            torch.from_numpy(np.ascontiguousarray(i_nA, np.float32).ravel()).to(self.dev))
+        self.v0 = torch.from_numpy(np.ascontiguousarray(v0, np.float32).ravel()).to(self.dev)
+
+    def pack(self, blocks: List) -> torch.Tensor:
+        return torch.cat([torch.as_tensor(b, dtype=torch.float32).reshape(-1) for b in blocks])
+
+    def build(self, g_flat: torch.Tensor, g_na, g_k, g_l):
+        net = copy.copy(self.template)
+        flat = g_flat.detach().to("cpu", torch.float32).numpy()
+        paths, off = [], 0
+        for p, (a, b) in zip(self.template.pathways, self.shapes):
+            q = copy.copy(p)
+            q.g_nS = flat[off:off + a * b].reshape(a, b).copy()
+            off += a * b
+            paths.append(q)
+        net.pathways = paths
+        net.params = dict(self.template.params)
+        for k, t in (("g_Na", g_na), ("g_K", g_k), ("g_L", g_l)):
+            net.params[k] = t.detach().to("cpu", torch.float32).numpy().copy()
+        return net
+
+    def __call__(self, g_flat, g_na, g_k, g_l) -> torch.Tensor:
+        return PsstTraceFn.apply(self, g_flat, g_na, g_k, g_l)
+
+
+class PsstTraceFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sim: TraceSimulation, g_flat, g_na, g_k, g_l):
+        net = psst.network_create(sim.build(g_flat, g_na, g_k, g_l))
+        batch = psst.batch_create([net] * sim.B)
+        nt = batch.n_total
+        states = torch.zeros(14 * nt, dtype=torch.float32, device=sim.dev)
+        psst.batch_state_init(batch, sim.v0, states)
+        v = torch.empty((sim.n_steps, nt), dtype=torch.float32, device=sim.dev)
+        n_ck = (sim.n_steps + sim.K - 1) // sim.K
+        ckpt = torch.empty((max(n_ck, 1), 14 * nt), dtype=torch.float32, device=sim.dev)
+        psst.integrate_batch(batch, states, sim.stim, sim.dt, sim.n_steps, 0,
+                             psst.DeviceRecord(v, 1, sim.n_steps), ckpt, sim.K)
+        psst.batch_poll(batch)
+        ctx.sim = sim
+        ctx.net, ctx.batch, ctx.ckpt = net, batch, ckpt
+        ctx.devs = (g_flat.device, g_na.device, g_k.device, g_l.device)
+        return v
+
+    @staticmethod
+    def backward(ctx, dLdV):
+        sim, batch = ctx.sim, ctx.batch
+        dLdV = dLdV.to(torch.float32).contiguous()
+        gg = torch.empty(ctx.net.grad_size, dtype=torch.float32, device=sim.dev)
+        gna = torch.empty(sim.n, dtype=torch.float32, device=sim.dev)
+        gk = torch.empty_like(gna)
+        gl = torch.empty_like(gna)
+        psst.adjoint(batch, ctx.ckpt, sim.K, sim.stim, sim.dt, sim.n_steps, 0, dLdV, gg, gna,
+                     gk, gl, per_instance=False)
+        psst.batch_poll(batch)
+        d = ctx.devs
+        return None, gg.to(d[0]), gna.to(d[1]), gk.to(d[2]), gl.to(d[3])

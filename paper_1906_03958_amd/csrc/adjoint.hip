@@ -1,0 +1,466 @@
+// adjoint.hip -- discrete adjoint of the RK4 map for batches of
+// per-instance networks: gradients of a loss of the recorded potentials with
+// respect to the synaptic conductances g_ij and the intrinsic g_Na, g_K, g_L.
+//
+// The paper integrates with RK4 ("Brain simulations as computational graphs")
+// but says nothing about gradients; this differentiates the discrete step
+// y_{n+1} = y_n + dt/6 (k1 + 2 k2 + 2 k3 + k4) exactly (discretise, then
+// differentiate), so the result matches finite differences of the forward
+// map.  With lam = dL/dy_{n+1}:
+//   kbar_q = dt b_q lam + dt c_{q+1} u_{q+1},  u_q = J(Y_q)^T kbar_q  (q = 3..0)
+//   dL/dy_n = lam + u_0 + u_1 + u_2 + u_3 (+ dL/dV_n injected from the loss)
+//   dL/dtheta += sum_q (df/dtheta)(Y_q)^T kbar_q.
+//
+// One workgroup per instance.  The forward trajectory is rebuilt segment by
+// segment from checkpoints taken every K steps: the segment's K states are
+// recomputed with the forward kernel's own routines (bitwise the forward
+// trajectory) and kept in a float64 workspace; each reverse step recomputes
+// its four stage inputs, then walks the stages backwards.  J^T has an
+// elementwise part per neuron and a presynaptic part sum_i g_ij q(i) -- a
+// transposed product, one wavefront per presynaptic row with a fixed-order
+// shuffle reduction.  dL/dg_ij = sum over steps and stages of q(i) x_j is a
+// contraction over the segment's 4K stage records, formed once per segment in
+// float64 and folded into a float32 (value, compensation) pair per entry;
+// per-neuron gradients likewise.
+#include "runtime.h"
+#include "wg_common.h"
+
+using namespace psst;
+
+namespace {
+
+struct AdjArgs {
+    const InstDesc *desc;
+    const float *ckpt;          // [ceil(n_steps / K)][14][nt]
+    int32_t K;
+    int64_t nt;
+    StimDev stim;
+    double dt;
+    int64_t n_steps, step0;
+    const float *dLdV;          // [n_steps][nt]
+    double *ws;                 // per-instance workspace, ws_stride doubles each
+    int64_t ws_stride;
+    float *gacc;                // per-instance compensated pairs, gacc_stride floats each
+    int64_t gacc_stride;
+    int32_t ld_max;
+    int64_t lds_bytes;
+    int32_t *flag;
+};
+
+// workspace layout of one instance (doubles), ld = padded neuron count
+struct WsLayout {
+    double *ys;   // [K][NVAR][ld] segment states
+    double *sY;   // [4][NVAR][ld] stage inputs of the current step
+    double *sS;   // [4][3][ld]    stage synaptic sums (nS)
+    double *Qs;   // [4K][3][ld]   q of each (step, stage)
+    double *Xs;   // [4K][2][ld]   activations x_s (all rows), x_B (LN rows)
+};
+
+__host__ __device__ inline int64_t ws_doubles(int ld, int K)
+{
+    return (int64_t)ld * ((int64_t)NVAR * K + 4 * NVAR + 12 + 12LL * K + 8LL * K);
+}
+
+__device__ inline WsLayout ws_layout(double *base, int ld, int K)
+{
+    WsLayout w;
+    w.ys = base;
+    w.sY = w.ys + (int64_t)NVAR * K * ld;
+    w.sS = w.sY + 4LL * NVAR * ld;
+    w.Qs = w.sS + 12LL * ld;
+    w.Xs = w.Qs + 12LL * K * ld;
+    return w;
+}
+
+// gradient accumulators of one instance: three sections of float32 pairs
+// (value plane then compensation plane): fast [n][ld], slow [n_ln][ld],
+// per-neuron [3][ld]
+__host__ __device__ inline int64_t gacc_floats(int n, int n_ln, int ld)
+{
+    return 2LL * ((int64_t)n * ld + (int64_t)n_ln * ld + 3LL * ld);
+}
+
+__device__ inline void comp_add(float *hi, float *lo, double v)
+{
+    const double s = (double)*hi + (double)*lo + v;
+    float h, l;
+    split_store(s, h, l);
+    *hi = h;
+    *lo = l;
+}
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
+{
+    constexpr int NPT = 1;
+    extern __shared__ double lds_d[];
+    const int b = blockIdx.x;
+    const InstDesc d = a.desc[b];
+    const int n = d.n, n_pn = d.n_pn, ld = d.ld, n_ln = d.n - d.n_pn;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = BS / 64;
+    // LDS: q vectors [3][ld], transposed products [2][ld], then the forward view
+    double *qb = lds_d;
+    double *tb = lds_d + 3 * ld;
+    const WGSyn w = wg_setup<BS>(d, lds_d + 5 * ld, a.lds_bytes - (int64_t)sizeof(double) * 5 * ld);
+    const bool gabab = w.gabab;
+    const Kin K = load_kin(d.kin);
+    const double dt = a.dt;
+    const int64_t NT = a.nt;
+    const int KK = a.K;
+    const WsLayout W = ws_layout(a.ws + (int64_t)b * a.ws_stride, ld, KK);
+    float *gacc = a.gacc + (int64_t)b * a.gacc_stride;
+    const int64_t sec_f = (int64_t)n * ld, sec_b = (int64_t)n_ln * ld, sec_p = 3LL * ld;
+    const int64_t half = sec_f + sec_b + sec_p;     // value plane size
+    for (int64_t e = tid; e < 2 * half; e += BS) gacc[e] = 0.f;
+    StageStash stash;
+    stash.sY = W.sY;
+    stash.sS = W.sS;
+    stash.ld = ld;
+
+    const int i = tid;                               // the thread's neuron (NPT = 1)
+    const bool own = i < n;
+    const int ic = own ? i : 0;
+    const int64_t gi = d.off + ic;
+    const bool is_ln = ic >= n_pn;
+    float pr[NPT][NPRM];
+#pragma unroll
+    for (int p = 0; p < NPRM; ++p) pr[0][p] = d.prm[p * ld + ic];
+    const Prm P = prm_of(pr[0]);
+    const double Ic = a.stim.i_const ? (double)a.stim.i_const[gi] : 0.0;
+    const int32_t p0 = a.stim.pulse_ptr ? a.stim.pulse_ptr[gi] : 0;
+    const int32_t p1 = a.stim.pulse_ptr ? a.stim.pulse_ptr[gi + 1] : 0;
+
+    double lam[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) lam[v] = 0.0;
+    double pg[3] = {0.0, 0.0, 0.0};
+    const double bq[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const double cq[4] = {0.0, 0.5, 0.5, 1.0};
+
+    const int64_t nseg = (a.n_steps + KK - 1) / KK;
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t s0 = seg * KK;
+        const int L = (int)((a.n_steps - s0) < KK ? (a.n_steps - s0) : KK);
+        // ---- forward recompute of the segment from its checkpoint
+        double y[NPT][NVAR];
+        const float *cp = a.ckpt + seg * (14 * NT);
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v)
+            y[0][v] = (double)cp[(2 * v) * NT + gi] + (double)cp[(2 * v + 1) * NT + gi];
+        for (int s = 0; s < L; ++s) {
+            if (own)
+#pragma unroll
+                for (int v = 0; v < NVAR; ++v) W.ys[((int64_t)s * NVAR + v) * ld + i] = y[0][v];
+            double Iu[NPT] = {d.ci * stim_nA(a.stim, Ic, p0, p1, a.step0 + s0 + s)};
+            rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr);
+        }
+        // ---- reverse steps
+        for (int s = L - 1; s >= 0; --s) {
+            const int64_t ls = s0 + s;                 // local step index
+            if (own) lam[YV] += (double)a.dLdV[ls * NT + gi];
+#pragma unroll
+            for (int v = 0; v < NVAR; ++v) y[0][v] = own ? W.ys[((int64_t)s * NVAR + v) * ld + i] : 0.0;
+            double Iu[NPT] = {d.ci * stim_nA(a.stim, Ic, p0, p1, a.step0 + ls)};
+            double ytmp[NPT][NVAR];
+#pragma unroll
+            for (int v = 0; v < NVAR; ++v) ytmp[0][v] = y[0][v];
+            rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, ytmp, &stash);
+            double un[NVAR], usum[NVAR];
+#pragma unroll
+            for (int v = 0; v < NVAR; ++v) {
+                un[v] = 0.0;
+                usum[v] = 0.0;
+            }
+            for (int q = 3; q >= 0; --q) {
+                double Yq[NVAR], kb[NVAR], u[NVAR], qq[3], dg[3];
+#pragma unroll
+                for (int v = 0; v < NVAR; ++v) {
+                    Yq[v] = own ? W.sY[(q * NVAR + v) * ld + i] : 0.0;
+                    kb[v] = dt * bq[q] * lam[v] + (q < 3 ? dt * cq[q + 1] * un[v] : 0.0);
+                }
+                if (!own) Yq[YM] = Yq[YH] = Yq[YN] = 0.5;   // keep idle lanes finite
+                const double sa = own ? W.sS[(q * 3 + 0) * ld + i] : 0.0;
+                const double sg = own ? W.sS[(q * 3 + 1) * ld + i] : 0.0;
+                const double sbv = own ? W.sS[(q * 3 + 2) * ld + i] : 0.0;
+                hh_vjp(Yq, P, K, d.cg, d.cg * sa, d.cg * sg, d.cg * sbv, kb, is_ln, gabab, u, qq,
+                       dg);
+                const int64_t rec = ls - s0;           // stage record within the segment
+                if (own) {
+                    pg[0] += dg[0];
+                    pg[1] += dg[1];
+                    pg[2] += dg[2];
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) {
+                        qb[t * ld + i] = qq[t];
+                        W.Qs[((rec * 4 + q) * 3 + t) * ld + i] = qq[t];
+                    }
+                    W.Xs[((rec * 4 + q) * 2 + 0) * ld + i] = Yq[YS];
+                    if (gabab && is_ln)
+                        W.Xs[((rec * 4 + q) * 2 + 1) * ld + (i - n_pn)] = gabab_act(Yq[YG], K);
+                }
+                __syncthreads();
+                // presynaptic terms: t_j = sum_i g_ij q_type(j)(i), one wavefront per row
+                const int rows = n + (gabab ? n_ln : 0);
+                for (int j = wave; j < rows; j += NW) {
+                    const bool slow = j >= n;
+                    const int jr = slow ? j - n : j;
+                    const double *qv = qb + (slow ? 2 : (j < n_pn ? 0 : 1)) * ld;
+                    double acc = 0.0;
+                    if (w.glds) {
+                        const float *row = w.gl + (slow ? (int64_t)n * ld : 0) + (int64_t)jr * ld;
+                        for (int ii = lane; ii < n; ii += 64) acc = fma((double)row[ii], qv[ii], acc);
+                    } else {
+                        const float *row = (slow ? d.gtb : d.gt) + (int64_t)jr * ld;
+                        for (int ii = lane; ii < n; ii += 64) acc = fma((double)row[ii], qv[ii], acc);
+                    }
+                    acc = wave_sum(acc);
+                    if (lane == 0) tb[(slow ? ld : 0) + jr] = acc;
+                }
+                __syncthreads();
+                if (own) {
+                    u[YS] += tb[i];
+                    if (gabab && is_ln) u[YG] += tb[ld + (i - n_pn)] * gabab_act_d(Yq[YG], K);
+                }
+#pragma unroll
+                for (int v = 0; v < NVAR; ++v) {
+                    un[v] = u[v];
+                    usum[v] += u[v];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < NVAR; ++v) lam[v] += usum[v];
+        }
+        __syncthreads();
+        // ---- dL/dg over the segment: sum over its 4L stage records of q(i) x_j
+        {
+            const int rows = n + (gabab ? n_ln : 0);
+            const int q4 = ld >> 2;
+            const int T = 4 * L;
+            for (int64_t p = tid; p < (int64_t)rows * q4; p += BS) {
+                const int r = (int)(p / q4), i4 = (int)(p % q4);
+                const bool slow = r >= n;
+                const int j = slow ? r - n : r;
+                const int t = slow ? 2 : (j < n_pn ? 0 : 1);
+                const int xs = slow ? 1 : 0;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                for (int tt = 0; tt < T; ++tt) {
+                    const double xv = W.Xs[((int64_t)tt * 2 + xs) * ld + j];
+                    const double *qr = W.Qs + ((int64_t)tt * 3 + t) * ld + 4 * i4;
+                    a0 = fma(qr[0], xv, a0);
+                    a1 = fma(qr[1], xv, a1);
+                    a2 = fma(qr[2], xv, a2);
+                    a3 = fma(qr[3], xv, a3);
+                }
+                const int64_t e = (slow ? sec_f : 0) + (int64_t)j * ld + 4 * i4;
+                comp_add(gacc + e + 0, gacc + half + e + 0, a0);
+                comp_add(gacc + e + 1, gacc + half + e + 1, a1);
+                comp_add(gacc + e + 2, gacc + half + e + 2, a2);
+                comp_add(gacc + e + 3, gacc + half + e + 3, a3);
+            }
+            if (own) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t e = sec_f + sec_b + (int64_t)k * ld + i;
+                    comp_add(gacc + e, gacc + half + e, pg[k]);
+                    pg[k] = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    double chk = 0.0;
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) chk += lam[v];
+    if (own && !finite_d(chk)) atomicOr(a.flag, 1);
+}
+
+// Scatter the accumulators into the caller's layout: per instance (grid.x =
+// instance) or summed over instances in instance order (grid.x = 1).
+struct FinArgs {
+    const InstDesc *desc;
+    int32_t n_inst;
+    const float *gacc;
+    int64_t gacc_stride;
+    const int64_t *goff;        // per instance offset into grad_g (per-instance mode)
+    float *grad_g, *gna, *gk, *gl;
+    int32_t per_instance;
+};
+
+__global__ __launch_bounds__(256) void adjoint_finalize(FinArgs f)
+{
+    const int b0 = f.per_instance ? blockIdx.x : 0;
+    const int nb = f.per_instance ? 1 : f.n_inst;
+    const InstDesc d = f.desc[b0];
+    const int n = d.n, ld = d.ld, n_ln = d.n - d.n_pn;
+    const int64_t sec_f = (int64_t)n * ld, sec_b = (int64_t)n_ln * ld;
+    const int64_t half = sec_f + sec_b + 3LL * ld;
+    auto total = [&](int64_t e) {
+        double s = 0.0;
+        for (int b = b0; b < b0 + nb; ++b) {
+            const float *g = f.gacc + (int64_t)b * f.gacc_stride;
+            s += (double)g[e] + (double)g[half + e];
+        }
+        return (float)s;
+    };
+    float *out = f.grad_g + (f.per_instance ? f.goff[b0] : 0);
+    for (int p = 0; p < d.n_paths; ++p) {
+        const int64_t *pi = d.paths + 6 * p;
+        const int type = (int)pi[0], pre0 = (int)pi[1], pre1 = (int)pi[2];
+        const int post0 = (int)pi[3], post1 = (int)pi[4];
+        const int64_t go = pi[5];
+        const int npre = pre1 - pre0;
+        const int64_t cnt = (int64_t)(post1 - post0) * npre;
+        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const int ii = post0 + (int)(e / npre), j = pre0 + (int)(e % npre);
+            const int64_t slot = type == T_GABA_B ? sec_f + (int64_t)(j - d.n_pn) * ld + ii
+                                                  : (int64_t)j * ld + ii;
+            out[go + e] = d.maskt[slot] ? total(slot) : 0.f;
+        }
+    }
+    const int64_t noff = f.per_instance ? d.off : 0;
+    for (int ii = threadIdx.x; ii < n; ii += blockDim.x) {
+        f.gna[noff + ii] = total(sec_f + sec_b + 0LL * ld + ii);
+        f.gk[noff + ii] = total(sec_f + sec_b + 1LL * ld + ii);
+        f.gl[noff + ii] = total(sec_f + sec_b + 2LL * ld + ii);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+struct AdjWork {
+    double *ws = nullptr;
+    size_t ws_bytes = 0;
+    float *gacc = nullptr;
+    size_t gacc_bytes = 0;
+    int64_t *goff = nullptr;
+};
+
+static psst_status ensure(void **p, size_t *have, size_t need)
+{
+    if (*have >= need) return PSST_OK;
+    (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    HIPCHK(hipMalloc(p, need));
+    *have = need;
+    return PSST_OK;
+}
+
+static const void *adj_fn(int bs)
+{
+    switch (bs) {
+    case 64: return (const void *)adjoint_wg_kernel<64>;
+    case 128: return (const void *)adjoint_wg_kernel<128>;
+    case 256: return (const void *)adjoint_wg_kernel<256>;
+    case 512: return (const void *)adjoint_wg_kernel<512>;
+    }
+    return nullptr;
+}
+
+psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
+                        int64_t nt, const std::vector<int64_t> &offsets, AdjWork **work,
+                        const float *ckpt, int32_t K, const psst_stimulus *stim, float dt,
+                        int64_t n_steps, int64_t step0, const float *dLdV, float *grad_g,
+                        float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
+                        size_t lds_max, void *stream)
+{
+    const int32_t n = (int32_t)nets.size();
+    int max_n = 0, max_ld = 0;
+    int64_t gstride = 0;
+    for (auto *q : nets) {
+        max_n = std::max(max_n, q->n);
+        max_ld = std::max(max_ld, q->ld);
+        gstride = std::max(gstride, gacc_floats(q->n, q->n - q->n_pn, q->ld));
+    }
+    if (max_n > 512)
+        return fail(PSST_ERR_UNSUPPORTED, "the adjoint takes networks of at most 512 neurons");
+    const int bs = max_n <= 64 ? 64 : max_n <= 128 ? 128 : max_n <= 256 ? 256 : 512;
+    if (4 * bs < max_ld) return fail(PSST_ERR_UNSUPPORTED, "no adjoint launch shape for n=%d", max_n);
+    if (!*work) *work = new AdjWork();
+    AdjWork *W = *work;
+    const int64_t wstride = ws_doubles(max_ld, K);
+    psst_status s = ensure((void **)&W->ws, &W->ws_bytes, sizeof(double) * wstride * n);
+    if (s != PSST_OK) return s;
+    if ((s = ensure((void **)&W->gacc, &W->gacc_bytes, sizeof(float) * gstride * n)) != PSST_OK)
+        return s;
+    // LDS: q and product vectors, the forward view, and G when it fits
+    size_t need = 0;
+    bool any_fit = false;
+    for (auto *q : nets) {
+        const size_t base = sizeof(double) * 5 * q->ld + wg_lds_bytes(false, q->ld, q->nch, 0);
+        need = std::max(need, base);
+        any_fit |= base + sizeof(float) * q->g_floats <= lds_max;
+    }
+    if (need > lds_max) return fail(PSST_ERR_UNSUPPORTED, "adjoint LDS buffers exceed the LDS");
+    const size_t lds = any_fit ? lds_max : need;
+    const void *fn = adj_fn(bs);
+    if (lds > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    AdjArgs a{};
+    a.desc = d_desc;
+    a.ckpt = ckpt;
+    a.K = K;
+    a.nt = nt;
+    if (stim) {
+        a.stim.i_const = stim->i_const_nA;
+        a.stim.pulse_ptr = stim->pulse_ptr;
+        a.stim.on_step = stim->on_step;
+        a.stim.off_step = stim->off_step;
+        a.stim.amp = stim->amp_nA;
+    }
+    a.dt = (double)dt;
+    a.n_steps = n_steps;
+    a.step0 = step0;
+    a.dLdV = dLdV;
+    a.ws = W->ws;
+    a.ws_stride = wstride;
+    a.gacc = W->gacc;
+    a.gacc_stride = gstride;
+    a.ld_max = max_ld;
+    a.lds_bytes = (int64_t)lds;
+    a.flag = flag;
+    hipStream_t st = (hipStream_t)stream;
+    void *args[] = {&a};
+    if (n_steps > 0) HIPCHK(hipLaunchKernel(fn, dim3(n), dim3(bs), args, lds, st));
+    else HIPCHK(hipMemsetAsync(W->gacc, 0, sizeof(float) * gstride * n, st));
+    // grad_g offsets per instance (per-instance mode)
+    std::vector<int64_t> goff(n, 0);
+    for (int32_t k = 1; k < n; ++k) goff[k] = goff[k - 1] + nets[k - 1]->grad_entries;
+    if (!W->goff) HIPCHK(hipMalloc(&W->goff, sizeof(int64_t) * n));
+    HIPCHK(hipMemcpyAsync(W->goff, goff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));     // goff host copy goes out of scope
+    FinArgs f{};
+    f.desc = d_desc;
+    f.n_inst = n;
+    f.gacc = W->gacc;
+    f.gacc_stride = gstride;
+    f.goff = W->goff;
+    f.grad_g = grad_g;
+    f.gna = gna;
+    f.gk = gk;
+    f.gl = gl;
+    f.per_instance = per_instance;
+    void *fargs[] = {&f};
+    HIPCHK(hipLaunchKernel((const void *)adjoint_finalize, dim3(per_instance ? n : 1), dim3(256),
+                           fargs, 0, st));
+    (void)offsets;
+    return PSST_OK;
+}
+
+void adjoint_free(AdjWork *w)
+{
+    if (!w) return;
+    (void)hipFree(w->ws);
+    (void)hipFree(w->gacc);
+    (void)hipFree(w->goff);
+    delete w;
+}

@@ -30,6 +30,10 @@ struct InstDesc {
     int64_t off;        // first neuron of this instance in the packed arrays
     int32_t n, n_pn, ld, flags;   // flags bit 0: has slow GABA
     double cg, ci;      // nS -> mS/cm^2 and nA -> uA/cm^2 for this network's area
+    const int64_t *paths;     // [n_paths][6]: type, pre0, pre1, post0, post1, grad offset
+    const uint8_t *maskt;     // synapse mask laid out like gt (then gtb)
+    int32_t n_paths;
+    int64_t grad_entries;     // entries of one copy of the pathway blocks
 };
 
 enum { DESC_GABAB = 1 };
@@ -159,6 +163,63 @@ __device__ inline void hh_rhs(const double Y[NVAR], const Prm &P, const Kin &K,
         f[YR] = 0.0;
         f[YG] = 0.0;
     }
+}
+
+// Vector-Jacobian product of hh_rhs at Y with cotangent w (dL/df): the
+// elementwise part of u = J(Y)^T w, the synaptic weights q_t = dL/dI-share
+// of each synapse class (q_t = w_V * (-(V - E_t) * cg / C), so that
+// dL/dg_ij = q_t(i) * x_j and the presynaptic term is sum_i g_ij q_t(i)), and
+// the per-neuron conductance cotangents dg = (dL/dg_Na, dL/dg_K, dL/dg_L).
+// The synaptic terms u_s += sum_i g_ij q(i), u_G += (...) dx/dG are added by
+// the caller, which holds the conductance matrix.
+__device__ inline void hh_vjp(const double Y[NVAR], const Prm &P, const Kin &K, double cgf,
+                              double gs_ach, double gs_ga, double gs_gb, const double w[NVAR],
+                              bool is_ln, bool gabab, double u[NVAR], double q[3], double dg[3])
+{
+    const double V = Y[YV], m = Y[YM], h = Y[YH], n = Y[YN], s = Y[YS];
+    const Rates r = hh_rates(V);
+    // derivatives of the rates in V
+    const double dam = exprel_d((V + 40.0) * 0.1) * 0.1;
+    const double dbm = -r.bm * (1.0 / 18.0);
+    const double dah = -r.ah * 0.05;
+    const double dbh = r.bh * (1.0 - r.bh) * 0.1;
+    const double dan = 0.1 * exprel_d((V + 55.0) * 0.1) * 0.1;
+    const double dbn = -r.bn * 0.0125;
+    const double invC = 1.0 / P.C;
+    const double m2h = m * m * h, m3 = m * m * m, n3 = n * n * n;
+    const double wV = w[YV];
+    const double gtot = P.gNa * m3 * h + P.gK * n3 * n + P.gL + gs_ach + gs_ga + gs_gb;
+    double uV = -wV * gtot * invC;
+    uV += w[YM] * (dam * (1.0 - m) - dbm * m);
+    uV += w[YH] * (dah * (1.0 - h) - dbh * h);
+    uV += w[YN] * (dan * (1.0 - n) - dbn * n);
+    const double al = is_ln ? K.a_ga : K.a_ach;
+    const double be = is_ln ? K.b_ga : K.b_ach;
+    const double kp = is_ln ? K.kp_ga : K.kp_ach;
+    const double T = is_ln ? release(V, K.vp_ga, K.kp_ga) : release(V, K.vp_ach, K.kp_ach);
+    uV += w[YS] * al * (T * (1.0 - T) / kp) * (1.0 - s);
+    u[YS] = -w[YS] * (al * T + be);
+    if (is_ln && gabab) {
+        const double TB = release(V, K.vp_gb, K.kp_gb);
+        const double rr = Y[YR];
+        uV += w[YR] * K.r1 * (TB * (1.0 - TB) / K.kp_gb) * (1.0 - rr);
+        u[YR] = -w[YR] * (K.r1 * TB + K.r2) + w[YG] * K.r3;
+        u[YG] = -w[YG] * K.r4;
+    } else {
+        u[YR] = 0.0;
+        u[YG] = 0.0;
+    }
+    u[YV] = uV;
+    const double dENa = V - P.ENa, dEK = V - P.EK;
+    u[YM] = -wV * 3.0 * P.gNa * m2h * dENa * invC - w[YM] * (r.am + r.bm);
+    u[YH] = -wV * P.gNa * m3 * dENa * invC - w[YH] * (r.ah + r.bh);
+    u[YN] = -wV * 4.0 * P.gK * n3 * dEK * invC - w[YN] * (r.an + r.bn);
+    dg[0] = -wV * m3 * h * dENa * invC;
+    dg[1] = -wV * n3 * n * dEK * invC;
+    dg[2] = -wV * (V - P.EL) * invC;
+    q[0] = -wV * (V - K.e_ach) * cgf * invC;
+    q[1] = -wV * (V - K.e_ga) * cgf * invC;
+    q[2] = -wV * (V - K.e_gb) * cgf * invC;
 }
 
 // Store a float64 value as a float32 pair (value, compensation); returns the

@@ -81,6 +81,7 @@ static void net_free(psst_network *n)
     hipFree(n->d_desc);
     hipFree(n->d_order);
     hipFree(n->d_flag);
+    hipFree(n->d_paths);
     stage_batch_free(n->single);
     stage_net_free(n->stage);
     delete n;
@@ -240,7 +241,20 @@ extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t 
     NETCHK(hipMemcpy(net->d_prm, prm.data(), sizeof(float) * prm.size(), hipMemcpyHostToDevice));
     NETCHK(hipMalloc(&net->d_kin, sizeof(float) * 3 * NKIN));
     NETCHK(hipMemcpy(net->d_kin, net->h_kin.data(), sizeof(float) * 3 * NKIN, hipMemcpyHostToDevice));
+    if (np > 0) {
+        std::vector<int64_t> pt;
+        for (auto &q : net->paths) {
+            pt.push_back(q.type); pt.push_back(q.pre0); pt.push_back(q.pre1);
+            pt.push_back(q.post0); pt.push_back(q.post1); pt.push_back(q.grad_off);
+        }
+        NETCHK(hipMalloc(&net->d_paths, sizeof(int64_t) * pt.size()));
+        NETCHK(hipMemcpy(net->d_paths, pt.data(), sizeof(int64_t) * pt.size(), hipMemcpyHostToDevice));
+    }
     InstDesc &d = net->desc;
+    d.paths = net->d_paths;
+    d.maskt = net->d_maskt;
+    d.n_paths = np;
+    d.grad_entries = net->grad_entries;
     d.gt = net->d_gt;
     d.gtb = net->d_gtb;
     d.prm = net->d_prm;
@@ -471,6 +485,7 @@ static void batch_free(psst_batch *b)
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
     stage_batch_free(b->stage);
+    adjoint_free(b->adj);
     delete b;
 }
 
@@ -807,5 +822,9 @@ extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
     if ((s = validate_stim(stim)) != PSST_OK) return s;
     if (!per_instance && !b->shared)
         return fail(PSST_ERR_INVALID_ARGUMENT, "summed gradients need every instance to share one network");
-    return fail(PSST_ERR_UNSUPPORTED, "adjoint not built yet");
+    if (b->stage_path)
+        return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available on the per-stage path");
+    return adjoint_run(b->nets, b->d_desc, b->nt, b->offsets, &b->adj, ckpt, K, stim, dt, n_steps,
+                       step0, dLdV, grad_g, grad_gNa, grad_gK, grad_gL, per_instance, b->d_flag,
+                       max_lds_per_block(), stream);
 }

@@ -27,6 +27,7 @@ psst_status fail(psst_status s, const char *fmt, ...);
 
 struct StageNet;
 struct StageBatch;
+struct AdjWork;
 
 using psst::InstDesc;
 using psst::WGArgs;
@@ -47,6 +48,7 @@ struct psst_network {
     // device
     float *d_gt = nullptr, *d_gtb = nullptr, *d_prm = nullptr, *d_kin = nullptr;
     uint8_t *d_maskt = nullptr;     // fast/slow mask transposed like gt (1 = synapse)
+    int64_t *d_paths = nullptr;     // [n_paths][6] pathway table for gradient scatter
     InstDesc desc{};
     InstDesc *d_desc = nullptr;
     int32_t *d_order = nullptr;
@@ -86,5 +88,15 @@ struct psst_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<hipGraphNode_t> nodes;
     std::vector<WGArgs> node_args;
+    AdjWork *adj = nullptr;         // adjoint workspace, sized on first use
 };
 
+
+// Discrete adjoint over a batch of per-instance networks (adjoint.hip).
+psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
+                        int64_t nt, const std::vector<int64_t> &offsets, AdjWork **work,
+                        const float *ckpt, int32_t K, const psst_stimulus *stim, float dt,
+                        int64_t n_steps, int64_t step0, const float *dLdV, float *grad_g,
+                        float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
+                        size_t lds_max, void *stream);
+void adjoint_free(AdjWork *w);
