@@ -149,6 +149,72 @@ def bench_large(args, torch, psst, W, dev, stream):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args, torch, psst, W, dev, stream):
+    """Adjoint workload: trials of the 120-neuron network sharing one set of
+    conductances; forward with checkpoints every K steps and the V trace,
+    MSE loss of the PN traces against targets, psst_adjoint for dL/dg_ij and
+    dL/dg_Na, g_K, g_L summed over trials.  Targets: the V traces of the same
+    trials at the hidden conductances (a GPU forward run; any targets time
+    the same)."""
+    B, T, K = args.adjoint_trials, args.adjoint_steps, args.adjoint_K
+    hidden, ev, i_nA, v0 = W.config5(B)
+    n = ev.n
+    stim = psst.DeviceStimulus(torch.from_numpy(i_nA.ravel()).to(dev))
+    v0d = torch.from_numpy(v0.ravel()).to(dev)
+    nh = psst.network_create(hidden)
+    bh = psst.batch_create([nh] * B)
+    nt = bh.n_total
+    st = torch.zeros(14 * nt, dtype=torch.float32, device=dev)
+    psst.batch_state_init(bh, v0d, st)
+    target = torch.empty((T, nt), dtype=torch.float32, device=dev)
+    psst.integrate_batch(bh, st, stim, DT, T, 0, psst.DeviceRecord(target, 1, T))
+    psst.batch_poll(bh)
+    del bh, nh
+    net = psst.network_create(ev)
+    batch = psst.batch_create([net] * B)
+    v = torch.empty((T, nt), dtype=torch.float32, device=dev)
+    ck = torch.empty(((T + K - 1) // K, 14 * nt), dtype=torch.float32, device=dev)
+    pn = torch.zeros(nt, dtype=torch.bool, device=dev)
+    for t in range(B):
+        pn[t * n:t * n + ev.n_pn] = True
+    gg = torch.empty(net.grad_size, dtype=torch.float32, device=dev)
+    gna = torch.empty(n, dtype=torch.float32, device=dev)
+    gk, gl = torch.empty_like(gna), torch.empty_like(gna)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev2 = torch.cuda.Event(enable_timing=True)
+    ev3 = torch.cuda.Event(enable_timing=True)
+    res = None
+    for rep in range(2):               # first pass warms up (workspace allocation)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        psst.batch_state_init(batch, v0d, st)
+        psst.integrate_batch(batch, st, stim, DT, T, 0, psst.DeviceRecord(v, 1, T), ck, K)
+        ev1.record(stream)
+        dl = torch.where(pn, 2.0 * (v - target) / (B * ev.n_pn * T), torch.zeros_like(v))
+        ev2.record(stream)
+        psst.adjoint(batch, ck, K, stim, DT, T, 0, dl, gg, gna, gk, gl, per_instance=False)
+        ev3.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        psst.batch_poll(batch)
+        fwd = ev0.elapsed_time(ev1) / 1e3
+        adj = ev2.elapsed_time(ev3) / 1e3
+        res = {"workload": f"{B} trials x {n}-neuron network (90 PN + 30 LN, ACh + fast "
+                           f"GABA), {T} RK4 steps (dt 0.01 ms), checkpoint every {K} steps; "
+                           "MSE of PN traces; gradients w.r.t. g_ij, g_Na, g_K, g_L",
+               "adjoint_neuron_steps_per_s": B * n * T / adj,
+               "adjoint_steps_per_s": T / adj,
+               "adjoint_s": adj, "forward_with_checkpoints_s": fwd,
+               "forward_plus_adjoint_s": wall,
+               "forward_plus_adjoint_neuron_steps_per_s": B * n * T / wall,
+               "grad_norm": float(gg.norm())}
+    log(f"adjoint: {res['adjoint_neuron_steps_per_s']:.3e} neuron-steps/s "
+        f"({res['adjoint_s']:.2f} s for {T} steps; forward {res['forward_with_checkpoints_s']:.2f} s)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +238,10 @@ def main():
     ap.add_argument("--workload", choices=("batched", "large"), default="batched",
                     help="batched: the 4096-network batch (the default line); large: the "
                          "16384-neuron network x 64 trials on the per-stage MFMA path")
+    ap.add_argument("--adjoint-trials", type=int, default=256)
+    ap.add_argument("--adjoint-steps", type=int, default=20000)
+    ap.add_argument("--adjoint-K", type=int, default=100)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
@@ -303,6 +373,8 @@ def main():
                            "steps each, one psst_integrate launch per network"}
         log(f"plain: {plain['value']:.3e} neuron-steps/s")
 
+    adjoint = None if args.no_adjoint else bench_adjoint(args, torch, psst, W, dev, stream)
+
     # ---------------- CPU baseline (oracle) and parity spot check ---------
     cpu = None
     parity = None
@@ -361,6 +433,7 @@ def main():
         "plain": plain,
         "batched_over_plain": (value / plain["value"]) if plain else None,
         "parity": parity,
+        "adjoint": adjoint,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
