@@ -214,8 +214,8 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
                     const int jr = slow ? j - n : j;
                     const double *qv = qb + (slow ? 2 : (j < n_pn ? 0 : 1)) * ld;
                     double acc = 0.0;
-                    if (w.glds) {
-                        const float *row = w.gl + (slow ? (int64_t)n * ld : 0) + (int64_t)jr * ld;
+                    if (w.R >= CW) {
+                        const float *row = lds_row(w, slow ? 1 : 0, jr);
                         for (int ii = lane; ii < n; ii += 64) acc = fma((double)row[ii], qv[ii], acc);
                     } else {
                         const float *row = (slow ? d.gtb : d.gt) + (int64_t)jr * ld;
@@ -395,14 +395,12 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
         return s;
     // LDS: q and product vectors, the forward view, and G when it fits
     size_t need = 0;
-    bool any_fit = false;
     for (auto *q : nets) {
         const size_t base = sizeof(double) * 5 * q->ld + wg_lds_bytes(false, q->ld, q->nch, 0);
         need = std::max(need, base);
-        any_fit |= base + sizeof(float) * q->g_floats <= lds_max;
     }
     if (need > lds_max) return fail(PSST_ERR_UNSUPPORTED, "adjoint LDS buffers exceed the LDS");
-    const size_t lds = any_fit ? lds_max : need;
+    const size_t lds = lds_max;     // the rest holds conductance columns
     const void *fn = adj_fn(bs);
     if (lds > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     AdjArgs a{};

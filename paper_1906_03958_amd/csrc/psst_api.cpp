@@ -428,9 +428,11 @@ extern "C" psst_status psst_integrate(psst_network *net, float *state, const pss
     if (n_steps == 0) return PSST_OK;
     int bs, npt;
     default_shape(net->n, &bs, &npt);
-    const size_t lds_g = wg_lds_bytes(true, net->ld, net->nch, net->g_floats);
-    const size_t lds = lds_g <= max_lds_per_block() ? lds_g
-                                                    : wg_lds_bytes(false, net->ld, net->nch, 0);
+    // the whole LDS: whatever the activation and partial buffers leave holds
+    // the leading columns of every conductance chunk (all of G when it fits)
+    const char *env = std::getenv("PSST_LDS_G");
+    const size_t lds = (env && env[0] == '0') ? wg_lds_bytes(false, net->ld, net->nch, 0)
+                                              : max_lds_per_block();
     const WGVariant *v = find_variant(bs, npt);
     if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant for n=%d", net->n);
     if ((s = set_lds_attr(v->fn, lds)) != PSST_OK) return s;
@@ -627,9 +629,9 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     }
 
     // One launch, workgroups in largest-first (LPT) order of cost ~ n^2; the
-    // LDS request is the full per-workgroup LDS whenever some instance's
-    // conductances fit in it (those instances then read G from LDS, the
-    // others stream it from L2/MALL/HBM).
+    // LDS request is the full per-workgroup LDS: each instance keeps the
+    // leading columns of every conductance chunk there (all of G when it
+    // fits) and streams the rest from L2/MALL/HBM.
     std::vector<int32_t> idx(n);
     for (int32_t k = 0; k < n; ++k) idx[k] = k;
     std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
@@ -640,16 +642,14 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     const bool allow_lds = !(env && env[0] == '0');
     Group g;
     size_t need = 0;
-    bool any_fit = false;
     for (int32_t k : idx) {
         const psst_network *q = nets[k];
         g.order.push_back(k);
         g.max_n = std::max(g.max_n, q->n);
         g.max_ld = std::max(g.max_ld, q->ld);
         need = std::max(need, wg_lds_bytes(false, q->ld, q->nch, 0));
-        any_fit |= wg_lds_bytes(true, q->ld, q->nch, q->g_floats) <= lmax;
     }
-    g.lds = (allow_lds && any_fit) ? lmax : need;
+    g.lds = allow_lds ? lmax : need;
     default_shape(g.max_n, &g.bs, &g.npt);
     // PSST_WG_SHAPE="<threads>x<neurons per thread>" fixes the launch shape
     // (and skips tuning) when that variant can take every instance.

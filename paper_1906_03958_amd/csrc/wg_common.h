@@ -29,29 +29,32 @@ __device__ inline Chunks chunks_of(int n, int n_pn, bool gabab)
     return c;
 }
 
-// Partial sums of one chunk for rows 4 r4 .. 4 r4 + 3.  Columns go in
-// batches of U: all U loads are issued before the first is consumed, so each
-// wavefront keeps U 16-byte loads in flight.  Past the chunk end the row
-// index is clamped and the activation taken as 0, which adds exact zeros and
-// leaves the column-order sum unchanged.
-template <int U>
-__device__ __forceinline__ void chunk_rows4(const float *G, int ld, const double *x, int j0,
-                                            int j1, int r4, double &s0, double &s1, double &s2,
+// Partial sums over columns [ja, jb) of one chunk for rows 4 r4 .. 4 r4 + 3,
+// added to s0..s3.  Row jj of the matrix is at G + (jj - row0) * ld.  Columns
+// go in batches of U: all U loads are issued before the first is consumed, so
+// each wavefront keeps U 16-byte loads in flight.  Past jb the row index is
+// clamped and the activation taken as 0, which adds exact zeros and leaves
+// the column-order sum unchanged.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const v4f global_float4;
+typedef __attribute__((address_space(3))) const v4f lds_float4;
+
+template <int U, typename V4>
+__device__ __forceinline__ void chunk_rows4(V4 *G4, int row0, int ld, const double *x, int ja,
+                                            int jb, int r4, double &s0, double &s1, double &s2,
                                             double &s3)
 {
-    const float4 *G4 = reinterpret_cast<const float4 *>(G);
     const int q = ld >> 2;
-    s0 = s1 = s2 = s3 = 0.0;
-    for (int j = j0; j < j1; j += U) {
-        float4 g[U];
+    for (int j = ja; j < jb; j += U) {
+        v4f g[U];
         double xv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int jj = min(j + u, j1 - 1);
-            g[u] = G4[(int64_t)jj * q + r4];
+            const int jj = min(j + u, jb - 1);
+            g[u] = G4[(int64_t)(jj - row0) * q + r4];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = (j + u < j1) ? x[j + u] : 0.0;
+        for (int u = 0; u < U; ++u) xv[u] = (j + u < jb) ? x[j + u] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             s0 = fma((double)g[u].x, xv[u], s0);
@@ -62,42 +65,46 @@ __device__ __forceinline__ void chunk_rows4(const float *G, int ld, const double
     }
 }
 
+// Column range and source of chunk c: matrix 0 = fast (rows = presynaptic
+// index), 1 = slow (rows = LN index); [j0, j1) in that matrix's row numbers
+// and in the matching activation vector.
+__device__ __forceinline__ void chunk_range(const Chunks &ch, int n, int n_pn, int c, int &mat,
+                                            int &j0, int &j1)
+{
+    if (c < ch.na) {
+        mat = 0; j0 = c * CW; j1 = min(j0 + CW, n_pn);
+    } else if (c < ch.na + ch.ng) {
+        mat = 0; j0 = n_pn + (c - ch.na) * CW; j1 = min(j0 + CW, n);
+    } else {
+        mat = 1; j0 = (c - ch.na - ch.ng) * CW; j1 = min(j0 + CW, n - n_pn);
+    }
+}
+
 // One stage's chunk partials: column group cg takes chunks cg, cg + NCG, ...
-__device__ __forceinline__ void stage_partials(const float *G, const float *GB, int ld,
-                                               const double *xf, const double *xb,
+// The first R columns of every chunk are read from the LDS copy (chunk c's
+// rows at gl + c * R * ld), the rest from global memory.
+__device__ __forceinline__ void stage_partials(const float *G, const float *GB, const float *gl,
+                                               int R, int ld, const double *xf, const double *xb,
                                                double *part, const Chunks &ch, int n, int n_pn,
                                                int cg, int NCG, int r4)
 {
     const int nch = ch.na + ch.ng + ch.nb;
     for (int c = cg; c < nch; c += NCG) {
-        const float *M;
-        const double *X;
-        int j0, j1;
-        if (c < ch.na) {
-            M = G; X = xf; j0 = c * CW; j1 = min(j0 + CW, n_pn);
-        } else if (c < ch.na + ch.ng) {
-            M = G; X = xf; j0 = n_pn + (c - ch.na) * CW; j1 = min(j0 + CW, n);
-        } else {
-            M = GB; X = xb; j0 = (c - ch.na - ch.ng) * CW; j1 = min(j0 + CW, n - n_pn);
-        }
-        double s0, s1, s2, s3;
-        chunk_rows4<8>(M, ld, X, j0, j1, r4, s0, s1, s2, s3);
+        int mat, j0, j1;
+        chunk_range(ch, n, n_pn, c, mat, j0, j1);
+        const float *M = mat ? GB : G;
+        const double *X = mat ? xb : xf;
+        const int jr = min(j1, j0 + R);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (jr > j0)
+            chunk_rows4<8>((lds_float4 *)(gl + (int64_t)c * R * ld), j0, ld, X, j0, jr, r4, s0,
+                           s1, s2, s3);
+        if (j1 > jr)
+            chunk_rows4<8>((global_float4 *)M, 0, ld, X, jr, j1, r4, s0, s1, s2, s3);
         double *pc = part + (size_t)c * ld + 4 * r4;
         pc[0] = s0; pc[1] = s1; pc[2] = s2; pc[3] = s3;
     }
 }
-
-// LDS layout of one instance: activations xf[ld], xb[ld], chunk partials
-// [nch][ld] (float64), then -- when the whole instance fits the launch's LDS
-// allocation -- its conductances gt[n][ld] and gtb[n_ln][ld] (float32).
-__device__ __forceinline__ size_t inst_lds_bytes(int n, int n_ln, int ld, int nch, bool gabab,
-                                                 bool with_g)
-{
-    size_t b = sizeof(double) * (size_t)(2 + nch) * ld;
-    if (with_g) b += sizeof(float) * ((size_t)n * ld + (gabab ? (size_t)n_ln * ld : 0));
-    return b;
-}
-
 
 // Injected current (nA) of one neuron at global step g: constant part plus
 // the pulses p0 .. p1-1 that are on (zero-order hold over the step).
@@ -113,11 +120,12 @@ __device__ __forceinline__ double stim_nA(const StimDev &s, double Ic, int32_t p
 // Per-workgroup view of one instance for the synaptic sums.
 struct WGSyn {
     const float *gt, *gtb;     // conductances in global memory
-    const float *gl;           // LDS copy (gt rows then gtb rows) when glds
+    const float *gl;           // LDS copy: the first R rows of every chunk
     double *xf, *xb, *part;    // LDS activations and chunk partials
     Chunks ch;
     int n, n_pn, ld, nch, NCG, r4, cg;
-    bool glds, gabab;
+    int R;                     // resident columns per chunk (CW = whole matrix in LDS)
+    bool gabab;
 };
 
 // Synaptic sums (nS) at stage input Y for the calling thread's neurons
@@ -137,14 +145,9 @@ __device__ __forceinline__ void syn_sums(const WGSyn &w, const Kin &K, const dou
         }
     }
     __syncthreads();
-    if (w.cg < w.NCG) {
-        if (w.glds)
-            stage_partials(w.gl, w.gl + (int64_t)w.n * w.ld, w.ld, w.xf, w.xb, w.part, w.ch, w.n,
-                           w.n_pn, w.cg, w.NCG, w.r4);
-        else
-            stage_partials(w.gt, w.gtb, w.ld, w.xf, w.xb, w.part, w.ch, w.n, w.n_pn, w.cg, w.NCG,
-                           w.r4);
-    }
+    if (w.cg < w.NCG)
+        stage_partials(w.gt, w.gtb, w.gl, w.R, w.ld, w.xf, w.xb, w.part, w.ch, w.n, w.n_pn, w.cg,
+                       w.NCG, w.r4);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -231,8 +234,9 @@ __device__ __forceinline__ void rk4_step_wg(const WGSyn &w, const Kin &K, double
     }
 }
 
-// Set up the workgroup's view of instance d: LDS carve-up and, when the
-// whole instance fits the launch's LDS allocation, the conductance copy.
+// Set up the workgroup's view of instance d: LDS carve-up and the resident
+// part of the conductances -- as many leading columns of every chunk as the
+// launch's LDS allocation leaves room for (all of them when the instance fits).
 template <int BS>
 __device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int64_t lds_bytes)
 {
@@ -250,18 +254,21 @@ __device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int6
     w.gl = gl;
     w.gt = d.gt;
     w.gtb = d.gtb;
-    const int n_ln = d.n - d.n_pn;
-    w.glds = inst_lds_bytes(d.n, n_ln, d.ld, w.nch, w.gabab, true) <= (size_t)lds_bytes;
+    const int64_t room = lds_bytes - (int64_t)sizeof(double) * (2 + w.nch) * d.ld;
+    const int64_t per_col = (int64_t)sizeof(float) * w.nch * d.ld;
+    int64_t R = room > 0 ? room / per_col : 0;
+    w.R = (int)(R < CW ? R : CW);
     const int tid = threadIdx.x;
-    if (w.glds) {
-        const int64_t nf4 = (int64_t)d.n * d.ld / 4;
-        const float4 *src = reinterpret_cast<const float4 *>(d.gt);
-        float4 *dst = reinterpret_cast<float4 *>(gl);
-        for (int64_t e = tid; e < nf4; e += BS) dst[e] = src[e];
-        if (w.gabab) {
-            const int64_t nb4 = (int64_t)n_ln * d.ld / 4;
-            const float4 *srcb = reinterpret_cast<const float4 *>(d.gtb);
-            for (int64_t e = tid; e < nb4; e += BS) dst[nf4 + e] = srcb[e];
+    if (w.R > 0) {
+        const int q = d.ld >> 2;
+        for (int c = 0; c < w.nch; ++c) {
+            int mat, j0, j1;
+            chunk_range(w.ch, d.n, d.n_pn, c, mat, j0, j1);
+            const int rows = min(j1, j0 + w.R) - j0;
+            const float4 *src = reinterpret_cast<const float4 *>((mat ? d.gtb : d.gt) +
+                                                                 (int64_t)j0 * d.ld);
+            float4 *dst = reinterpret_cast<float4 *>(gl + (int64_t)c * w.R * d.ld);
+            for (int e = tid; e < rows * q; e += BS) dst[e] = src[e];
         }
     }
     const int RQ = d.ld >> 2;
@@ -269,6 +276,16 @@ __device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int6
     w.r4 = tid % RQ;
     w.cg = tid / RQ;
     return w;
+}
+
+// Row j of matrix mat (0 fast, 1 slow) in the LDS copy, when the whole
+// instance is resident (R == CW).
+__device__ __forceinline__ const float *lds_row(const WGSyn &w, int mat, int j)
+{
+    const int c = mat ? w.ch.na + w.ch.ng + j / CW
+                      : (j < w.n_pn ? j / CW : w.ch.na + (j - w.n_pn) / CW);
+    const int j0 = mat ? (j / CW) * CW : (j < w.n_pn ? (j / CW) * CW : w.n_pn + ((j - w.n_pn) / CW) * CW);
+    return w.gl + ((int64_t)c * w.R + (j - j0)) * w.ld;
 }
 
 }  // namespace psst
