@@ -12,13 +12,12 @@
 //   dL/dtheta += sum_q (df/dtheta)(Y_q)^T kbar_q.
 //
 // One workgroup per instance.  The forward trajectory is rebuilt segment by
-// segment from checkpoints taken every K steps: the segment's K states are
+// segment from checkpoints taken every K steps: the segment's K steps are
 // recomputed with the forward kernel's own routines (bitwise the forward
-// trajectory) and kept in a float64 workspace; each reverse step recomputes
-// its four stage inputs, then walks the stages backwards.  J^T has an
+// trajectory) and each step's four stage inputs and synaptic sums are kept in
+// a float64 workspace; each reverse step then walks its stages backwards.  J^T has an
 // elementwise part per neuron and a presynaptic part sum_i g_ij q(i) -- a
-// transposed product, one wavefront per presynaptic row with a fixed-order
-// shuffle reduction.  dL/dg_ij = sum over steps and stages of q(i) x_j is a
+// transposed product, one thread per presynaptic row summing in index order.  dL/dg_ij = sum over steps and stages of q(i) x_j is a
 // contraction over the segment's 4K stage records, formed once per segment in
 // float64 and folded into a float32 (value, compensation) pair per entry;
 // per-neuron gradients likewise.
@@ -49,25 +48,23 @@ struct AdjArgs {
 
 // workspace layout of one instance (doubles), ld = padded neuron count
 struct WsLayout {
-    double *ys;   // [K][NVAR][ld] segment states
-    double *sY;   // [4][NVAR][ld] stage inputs of the current step
-    double *sS;   // [4][3][ld]    stage synaptic sums (nS)
-    double *Qs;   // [4K][3][ld]   q of each (step, stage)
-    double *Xs;   // [4K][2][ld]   activations x_s (all rows), x_B (LN rows)
+    double *sY;   // [K][4][NVAR][ld] stage inputs of every step of the segment
+    double *sS;   // [K][4][3][ld]    their synaptic sums (nS)
+    double *Qs;   // [4K][3][ld]      q of each (step, stage)
+    double *Xs;   // [4K][2][ld]      activations x_s (all rows), x_B (LN rows)
 };
 
 __host__ __device__ inline int64_t ws_doubles(int ld, int K)
 {
-    return (int64_t)ld * ((int64_t)NVAR * K + 4 * NVAR + 12 + 12LL * K + 8LL * K);
+    return (int64_t)ld * K * (4LL * NVAR + 12 + 12 + 8);
 }
 
 __device__ inline WsLayout ws_layout(double *base, int ld, int K)
 {
     WsLayout w;
-    w.ys = base;
-    w.sY = w.ys + (int64_t)NVAR * K * ld;
-    w.sS = w.sY + 4LL * NVAR * ld;
-    w.Qs = w.sS + 12LL * ld;
+    w.sY = base;
+    w.sS = w.sY + 4LL * NVAR * K * ld;
+    w.Qs = w.sS + 12LL * K * ld;
     w.Xs = w.Qs + 12LL * K * ld;
     return w;
 }
@@ -89,11 +86,26 @@ __device__ inline void comp_add(float *hi, float *lo, double v)
     *lo = l;
 }
 
-__device__ inline double wave_sum(double v)
+// sum_i row[i] q[i] over i < n in index order; row holds ld >= n floats
+// (zero padded to a multiple of 4)
+// sum_i row[i] q[i] over i < n: four interleaved partial sums (i mod 4),
+// each in index order, added as (s0 + s1) + (s2 + s3); row holds ld >= n
+// floats, zero padded, and q is finite up to ld.
+template <typename V4>
+__device__ __forceinline__ double row_dot(V4 *row, const double *q, int n)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const int n4 = (n + 3) >> 2;
+#pragma unroll 4
+    for (int k = 0; k < n4; ++k) {
+        const v4f g = row[k];
+        const int i0 = 4 * k;
+        s0 = fma((double)g.x, q[i0], s0);
+        s1 = fma((double)g.y, q[i0 + 1], s1);
+        s2 = fma((double)g.z, q[i0 + 2], s2);
+        s3 = fma((double)g.w, q[i0 + 3], s3);
+    }
+    return (s0 + s1) + (s2 + s3);
 }
 
 template <int BS>
@@ -104,12 +116,31 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
     const int b = blockIdx.x;
     const InstDesc d = a.desc[b];
     const int n = d.n, n_pn = d.n_pn, ld = d.ld, n_ln = d.n - d.n_pn;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NW = BS / 64;
-    // LDS: q vectors [3][ld], transposed products [2][ld], then the forward view
+    const int tid = threadIdx.x;
+    // LDS: q vectors [3][ld] and transposed products [2][ld]; then, when
+    // they fit, the step's four stage records [4][5][ld] and the gradient
+    // accumulator as float32 (value, compensation) planes [2][rows][ld], or
+    // else a staging area for one step's stage data [40][ld]; then the
+    // forward view with as many conductance columns as remain.
+    const bool gb_net = (d.flags & DESC_GABAB) != 0;
+    const int rows = n + (gb_net ? n_ln : 0);
+    const Chunks ch0 = chunks_of(n, n_pn, gb_net);
+    const int64_t fwd_min = (int64_t)sizeof(double) * (2 + ch0.na + ch0.ng + ch0.nb) * ld;
+    const int64_t lacc_bytes = (int64_t)sizeof(double) * (5 + 20) * ld +
+                               (int64_t)sizeof(float) * 2 * rows * ld;
+    const bool lacc = lacc_bytes + fwd_min <= a.lds_bytes;
     double *qb = lds_d;
     double *tb = lds_d + 3 * ld;
-    const WGSyn w = wg_setup<BS>(d, lds_d + 5 * ld, a.lds_bytes - (int64_t)sizeof(double) * 5 * ld);
+    double *recs = lds_d + 5 * ld;                         // lacc: [4][5][ld]
+    float *gls = reinterpret_cast<float *>(lds_d + 25 * ld);  // lacc: [2][rows][ld]
+    // staging of one step's stage data (40 doubles per neuron) when it takes
+    // at most half of the LDS: one global round trip per reverse step
+    const int64_t stage_d = 40LL * ld;
+    const bool staged = !lacc && (int64_t)sizeof(double) * (5 * ld + stage_d) * 2 <= a.lds_bytes;
+    double *stg = lds_d + 5 * ld;
+    const int64_t used_b = lacc ? lacc_bytes
+                                : (int64_t)sizeof(double) * (5 * ld + (staged ? stage_d : 0));
+    const WGSyn w = wg_setup<BS>(d, lds_d + used_b / sizeof(double), a.lds_bytes - used_b);
     const bool gabab = w.gabab;
     const Kin K = load_kin(d.kin);
     const double dt = a.dt;
@@ -120,11 +151,12 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
     const int64_t sec_f = (int64_t)n * ld, sec_b = (int64_t)n_ln * ld, sec_p = 3LL * ld;
     const int64_t half = sec_f + sec_b + sec_p;     // value plane size
     for (int64_t e = tid; e < 2 * half; e += BS) gacc[e] = 0.f;
-    StageStash stash;
-    stash.sY = W.sY;
-    stash.sS = W.sS;
-    stash.ld = ld;
 
+    for (int e = tid; e < 3 * ld; e += BS) qb[e] = 0.0;   // padding entries stay 0
+    if (lacc) {
+        for (int e = tid; e < 20 * ld; e += BS) recs[e] = 0.0;
+        for (int e = tid; e < 2 * rows * ld; e += BS) gls[e] = 0.f;
+    }
     const int i = tid;                               // the thread's neuron (NPT = 1)
     const bool own = i < n;
     const int ic = own ? i : 0;
@@ -156,23 +188,34 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
         for (int v = 0; v < NVAR; ++v)
             y[0][v] = (double)cp[(2 * v) * NT + gi] + (double)cp[(2 * v + 1) * NT + gi];
         for (int s = 0; s < L; ++s) {
-            if (own)
-#pragma unroll
-                for (int v = 0; v < NVAR; ++v) W.ys[((int64_t)s * NVAR + v) * ld + i] = y[0][v];
+            StageStash stash;      // this step's stage inputs and sums
+            stash.sY = W.sY + (int64_t)s * 4 * NVAR * ld;
+            stash.sS = W.sS + (int64_t)s * 12 * ld;
+            stash.ld = ld;
             double Iu[NPT] = {d.ci * stim_nA(a.stim, Ic, p0, p1, a.step0 + s0 + s)};
-            rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr);
+            rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, &stash);
         }
         // ---- reverse steps
         for (int s = L - 1; s >= 0; --s) {
             const int64_t ls = s0 + s;                 // local step index
             if (own) lam[YV] += (double)a.dLdV[ls * NT + gi];
+            const double *sYs = W.sY + (int64_t)s * 4 * NVAR * ld;
+            const double *sSs = W.sS + (int64_t)s * 12 * ld;
+            if (staged) {
+                // each thread moves its own neuron's 40 values (the same
+                // thread reads them back, so no barrier is needed)
+                if (own) {
+                    double tmp[40];
 #pragma unroll
-            for (int v = 0; v < NVAR; ++v) y[0][v] = own ? W.ys[((int64_t)s * NVAR + v) * ld + i] : 0.0;
-            double Iu[NPT] = {d.ci * stim_nA(a.stim, Ic, p0, p1, a.step0 + ls)};
-            double ytmp[NPT][NVAR];
+                    for (int e = 0; e < 28; ++e) tmp[e] = sYs[(int64_t)e * ld + i];
 #pragma unroll
-            for (int v = 0; v < NVAR; ++v) ytmp[0][v] = y[0][v];
-            rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, ytmp, &stash);
+                    for (int e = 0; e < 12; ++e) tmp[28 + e] = sSs[(int64_t)e * ld + i];
+#pragma unroll
+                    for (int e = 0; e < 40; ++e) stg[(int64_t)e * ld + i] = tmp[e];
+                }
+                sYs = stg;
+                sSs = stg + 28 * ld;
+            }
             double un[NVAR], usum[NVAR];
 #pragma unroll
             for (int v = 0; v < NVAR; ++v) {
@@ -183,46 +226,48 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
                 double Yq[NVAR], kb[NVAR], u[NVAR], qq[3], dg[3];
 #pragma unroll
                 for (int v = 0; v < NVAR; ++v) {
-                    Yq[v] = own ? W.sY[(q * NVAR + v) * ld + i] : 0.0;
+                    Yq[v] = own ? sYs[(q * NVAR + v) * ld + i] : 0.0;
                     kb[v] = dt * bq[q] * lam[v] + (q < 3 ? dt * cq[q + 1] * un[v] : 0.0);
                 }
                 if (!own) Yq[YM] = Yq[YH] = Yq[YN] = 0.5;   // keep idle lanes finite
-                const double sa = own ? W.sS[(q * 3 + 0) * ld + i] : 0.0;
-                const double sg = own ? W.sS[(q * 3 + 1) * ld + i] : 0.0;
-                const double sbv = own ? W.sS[(q * 3 + 2) * ld + i] : 0.0;
+                const double sa = own ? sSs[(q * 3 + 0) * ld + i] : 0.0;
+                const double sg = own ? sSs[(q * 3 + 1) * ld + i] : 0.0;
+                const double sbv = own ? sSs[(q * 3 + 2) * ld + i] : 0.0;
                 hh_vjp(Yq, P, K, d.cg, d.cg * sa, d.cg * sg, d.cg * sbv, kb, is_ln, gabab, u, qq,
                        dg);
                 const int64_t rec = ls - s0;           // stage record within the segment
+                double *qv0 = lacc ? recs + q * 5 * ld : qb;  // this stage's q vectors
                 if (own) {
                     pg[0] += dg[0];
                     pg[1] += dg[1];
                     pg[2] += dg[2];
 #pragma unroll
-                    for (int t = 0; t < 3; ++t) {
-                        qb[t * ld + i] = qq[t];
-                        W.Qs[((rec * 4 + q) * 3 + t) * ld + i] = qq[t];
+                    for (int t = 0; t < 3; ++t) qv0[t * ld + i] = qq[t];
+                    if (lacc) {
+                        recs[(q * 5 + 3) * ld + i] = Yq[YS];
+                        if (gabab && is_ln) recs[(q * 5 + 4) * ld + (i - n_pn)] = gabab_act(Yq[YG], K);
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) W.Qs[((rec * 4 + q) * 3 + t) * ld + i] = qq[t];
+                        W.Xs[((rec * 4 + q) * 2 + 0) * ld + i] = Yq[YS];
+                        if (gabab && is_ln)
+                            W.Xs[((rec * 4 + q) * 2 + 1) * ld + (i - n_pn)] = gabab_act(Yq[YG], K);
                     }
-                    W.Xs[((rec * 4 + q) * 2 + 0) * ld + i] = Yq[YS];
-                    if (gabab && is_ln)
-                        W.Xs[((rec * 4 + q) * 2 + 1) * ld + (i - n_pn)] = gabab_act(Yq[YG], K);
                 }
                 __syncthreads();
-                // presynaptic terms: t_j = sum_i g_ij q_type(j)(i), one wavefront per row
-                const int rows = n + (gabab ? n_ln : 0);
-                for (int j = wave; j < rows; j += NW) {
-                    const bool slow = j >= n;
-                    const int jr = slow ? j - n : j;
-                    const double *qv = qb + (slow ? 2 : (j < n_pn ? 0 : 1)) * ld;
+                // presynaptic terms: t_j = sum_i g_ij q_type(j)(i), one thread per
+                // presynaptic row j (row j of the transposed matrix is contiguous)
+                for (int r = tid; r < rows; r += BS) {
+                    const bool slow = r >= n;
+                    const int jr = slow ? r - n : r;
+                    const double *qv = qv0 + (slow ? 2 : (jr < n_pn ? 0 : 1)) * ld;
                     double acc = 0.0;
-                    if (w.R >= CW) {
-                        const float *row = lds_row(w, slow ? 1 : 0, jr);
-                        for (int ii = lane; ii < n; ii += 64) acc = fma((double)row[ii], qv[ii], acc);
-                    } else {
-                        const float *row = (slow ? d.gtb : d.gt) + (int64_t)jr * ld;
-                        for (int ii = lane; ii < n; ii += 64) acc = fma((double)row[ii], qv[ii], acc);
-                    }
-                    acc = wave_sum(acc);
-                    if (lane == 0) tb[(slow ? ld : 0) + jr] = acc;
+                    if (w.R >= CW)
+                        acc = row_dot((lds_float4 *)lds_row(w, slow ? 1 : 0, jr), qv, n);
+                    else
+                        acc = row_dot((global_float4 *)((slow ? d.gtb : d.gt) + (int64_t)jr * ld),
+                                      qv, n);
+                    tb[(slow ? ld : 0) + jr] = acc;
                 }
                 __syncthreads();
                 if (own) {
@@ -237,33 +282,132 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
             }
 #pragma unroll
             for (int v = 0; v < NVAR; ++v) lam[v] += usum[v];
+            if (lacc) {
+                // dL/dg_ij += sum over this step's stages of q(i) x_j: float64
+                // sum of the four products, then one compensated add per entry
+                __syncthreads();
+                const int q4 = ld >> 2;
+                const int RG = BS / q4;
+                const int i4 = tid % q4, rg = tid / q4;
+                if (rg < RG) {
+                    int cur_t = -1;
+                    double qv[4][4];
+                    for (int r = rg; r < rows; r += RG) {
+                        const bool slow = r >= n;
+                        const int j = slow ? r - n : r;
+                        const int t = slow ? 2 : (j < n_pn ? 0 : 1);
+                        if (t != cur_t) {
+                            cur_t = t;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) qv[q][c] = recs[(q * 5 + t) * ld + 4 * i4 + c];
+                        }
+                        double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const double x = recs[(q * 5 + (slow ? 4 : 3)) * ld + j];
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) v[c] = fma(qv[q][c], x, v[c]);
+                        }
+                        float *hp = gls + (int64_t)r * ld + 4 * i4;
+                        float *lp = gls + (int64_t)(rows + r) * ld + 4 * i4;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            float h, l;
+                            split_store((double)hp[c] + (double)lp[c] + v[c], h, l);
+                            hp[c] = h;
+                            lp[c] = l;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
         }
         __syncthreads();
-        // ---- dL/dg over the segment: sum over its 4L stage records of q(i) x_j
+        // ---- dL/dg over the segment: sum over its 4L stage records of q(i) x_j,
+        // in record order for every entry.  With the staging area available
+        // the records go through LDS eight at a time and each thread keeps
+        // IPT row quads of accumulators per pass.
         {
-            const int rows = n + (gabab ? n_ln : 0);
             const int q4 = ld >> 2;
             const int T = 4 * L;
-            for (int64_t p = tid; p < (int64_t)rows * q4; p += BS) {
-                const int r = (int)(p / q4), i4 = (int)(p % q4);
-                const bool slow = r >= n;
-                const int j = slow ? r - n : r;
-                const int t = slow ? 2 : (j < n_pn ? 0 : 1);
-                const int xs = slow ? 1 : 0;
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                for (int tt = 0; tt < T; ++tt) {
-                    const double xv = W.Xs[((int64_t)tt * 2 + xs) * ld + j];
-                    const double *qr = W.Qs + ((int64_t)tt * 3 + t) * ld + 4 * i4;
-                    a0 = fma(qr[0], xv, a0);
-                    a1 = fma(qr[1], xv, a1);
-                    a2 = fma(qr[2], xv, a2);
-                    a3 = fma(qr[3], xv, a3);
+            const int items = lacc ? 0 : rows * q4;
+            if (staged) {
+                constexpr int IPT = 8, TT = 8;
+                for (int base = 0; base < items; base += BS * IPT) {
+                    double acc[IPT][4];
+#pragma unroll
+                    for (int k = 0; k < IPT; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.0;
+                    for (int t0 = 0; t0 < T; t0 += TT) {
+                        const int tn = min(TT, T - t0);
+                        __syncthreads();
+                        for (int idx = tid; idx < ld; idx += BS) {
+                            for (int rec = 0; rec < tn; ++rec) {
+                                const double *qs = W.Qs + (int64_t)(t0 + rec) * 3 * ld + idx;
+                                const double *xsr = W.Xs + (int64_t)(t0 + rec) * 2 * ld + idx;
+                                double *dst = stg + rec * 5 * ld + idx;
+                                dst[0] = qs[0];
+                                dst[ld] = qs[ld];
+                                dst[2 * ld] = qs[2 * ld];
+                                dst[3 * ld] = xsr[0];
+                                dst[4 * ld] = xsr[ld];
+                            }
+                        }
+                        __syncthreads();
+#pragma unroll
+                        for (int k = 0; k < IPT; ++k) {
+                            const int item = base + tid + k * BS;
+                            if (item >= items) continue;
+                            const int r = item / q4, i4 = item % q4;
+                            const bool slow = r >= n;
+                            const int j = slow ? r - n : r;
+                            const int t = slow ? 2 : (j < n_pn ? 0 : 1);
+                            const int xs = slow ? 1 : 0;
+                            for (int tt = 0; tt < tn; ++tt) {
+                                const double xv = stg[(tt * 5 + 3 + xs) * ld + j];
+                                const double *qr = stg + (tt * 5 + t) * ld + 4 * i4;
+                                acc[k][0] = fma(qr[0], xv, acc[k][0]);
+                                acc[k][1] = fma(qr[1], xv, acc[k][1]);
+                                acc[k][2] = fma(qr[2], xv, acc[k][2]);
+                                acc[k][3] = fma(qr[3], xv, acc[k][3]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < IPT; ++k) {
+                        const int item = base + tid + k * BS;
+                        if (item >= items) continue;
+                        const int r = item / q4, i4 = item % q4;
+                        const bool slow = r >= n;
+                        const int j = slow ? r - n : r;
+                        const int64_t e = (slow ? sec_f : 0) + (int64_t)j * ld + 4 * i4;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) comp_add(gacc + e + c, gacc + half + e + c, acc[k][c]);
+                    }
                 }
-                const int64_t e = (slow ? sec_f : 0) + (int64_t)j * ld + 4 * i4;
-                comp_add(gacc + e + 0, gacc + half + e + 0, a0);
-                comp_add(gacc + e + 1, gacc + half + e + 1, a1);
-                comp_add(gacc + e + 2, gacc + half + e + 2, a2);
-                comp_add(gacc + e + 3, gacc + half + e + 3, a3);
+            } else {
+                for (int64_t p = tid; p < items; p += BS) {
+                    const int r = (int)(p / q4), i4 = (int)(p % q4);
+                    const bool slow = r >= n;
+                    const int j = slow ? r - n : r;
+                    const int t = slow ? 2 : (j < n_pn ? 0 : 1);
+                    const int xs = slow ? 1 : 0;
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                    for (int tt = 0; tt < T; ++tt) {
+                        const double xv = W.Xs[((int64_t)tt * 2 + xs) * ld + j];
+                        const double *qr = W.Qs + ((int64_t)tt * 3 + t) * ld + 4 * i4;
+                        a0 = fma(qr[0], xv, a0);
+                        a1 = fma(qr[1], xv, a1);
+                        a2 = fma(qr[2], xv, a2);
+                        a3 = fma(qr[3], xv, a3);
+                    }
+                    const int64_t e = (slow ? sec_f : 0) + (int64_t)j * ld + 4 * i4;
+                    comp_add(gacc + e + 0, gacc + half + e + 0, a0);
+                    comp_add(gacc + e + 1, gacc + half + e + 1, a1);
+                    comp_add(gacc + e + 2, gacc + half + e + 2, a2);
+                    comp_add(gacc + e + 3, gacc + half + e + 3, a3);
+                }
             }
             if (own) {
 #pragma unroll
@@ -275,6 +419,13 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
             }
         }
         __syncthreads();
+    }
+    if (lacc) {
+        // value plane -> gacc[0 .. rows*ld), compensation plane -> gacc[half ..]
+        for (int64_t e = tid; e < (int64_t)rows * ld; e += BS) {
+            gacc[e] = gls[e];
+            gacc[half + e] = gls[(int64_t)rows * ld + e];
+        }
     }
     double chk = 0.0;
 #pragma unroll
