@@ -21,6 +21,8 @@
 // contraction over the segment's 4K stage records, formed once per segment in
 // float64 and folded into a float32 (value, compensation) pair per entry;
 // per-neuron gradients likewise.
+#include <cstdlib>
+
 #include "runtime.h"
 #include "wg_common.h"
 
@@ -535,7 +537,13 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
     }
     if (max_n > 512)
         return fail(PSST_ERR_UNSUPPORTED, "the adjoint takes networks of at most 512 neurons");
-    const int bs = max_n <= 64 ? 64 : max_n <= 128 ? 128 : max_n <= 256 ? 256 : 512;
+    // 256 threads even for small networks: the spare threads shorten the
+    // synaptic products and the gradient update (measured 10 % faster at 120)
+    int bs = max_n <= 256 ? 256 : 512;
+    if (const char *e = std::getenv("PSST_ADJ_BS")) {     // launch-shape override
+        const int v = std::atoi(e);
+        if (adj_fn(v) && v >= max_n) bs = v;
+    }
     if (4 * bs < max_ld) return fail(PSST_ERR_UNSUPPORTED, "no adjoint launch shape for n=%d", max_n);
     if (!*work) *work = new AdjWork();
     AdjWork *W = *work;
