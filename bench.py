@@ -141,7 +141,7 @@ def bench_large(args, torch, psst, W, dev, stream):
            "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
                         "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4), "traffic": None,
-                        "kernel": "stage_kernel<2,2,2,2> (fp32 MFMA GEMM + fused RK4 stage)",
+                        "kernel": "stage_kernel<4,2,1,2> (fp32 MFMA GEMM, 8 wavefronts, + fused RK4 stage)",
                         "avg_launch_ms": round(1e3 * stage_s, 4),
                         "algorithmic_flops_per_launch": flops_stage,
                         "note": "launch time = graph time per RK4 step / 4 (the step's 4 "

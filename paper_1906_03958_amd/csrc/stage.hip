@@ -107,13 +107,14 @@ __device__ __forceinline__ void tile_load(floatx4 (&rg)[GV], floatx4 (&rx)[XVT],
         rx[u] = *reinterpret_cast<const floatx4 *>(X + (int64_t)(n0 + lr + RPP * u) * Kp + k0 + lk);
 }
 
-// One workgroup per CU (its LDS tiles take most of the CU's LDS), so each
-// wavefront may use the whole register file of its SIMD.
+// One workgroup per CU (its LDS tiles take most of the CU's LDS); WR x WC
+// wavefronts, each owning BR x BC blocks of 16 x 16 outputs.
 template <int WR, int WC, int BR, int BC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void stage_kernel(StageFixed fx, const StageCtl *__restrict__ dctl,
+__global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR * WC / 4, WR * WC / 4))) void stage_kernel(StageFixed fx, const StageCtl *__restrict__ dctl,
                                                     int q)
 {
     constexpr int NTILE = WC * BC * 16;
+    constexpr int NTH = 64 * WR * WC;           // threads per workgroup
     static_assert(WR * BR * 16 == MT, "tile rows");
     constexpr int TILE_F = 2 * (MT + NTILE) * LDK;
     constexpr int ACC_F = 3 * MT * (NTILE + 1);
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // tile NTILE x KT floats = NTILE / 8 float4 per thread; the next tile is
     // loaded into registers while the current one feeds the matrix cores
     constexpr int K4 = KT / 4;                 // float4 per tile row
-    constexpr int RPP = 256 / K4;              // rows per pass of the workgroup
+    constexpr int RPP = NTH / K4;              // rows per pass of the workgroup
     constexpr int GV = MT / RPP;               // G float4 per thread
     constexpr int XVT = NTILE / RPP;           // X float4 per thread
     const int lr = tid / K4, lk = (tid % K4) * 4;
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int64_t g = c.g;
     const int64_t nt = fx.nt;
     bool bad = false;
-    for (int p = tid; p < MT * NTILE; p += 256) {
+    for (int p = tid; p < MT * NTILE; p += NTH) {
         const int il = p % MT, bl = p / MT;
         const int i = m0 + il, b = n0 + bl;
         if (i >= fx.n || b >= fx.B) continue;
@@ -420,8 +421,10 @@ const char *stage_batch_describe(const StageBatch *sb) { return sb ? sb->desc.c_
 static const void *stage_fn(int ntile)
 {
     return ntile == 16 ? (const void *)stage_kernel<4, 1, 1, 1>
-                       : (const void *)stage_kernel<2, 2, 2, 2>;
+                       : (const void *)stage_kernel<4, 2, 1, 2>;
 }
+
+static int stage_threads(int ntile) { return ntile == 16 ? 256 : 512; }
 
 static size_t stage_lds_bytes(int ntile)
 {
@@ -444,7 +447,7 @@ static psst_status build_graph(StageBatch *sb)
         hipKernelNodeParams p{};
         p.func = const_cast<void *>(stage_fn(sb->ntile));
         p.gridDim = grid;
-        p.blockDim = dim3(256);
+        p.blockDim = dim3(stage_threads(sb->ntile));
         p.sharedMemBytes = (unsigned)lds;
         p.kernelParams = kp;
         p.extra = nullptr;
