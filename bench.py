@@ -47,38 +47,73 @@ def _counter_rows(path, kernel_substr, counter):
     return out
 
 
+# the sources each profiled kernel is compiled from: a traffic figure is used
+# only while they are unchanged
+KERNEL_SOURCES = {
+    "rk4_wg_kernel": ("rk4_wg.hip", "wg_common.h", "hh_device.h", "kernels.h"),
+    "stage_kernel": ("stage.hip", "stage.h", "hh_device.h"),
+}
+
+
+def kernel_sha(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_1906_03958_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_file(kernel):
+    return os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+
+
 def write_traffic(args):
-    """Per-launch HBM bytes of the batched kernel from rocprofv3 counters.
+    """Per-launch HBM bytes of a kernel from rocprofv3 counters.
 
     FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by the
     ratio of the known byte count of a plain device copy to what the same
     counter reads for that copy.  Only the longest dispatches (the timed bench
     launches, not the short tuning runs) are used."""
-    f_csv, w_csv, cf_csv, cw_csv = args.write_traffic
+    kernel, f_csv, w_csv, cf_csv, cw_csv = args.write_traffic
     ref = args.copy_calibration * (1 << 20) if args.copy_calibration else (1 << 30)
     cf = [v for _, v in _counter_rows(cf_csv, "copyBuffer", "FETCH_SIZE")]
     cw = [v for _, v in _counter_rows(cw_csv, "copyBuffer", "WRITE_SIZE")]
     kf = float(ref) / (1024.0 * float(np.median(cf)))
     kw = float(ref) / (1024.0 * float(np.median(cw)))
-    f = _counter_rows(f_csv, "rk4_wg_kernel", "FETCH_SIZE")
-    w = _counter_rows(w_csv, "rk4_wg_kernel", "WRITE_SIZE")
+    f = _counter_rows(f_csv, kernel, "FETCH_SIZE")
+    w = _counter_rows(w_csv, kernel, "WRITE_SIZE")
     longest = max(d for d, _ in f)
     f = [v for d, v in f if d > 0.5 * longest]
     longest = max(d for d, _ in w)
     w = [v for d, v in w if d > 0.5 * longest]
     fetch = float(np.mean(f)) * 1024 * kf
     write = float(np.mean(w)) * 1024 * kw
-    src = os.path.join(ROOT, "paper_1906_03958_amd", "csrc", "rk4_wg.hip")
-    out = {"kernel_source_sha": hashlib.sha256(open(src, "rb").read()).hexdigest()[:16],
-           "chunk": args.chunk, "instances": args.instances,
+    out = {"kernel": kernel, "kernel_source_sha": kernel_sha(kernel),
+           "workload": args.workload, "chunk": args.chunk, "instances": args.instances,
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "hbm_bytes_per_launch": fetch + write,
            "fetch_scale": kf, "write_scale": kw, "launches": len(f),
            "copy_reference_bytes": ref}
-    path = os.path.join(ROOT, "profiles", "rk4_batch_traffic.json")
-    with open(path, "w") as fh:
+    with open(traffic_file(kernel), "w") as fh:
         json.dump(out, fh, indent=1)
+        fh.write("\n")
     print(json.dumps(out))
+
+
+def read_traffic(kernel, args):
+    """HBM bytes per launch measured for this kernel source and workload, or
+    None when no such measurement is on file."""
+    path = traffic_file(kernel)
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernel_source_sha") != kernel_sha(kernel) or t.get("workload") != args.workload:
+        return None
+    # a batched launch covers --chunk steps of --instances networks; a large
+    # network launch is one stage whatever the chunk
+    if args.workload == "batched" and (t.get("chunk"), t.get("instances")) != \
+            (args.chunk, args.instances):
+        return None
+    return t.get("hbm_bytes_per_launch")
 
 
 MFMA_FP32_PEAK_TFLOPS = 157.3
@@ -140,7 +175,8 @@ def bench_large(args, torch, psst, W, dev, stream):
                       "launch": psst.batch_describe(batch)},
            "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
                         "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4), "traffic": None,
+                        "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4),
+                        "traffic": read_traffic("stage_kernel", args),
                         "kernel": "stage_kernel<4,2,1,2> (fp32 MFMA GEMM, 8 wavefronts, + fused RK4 stage)",
                         "avg_launch_ms": round(1e3 * stage_s, 4),
                         "algorithmic_flops_per_launch": flops_stage,
@@ -230,11 +266,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float32 buffer 5 times (reference kernel "
                          "for scaling HBM counters) and exit")
-    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV",
+    ap.add_argument("--write-traffic", nargs=5, metavar=("KERNEL", "FETCH_CSV", "WRITE_CSV",
                                                           "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter files of a "
-                         "bench run and of a --copy-calibration run into "
-                         "profiles/rk4_batch_traffic.json and exit")
+                         "bench run (same --workload/--chunk/--instances) and of a "
+                         "--copy-calibration run into profiles/KERNEL_traffic.txt and exit")
     ap.add_argument("--workload", choices=("batched", "large"), default="batched",
                     help="batched: the 4096-network batch (the default line); large: the "
                          "16384-neuron network x 64 trials on the per-stage MFMA path")
@@ -335,15 +371,7 @@ def main():
     bytes_per_rk4 = 16 * sum_n2 + 80 * sum_n
     bytes_per_launch = bytes_per_rk4 * args.chunk
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    src = os.path.join(ROOT, "paper_1906_03958_amd", "csrc", "rk4_wg.hip")
-    ksha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "rk4_batch_traffic.json")
-    if os.path.exists(tfile):
-        t = json.load(open(tfile))
-        if t.get("kernel_source_sha") == ksha and t.get("chunk") == args.chunk and \
-                t.get("instances") == args.instances:
-            traffic = t.get("hbm_bytes_per_launch")
+    traffic = read_traffic("rk4_wg_kernel", args)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "rk4_wg_kernel (batched persistent RK4)",
