@@ -32,29 +32,50 @@ __device__ inline Chunks chunks_of(int n, int n_pn, bool gabab)
 // Partial sums over columns [ja, jb) of one chunk for rows 4 r4 .. 4 r4 + 3,
 // added to s0..s3.  Row jj of the matrix is at G + (jj - row0) * ld.  Columns
 // go in batches of U: all U loads are issued before the first is consumed, so
-// each wavefront keeps U 16-byte loads in flight.  Past jb the row index is
-// clamped and the activation taken as 0, which adds exact zeros and leaves
-// the column-order sum unchanged.
+// each wavefront keeps U 16-byte loads in flight.  In the last, partial batch
+// the row index is clamped and the activation taken as 0, which adds exact
+// zeros and leaves the column-order sum unchanged.
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const v4f global_float4;
 typedef __attribute__((address_space(3))) const v4f lds_float4;
+typedef __attribute__((address_space(3))) const double lds_double;
+typedef __attribute__((address_space(3))) const float lds_float;
 
 template <int U, typename V4>
 __device__ __forceinline__ void chunk_rows4(V4 *G4, int row0, int ld, const double *x, int ja,
                                             int jb, int r4, double &s0, double &s1, double &s2,
                                             double &s3)
 {
-    const int q = ld >> 2;
-    for (int j = ja; j < jb; j += U) {
+    lds_double *X = (lds_double *)x;
+    const int64_t q = ld >> 2;
+    V4 *p = G4 + (ja - row0) * q + r4;
+    int j = ja;
+    for (; j + U <= jb; j += U, p += U * q) {
         v4f g[U];
         double xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int jj = min(j + u, jb - 1);
-            g[u] = G4[(int64_t)(jj - row0) * q + r4];
-        }
+        for (int u = 0; u < U; ++u) g[u] = p[u * q];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = (j + u < jb) ? x[j + u] : 0.0;
+        for (int u = 0; u < U; ++u) xv[u] = X[j + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s0 = fma((double)g[u].x, xv[u], s0);
+            s1 = fma((double)g[u].y, xv[u], s1);
+            s2 = fma((double)g[u].z, xv[u], s2);
+            s3 = fma((double)g[u].w, xv[u], s3);
+        }
+    }
+    if (j < jb) {
+        const int last = jb - 1 - j;
+        v4f g[U];
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) g[u] = p[min(u, last) * q];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double xx = X[j + min(u, last)];
+            xv[u] = u <= last ? xx : 0.0;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             s0 = fma((double)g[u].x, xv[u], s0);
@@ -106,6 +127,55 @@ __device__ __forceinline__ void stage_partials(const float *G, const float *GB, 
     }
 }
 
+// One stage's chunk partials when the whole instance is in LDS: a thread
+// takes one (chunk, postsynaptic row) pair at a time and sums that row over
+// the chunk's columns -- the same column-order fma sequence (batches of U
+// with clamped extra columns adding exact zeros) as the four-row form above,
+// spread over rows x chunks threads instead of rows / 4 x chunks, so the
+// sequential chain per stage is one chunk of one row.
+template <int U>
+__device__ __forceinline__ void stage_partials_lds(const float *gl, int ld, const double *xf,
+                                                   const double *xb, double *part,
+                                                   const Chunks &ch, int n, int n_pn, int tid,
+                                                   int nthreads)
+{
+    const int nch = ch.na + ch.ng + ch.nb;
+    for (int t = tid; t < nch * n; t += nthreads) {
+        const int c = t / n, i = t - c * n;
+        int mat, j0, j1;
+        chunk_range(ch, n, n_pn, c, mat, j0, j1);
+        lds_float *M = (lds_float *)(gl + (int64_t)c * CW * ld + i);
+        lds_double *X = (lds_double *)(mat ? xb : xf);
+        double s = 0.0;
+        int j = j0;
+        for (; j + U <= j1; j += U, M += U * ld) {
+            float g[U];
+            double xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) g[u] = M[u * ld];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = X[j + u];
+#pragma unroll
+            for (int u = 0; u < U; ++u) s = fma((double)g[u], xv[u], s);
+        }
+        if (j < j1) {
+            const int last = j1 - 1 - j;
+            float g[U];
+            double xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) g[u] = M[min(u, last) * ld];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double xx = X[j + min(u, last)];
+                xv[u] = u <= last ? xx : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) s = fma((double)g[u], xv[u], s);
+        }
+        part[(size_t)c * ld + i] = s;
+    }
+}
+
 // Injected current (nA) of one neuron at global step g: constant part plus
 // the pulses p0 .. p1-1 that are on (zero-order hold over the step).
 __device__ __forceinline__ double stim_nA(const StimDev &s, double Ic, int32_t p0, int32_t p1,
@@ -115,6 +185,24 @@ __device__ __forceinline__ double stim_nA(const StimDev &s, double Ic, int32_t p
     for (int p = p0; p < p1; ++p)
         if (s.on_step[p] <= g && g < s.off_step[p]) I += (double)s.amp[p];
     return I;
+}
+
+// Sum of the chunk partials c0 .. c1-1 of one row (stride ld), added in
+// chunk order starting from 0; loads go four at a time.
+__device__ __forceinline__ double chunk_total(lds_double *P, int ld, int c0, int c1)
+{
+    double t = 0.0;
+    int c = c0;
+    for (; c + 4 <= c1; c += 4) {
+        const double p0 = P[(c + 0) * ld], p1 = P[(c + 1) * ld];
+        const double p2 = P[(c + 2) * ld], p3 = P[(c + 3) * ld];
+        t += p0;
+        t += p1;
+        t += p2;
+        t += p3;
+    }
+    for (; c < c1; ++c) t += P[c * ld];
+    return t;
 }
 
 // Per-workgroup view of one instance for the synaptic sums.
@@ -145,7 +233,9 @@ __device__ __forceinline__ void syn_sums(const WGSyn &w, const Kin &K, const dou
         }
     }
     __syncthreads();
-    if (w.cg < w.NCG)
+    if (w.R == CW)
+        stage_partials_lds<8>(w.gl, w.ld, w.xf, w.xb, w.part, w.ch, w.n, w.n_pn, tid, BS);
+    else if (w.cg < w.NCG)
         stage_partials(w.gt, w.gtb, w.gl, w.R, w.ld, w.xf, w.xb, w.part, w.ch, w.n, w.n_pn, w.cg,
                        w.NCG, w.r4);
     __syncthreads();
@@ -153,13 +243,10 @@ __device__ __forceinline__ void syn_sums(const WGSyn &w, const Kin &K, const dou
     for (int k = 0; k < NPT; ++k) {
         const int i = tid + k * BS;
         const int ir = i < w.n ? i : 0;
-        double a = 0.0, g = 0.0, b = 0.0;
-        for (int c = 0; c < w.ch.na; ++c) a += w.part[(size_t)c * w.ld + ir];
-        for (int c = w.ch.na; c < w.ch.na + w.ch.ng; ++c) g += w.part[(size_t)c * w.ld + ir];
-        for (int c = w.ch.na + w.ch.ng; c < w.nch; ++c) b += w.part[(size_t)c * w.ld + ir];
-        sa[k] = a;
-        sg[k] = g;
-        sb[k] = b;
+        lds_double *P = (lds_double *)w.part + ir;
+        sa[k] = chunk_total(P, w.ld, 0, w.ch.na);
+        sg[k] = chunk_total(P, w.ld, w.ch.na, w.ch.na + w.ch.ng);
+        sb[k] = chunk_total(P, w.ld, w.ch.na + w.ch.ng, w.nch);
     }
 }
 

@@ -125,6 +125,26 @@ def test_batch_equals_plain_and_is_order_invariant_bitwise():
         np.testing.assert_array_equal(a["v"][:, a0:a1], c["v"][:, c0:c1])
 
 
+def test_lds_resident_equals_streamed_bitwise(monkeypatch):
+    # small instances keep their whole conductance matrix in LDS and form
+    # the chunk partials one row per thread; with PSST_LDS_G=0 every matrix
+    # streams from global memory through the four-rows-per-thread form.  The
+    # summation order is the same, so the trajectories agree bit for bit
+    # (the slow-GABA network covers the second matrix).
+    ids = _c3_sample(8)
+    insts = [W.config3_instance(b) for b in ids] + [W.config2(0, t_ms=10.0)]
+    _say("sizes", [i.net.n for i in insts])
+    for batched in (True, False):
+        monkeypatch.delenv("PSST_LDS_G", raising=False)
+        a = R.gpu_run(insts, 300, rec_stride=1, spike_cap=8, batched=batched)
+        monkeypatch.setenv("PSST_LDS_G", "0")
+        b = R.gpu_run(insts, 300, rec_stride=1, spike_cap=8, batched=batched)
+        np.testing.assert_array_equal(a["state"], b["state"])
+        np.testing.assert_array_equal(a["v"], b["v"])
+        np.testing.assert_array_equal(a["spike_t"], b["spike_t"])
+    monkeypatch.delenv("PSST_LDS_G", raising=False)
+
+
 def test_config3_sampled_parity():
     ids = _c3_sample(12)
     insts = [W.config3_instance(b) for b in ids]
