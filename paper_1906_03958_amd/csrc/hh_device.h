@@ -77,35 +77,63 @@ __device__ inline Prm load_prm(const float *p, int ld, int i)
     return q;
 }
 
-// u / (1 - exp(-u)), extended by continuity (value 1) at u = 0.
-__device__ inline double exprel(double u)
+// u / (1 - exp(-u)) from u and emu = exp(-u), extended by continuity
+// (value 1) at u = 0; near 0 the series 1 + u/2 + u^2/12 - u^4/720 +
+// u^6/30240 (Bernoulli numbers) replaces the cancelling quotient.
+__device__ inline double exprel_from(double u, double emu)
 {
-    if (fabs(u) < 1e-6) return 1.0 + u * 0.5 + u * u * (1.0 / 12.0);
-    return u / (-expm1(-u));
+    if (fabs(u) < 5e-2)
+        return 1.0 + u * (0.5 + u * ((1.0 / 12.0) +
+                                     u * u * ((-1.0 / 720.0) + u * u * (1.0 / 30240.0))));
+    return u / (1.0 - emu);
 }
 
-__device__ inline double exprel_d(double u)
+// d/du of exprel, from u and exp(-u); series 1/2 + u/6 - u^3/180 + u^5/5040
+// near 0.
+__device__ inline double exprel_d_from(double u, double emu)
 {
-    if (fabs(u) < 1e-4) return 0.5 + u * (1.0 / 6.0) - u * u * u * (1.0 / 180.0);
-    double e = exp(-u);
-    double d = -expm1(-u);
-    return (d - u * e) / (d * d);
+    if (fabs(u) < 5e-2)
+        return 0.5 + u * ((1.0 / 6.0) + u * u * ((-1.0 / 180.0) + u * u * (1.0 / 5040.0)));
+    const double d = 1.0 - emu;
+    return (d - u * emu) / (d * d);
 }
 
 struct Rates {
     double am, bm, ah, bh, an, bn;
+    double um, em, un, en;   // argument u and exp(-u) of the two exprel terms
 };
 
-// Hodgkin & Huxley 1952 rate functions, -65 mV convention, ms^-1.
+// Hodgkin & Huxley 1952 rate functions, -65 mV convention, ms^-1.  With
+// z = V + 65, every exponential of V in them is a power of E = exp(-z/720):
+// exp(-z/80) = E^9, exp(-z/40) = E^18, exp(-z/20) = E^36, exp(-z/18) = E^40,
+// exp(-z/10) = E^72, and exp(-(V+40)/10), exp(-(V+55)/10), exp(-(V+35)/10)
+// are exp(-z/10) times e^2.5, e, e^3.  One exponential and eight products
+// replace seven exponentials; the powers carry a relative error of a few
+// tens of ulp (about 1e-14).
 __device__ inline Rates hh_rates(double V)
 {
+    constexpr double kE1 = 2.718281828459045;      // e
+    constexpr double kE25 = 12.182493960703473;    // e^2.5
+    constexpr double kE3 = 20.085536923187668;     // e^3
+    const double z = V + 65.0;
+    const double e1 = exp(z * (-1.0 / 720.0));
+    const double e2 = e1 * e1, e4 = e2 * e2, e8 = e4 * e4;
+    const double e80 = e8 * e1;        // exp(-z / 80)
+    const double e40 = e80 * e80;      // exp(-z / 40)
+    const double e20 = e40 * e40;      // exp(-z / 20)
+    const double e18 = e20 * e4;       // exp(-z / 18)
+    const double e10 = e20 * e20;      // exp(-z / 10)
     Rates r;
-    r.am = exprel((V + 40.0) * 0.1);
-    r.bm = 4.0 * exp(-(V + 65.0) * (1.0 / 18.0));
-    r.ah = 0.07 * exp(-(V + 65.0) * 0.05);
-    r.bh = 1.0 / (1.0 + exp(-(V + 35.0) * 0.1));
-    r.an = 0.1 * exprel((V + 55.0) * 0.1);
-    r.bn = 0.125 * exp(-(V + 65.0) * 0.0125);
+    r.um = (V + 40.0) * 0.1;
+    r.em = e10 * kE25;
+    r.un = (V + 55.0) * 0.1;
+    r.en = e10 * kE1;
+    r.am = exprel_from(r.um, r.em);
+    r.bm = 4.0 * e18;
+    r.ah = 0.07 * e20;
+    r.bh = 1.0 / (1.0 + e10 * kE3);
+    r.an = 0.1 * exprel_from(r.un, r.en);
+    r.bn = 0.125 * e80;
     return r;
 }
 
@@ -179,11 +207,11 @@ __device__ inline void hh_vjp(const double Y[NVAR], const Prm &P, const Kin &K, 
     const double V = Y[YV], m = Y[YM], h = Y[YH], n = Y[YN], s = Y[YS];
     const Rates r = hh_rates(V);
     // derivatives of the rates in V
-    const double dam = exprel_d((V + 40.0) * 0.1) * 0.1;
+    const double dam = exprel_d_from(r.um, r.em) * 0.1;
     const double dbm = -r.bm * (1.0 / 18.0);
     const double dah = -r.ah * 0.05;
     const double dbh = r.bh * (1.0 - r.bh) * 0.1;
-    const double dan = 0.1 * exprel_d((V + 55.0) * 0.1) * 0.1;
+    const double dan = 0.1 * exprel_d_from(r.un, r.en) * 0.1;
     const double dbn = -r.bn * 0.0125;
     const double invC = 1.0 / P.C;
     const double m2h = m * m * h, m3 = m * m * m, n3 = n * n * n;
