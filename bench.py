@@ -99,6 +99,36 @@ def write_traffic(args):
     print(json.dumps(out))
 
 
+def write_flops(args):
+    """Per-launch float64 VALU flops of a kernel from rocprofv3 counters
+    SQ_INSTS_VALU_FLOPS_FP64 and SQ_INSTS_VALU_FLOPS_FP64_TRANS (one run, both
+    counters); only the longest dispatches are used."""
+    kernel, csv_path = args.write_flops
+    per = {}
+    for c in ("SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP64_TRANS"):
+        rows = _counter_rows(csv_path, kernel, c)
+        longest = max(d for d, _ in rows)
+        per[c] = float(np.mean([v for d, v in rows if d > 0.5 * longest]))
+    out = {"kernel": kernel, "kernel_source_sha": kernel_sha(kernel),
+           "workload": args.workload, "chunk": args.chunk, "instances": args.instances,
+           "fp64_flops_per_launch": sum(per.values()), "counters": per}
+    with open(os.path.join(ROOT, "profiles", f"{kernel}_{args.workload}_flops.txt"), "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out))
+
+
+def read_flops(kernel, args):
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{args.workload}_flops.txt")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernel_source_sha") != kernel_sha(kernel) or \
+            (t.get("chunk"), t.get("instances")) != (args.chunk, args.instances):
+        return None
+    return t.get("fp64_flops_per_launch")
+
+
 def read_traffic(kernel, args):
     """HBM bytes per launch measured for this kernel source and workload, or
     None when no such measurement is on file."""
@@ -117,6 +147,7 @@ def read_traffic(kernel, args):
 
 
 MFMA_FP32_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
 def bench_large(args, torch, psst, W, dev, stream):
@@ -271,9 +302,15 @@ def main():
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter files of a "
                          "bench run (same --workload/--chunk/--instances) and of a "
                          "--copy-calibration run into profiles/KERNEL_traffic.txt and exit")
-    ap.add_argument("--workload", choices=("batched", "large"), default="batched",
+    ap.add_argument("--workload", choices=("batched", "large", "uncoupled"), default="batched",
                     help="batched: the 4096-network batch (the default line); large: the "
-                         "16384-neuron network x 64 trials on the per-stage MFMA path")
+                         "16384-neuron network x 64 trials on the per-stage MFMA path; "
+                         "uncoupled: the batch with every synapse removed (compute only)")
+    ap.add_argument("--write-flops", nargs=2, metavar=("KERNEL", "CSV"),
+                    help="turn a rocprofv3 --pmc SQ_INSTS_VALU_FLOPS_FP64 "
+                         "SQ_INSTS_VALU_FLOPS_FP64_TRANS counter file of a bench run (same "
+                         "--workload/--chunk/--instances) into "
+                         "profiles/KERNEL_WORKLOAD_flops.txt and exit")
     ap.add_argument("--adjoint-trials", type=int, default=256)
     ap.add_argument("--adjoint-steps", type=int, default=20000)
     ap.add_argument("--adjoint-K", type=int, default=100)
@@ -284,6 +321,9 @@ def main():
 
     if args.write_traffic:
         write_traffic(args)
+        return
+    if args.write_flops:
+        write_flops(args)
         return
 
     if args.gpus != 1:
@@ -315,8 +355,9 @@ def main():
         return
 
     # ---------------- workload: batched config -----------------------------
+    uncoupled = args.workload == "uncoupled"
     t0 = time.time()
-    insts = W.config3(args.instances)
+    insts = W.config3_uncoupled(args.instances) if uncoupled else W.config3(args.instances)
     sizes = np.array([i.net.n for i in insts])
     sum_n = int(sizes.sum())
     sum_n2 = int((sizes.astype(np.int64) ** 2).sum())
@@ -377,10 +418,24 @@ def main():
                 "kernel": "rk4_wg_kernel (batched persistent RK4)",
                 "avg_launch_ms": round(1e3 * avg_launch_s, 3),
                 "algorithmic_bytes_per_launch": bytes_per_launch}
+    if uncoupled:
+        # no conductances: the float64 right-hand side is the work; flops per
+        # launch come from the float64 VALU flop counters of this kernel
+        fl = read_flops("rk4_wg_kernel", args)
+        tf = fl / avg_launch_s / 1e12 if fl else None
+        roofline = {"bound": "alu", "achieved": round(tf, 3) if tf else None,
+                    "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 4) if tf else None,
+                    "traffic": None, "kernel": "rk4_wg_kernel (batched persistent RK4)",
+                    "avg_launch_ms": round(1e3 * avg_launch_s, 3),
+                    "fp64_flops_per_launch": fl,
+                    "note": "peak: float64 vector rate of the chip (256 CUs x 128 flop/clk "
+                            "x 2.4 GHz); flops per launch from SQ_INSTS_VALU_FLOPS_FP64 "
+                            "(+_TRANS), null until measured for this kernel source"}
 
     # ---------------- plain form: one network per launch ------------------
     plain = None
-    if not args.no_plain:
+    if not args.no_plain and not uncoupled:
         pick = stratified(sizes, min(args.plain_instances, len(insts)))
         tot_ns, tot_t = 0, 0.0
         for b in pick:
@@ -401,7 +456,8 @@ def main():
                            "steps each, one psst_integrate launch per network"}
         log(f"plain: {plain['value']:.3e} neuron-steps/s")
 
-    adjoint = None if args.no_adjoint else bench_adjoint(args, torch, psst, W, dev, stream)
+    adjoint = None if (args.no_adjoint or uncoupled) else \
+        bench_adjoint(args, torch, psst, W, dev, stream)
 
     # ---------------- CPU baseline (oracle) and parity spot check ---------
     cpu = None
@@ -418,7 +474,26 @@ def main():
         cpu = {"value": ns / ct, "unit": "neuron-steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{len(sub)} instances stratified by size, {args.cpu_steps} RK4 steps "
                          f"each ({ct:.1f} s wall on {threads} threads)"}
-        log(f"cpu oracle: {cpu['value']:.3e} neuron-steps/s on {threads} threads")
+        # one thread on a smaller sample, and the host it ran on
+        sub1 = sub[::8]
+        steps1 = max(args.cpu_steps // 2, 1)
+        t0 = time.perf_counter()
+        oracle.run_many(sub1, steps1, dt=DT, rec_stride=0, threads=1)
+        ct1 = time.perf_counter() - t0
+        cpu["value_1thread"] = sum(i.net.n for i in sub1) * steps1 / ct1
+        cpu["sample_1thread"] = f"{len(sub1)} of those instances, {steps1} RK4 steps, 1 thread"
+        model = ""
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        cpu["host"] = {"cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+                       "model": model}
+        log(f"cpu oracle: {cpu['value']:.3e} neuron-steps/s on {threads} threads, "
+            f"{cpu['value_1thread']:.3e} on 1 thread")
         # same instances from their initial state on the GPU, V every 10 steps
         states2 = torch.zeros_like(states)
         psst.batch_state_init(batch, v0, states2)
@@ -451,10 +526,13 @@ def main():
         "dtype": "f64",
         "storage": "f32 (state as value+compensation pairs; conductances as given)",
         "data": "synthetic",
-        "config": {"workload": f"batched: {len(insts)} independent antennal-lobe-shaped HH "
-                               "networks, 60-480 neurons (PN:LN 3:1), Bernoulli(0.5) ACh + "
-                               "fast-GABA synapses, g ~ U(0,0.5) nS x LogNormal(0,0.1), "
-                               "I ~ U(0,2) nA, dt 0.01 ms",
+        "config": {"workload": (f"uncoupled: {len(insts)} batched instances of 60-480 HH "
+                                "neurons with no synapses, I ~ U(0,2) nA, dt 0.01 ms")
+                   if uncoupled else
+                   (f"batched: {len(insts)} independent antennal-lobe-shaped HH "
+                    "networks, 60-480 neurons (PN:LN 3:1), Bernoulli(0.5) ACh + "
+                    "fast-GABA synapses, g ~ U(0,0.5) nS x LogNormal(0,0.1), "
+                    "I ~ U(0,2) nA, dt 0.01 ms"),
                    "instances": len(insts), "neurons": sum_n, "rk4_steps_per_step": args.chunk,
                    "dt_ms": DT, "recording": f"spikes + V every {REC_STRIDE} steps",
                    "launch": psst.batch_describe(batch)},

@@ -125,7 +125,8 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
     // else a staging area for one step's stage data [40][ld]; then the
     // forward view with as many conductance columns as remain.
     const bool gb_net = (d.flags & DESC_GABAB) != 0;
-    const int rows = n + (gb_net ? n_ln : 0);
+    // presynaptic rows of the conductance matrices (none without synapses)
+    const int rows = (d.flags & DESC_NOSYN) ? 0 : n + (gb_net ? n_ln : 0);
     const Chunks ch0 = chunks_of(n, n_pn, gb_net);
     const int64_t fwd_min = (int64_t)sizeof(double) * (2 + ch0.na + ch0.ng + ch0.nb) * ld;
     const int64_t lacc_bytes = (int64_t)sizeof(double) * (5 + 20) * ld +
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
                     tb[(slow ? ld : 0) + jr] = acc;
                 }
                 __syncthreads();
-                if (own) {
+                if (own && rows > 0) {
                     u[YS] += tb[i];
                     if (gabab && is_ln) u[YG] += tb[ld + (i - n_pn)] * gabab_act_d(Yq[YG], K);
                 }

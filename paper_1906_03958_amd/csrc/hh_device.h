@@ -36,7 +36,9 @@ struct InstDesc {
     int64_t grad_entries;     // entries of one copy of the pathway blocks
 };
 
-enum { DESC_GABAB = 1 };
+// flags: bit 0 the network has slow GABA; bit 1 it has no synapses at all
+// (the synaptic products are skipped, every synaptic sum is 0)
+enum { DESC_GABAB = 1, DESC_NOSYN = 2 };
 
 // Synapse kinetics widened to float64.
 struct Kin {

@@ -263,7 +263,7 @@ extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t 
     d.n = n;
     d.n_pn = p->n_pn;
     d.ld = ld;
-    d.flags = net->gabab ? DESC_GABAB : 0;
+    d.flags = (net->gabab ? DESC_GABAB : 0) | (np == 0 ? DESC_NOSYN : 0);
     d.cg = net->cg;
     d.ci = net->ci;
     NETCHK(hipMalloc(&net->d_desc, sizeof(InstDesc)));
@@ -649,7 +649,11 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
         g.max_ld = std::max(g.max_ld, q->ld);
         need = std::max(need, wg_lds_bytes(false, q->ld, q->nch, 0));
     }
-    g.lds = allow_lds ? lmax : need;
+    // networks without synapses need no LDS beyond the small buffers, so
+    // several workgroups share a CU
+    bool any_syn = false;
+    for (int32_t k : idx) any_syn |= nets[k]->desc.n_paths > 0;
+    g.lds = (allow_lds && any_syn) ? lmax : need;
     default_shape(g.max_n, &g.bs, &g.npt);
     // PSST_WG_SHAPE="<threads>x<neurons per thread>" fixes the launch shape
     // (and skips tuning) when that variant can take every instance.

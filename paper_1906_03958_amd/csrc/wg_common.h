@@ -224,6 +224,11 @@ __device__ __forceinline__ void syn_sums(const WGSyn &w, const Kin &K, const dou
                                          double (&sa)[NPT], double (&sg)[NPT], double (&sb)[NPT])
 {
     const int tid = threadIdx.x;
+    if (w.nch == 0) {      // no synapses (uniform over the workgroup: no barriers)
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) sa[k] = sg[k] = sb[k] = 0.0;
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int i = tid + k * BS;
@@ -332,7 +337,7 @@ __device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int6
     w.n_pn = d.n_pn;
     w.ld = d.ld;
     w.gabab = (d.flags & DESC_GABAB) != 0;
-    w.ch = chunks_of(d.n, d.n_pn, w.gabab);
+    w.ch = (d.flags & DESC_NOSYN) ? Chunks{0, 0, 0} : chunks_of(d.n, d.n_pn, w.gabab);
     w.nch = w.ch.na + w.ch.ng + w.ch.nb;
     w.xf = lds_d;
     w.xb = lds_d + d.ld;
@@ -343,7 +348,7 @@ __device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int6
     w.gtb = d.gtb;
     const int64_t room = lds_bytes - (int64_t)sizeof(double) * (2 + w.nch) * d.ld;
     const int64_t per_col = (int64_t)sizeof(float) * w.nch * d.ld;
-    int64_t R = room > 0 ? room / per_col : 0;
+    int64_t R = per_col == 0 ? CW : (room > 0 ? room / per_col : 0);
     w.R = (int)(R < CW ? R : CW);
     const int tid = threadIdx.x;
     if (w.R > 0) {

@@ -267,6 +267,19 @@ def config3(n_instances: int = 4096, first: int = 0) -> List[Instance]:
     return [config3_instance(b) for b in range(first, first + n_instances)]
 
 
+def config3_uncoupled(n_instances: int = 4096, first: int = 0) -> List[Instance]:
+    """The batched workload with every synapse removed (independent neurons,
+    the compute-only counterpart): instance b keeps its size, neuron
+    parameters, stimulus and V0."""
+    cfg = 3
+    out = []
+    for b in range(first, first + n_instances):
+        n = config3_size(b)
+        net = Network(n, 3 * (n // 4), hh_params(n), [])
+        out.append(Instance(net, _v0(cfg, b, n), _const_stim(cfg, b, n)))
+    return out
+
+
 CONFIG3_INSTANCES = 4096
 CONFIG3_STEPS = 50_000
 
