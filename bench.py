@@ -102,7 +102,9 @@ def write_traffic(args):
 def write_flops(args):
     """Per-launch float64 VALU flops of a kernel from rocprofv3 counters
     SQ_INSTS_VALU_FLOPS_FP64 and SQ_INSTS_VALU_FLOPS_FP64_TRANS (one run, both
-    counters); only the longest dispatches are used."""
+    counters); only the longest dispatches are used.  The counters add the
+    flops of each wavefront instruction once (an fma counts 2), so the lane
+    total is 64 times their sum."""
     kernel, csv_path = args.write_flops
     per = {}
     for c in ("SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP64_TRANS"):
@@ -111,7 +113,8 @@ def write_flops(args):
         per[c] = float(np.mean([v for d, v in rows if d > 0.5 * longest]))
     out = {"kernel": kernel, "kernel_source_sha": kernel_sha(kernel),
            "workload": args.workload, "chunk": args.chunk, "instances": args.instances,
-           "fp64_flops_per_launch": sum(per.values()), "counters": per}
+           "fp64_flops_per_launch": 64.0 * sum(per.values()), "counters": per,
+           "lanes_per_wavefront": 64}
     with open(os.path.join(ROOT, "profiles", f"{kernel}_{args.workload}_flops.txt"), "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
