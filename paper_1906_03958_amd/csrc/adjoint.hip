@@ -88,8 +88,6 @@ __device__ inline void comp_add(float *hi, float *lo, double v)
     *lo = l;
 }
 
-// sum_i row[i] q[i] over i < n in index order; row holds ld >= n floats
-// (zero padded to a multiple of 4)
 // sum_i row[i] q[i] over i < n: four interleaved partial sums (i mod 4),
 // each in index order, added as (s0 + s1) + (s2 + s3); row holds ld >= n
 // floats, zero padded, and q is finite up to ld.
@@ -108,6 +106,35 @@ __device__ __forceinline__ double row_dot(V4 *row, const double *q, int n)
         s3 = fma((double)g.w, q[i0 + 3], s3);
     }
     return (s0 + s1) + (s2 + s3);
+}
+
+// One residue class of row_dot, for four lanes sharing a row: lane k of the
+// group sums row[i] q[i] over i = k, k + 4, ... below 4 ceil(n / 4) in index
+// order; the group then forms (s0 + s1) + (s2 + s3), so the result equals
+// row_dot's bit for bit.  Every lane of the wavefront must call (shuffles).
+template <typename F>
+__device__ __forceinline__ double row_dot_quad(F *row, const double *q, int n, int k, bool on)
+{
+    typedef __attribute__((address_space(3))) const double lds_dbl;
+    lds_dbl *Q = (lds_dbl *)q;
+    double s = 0.0;
+    if (on) {
+        const int n4 = (n + 3) >> 2;
+        int m = 0;
+        for (; m + 8 <= n4; m += 8) {
+            float g[8];
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) g[u] = row[4 * (m + u) + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = Q[4 * (m + u) + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s = fma((double)g[u], x[u], s);
+        }
+        for (; m < n4; ++m) s = fma((double)row[4 * m + k], Q[4 * m + k], s);
+    }
+    const double p = s + __shfl_xor(s, 1);       // s0 + s1 on lanes 0, 1; s2 + s3 on 2, 3
+    return p + __shfl_xor(p, 2);
 }
 
 template <int BS>
@@ -258,19 +285,23 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
                     }
                 }
                 __syncthreads();
-                // presynaptic terms: t_j = sum_i g_ij q_type(j)(i), one thread per
+                // presynaptic terms: t_j = sum_i g_ij q_type(j)(i), four lanes per
                 // presynaptic row j (row j of the transposed matrix is contiguous)
-                for (int r = tid; r < rows; r += BS) {
-                    const bool slow = r >= n;
-                    const int jr = slow ? r - n : r;
+                for (int r0 = 0; r0 < rows; r0 += BS / 4) {
+                    const int r = r0 + (tid >> 2);
+                    const bool on = r < rows;
+                    const int rr = on ? r : 0;
+                    const bool slow = rr >= n;
+                    const int jr = slow ? rr - n : rr;
                     const double *qv = qv0 + (slow ? 2 : (jr < n_pn ? 0 : 1)) * ld;
-                    double acc = 0.0;
+                    double acc;
                     if (w.R >= CW)
-                        acc = row_dot((lds_float4 *)lds_row(w, slow ? 1 : 0, jr), qv, n);
+                        acc = row_dot_quad((lds_float *)lds_row(w, slow ? 1 : 0, jr), qv, n,
+                                           tid & 3, on);
                     else
-                        acc = row_dot((global_float4 *)((slow ? d.gtb : d.gt) + (int64_t)jr * ld),
-                                      qv, n);
-                    tb[(slow ? ld : 0) + jr] = acc;
+                        acc = row_dot_quad((global_float *)((slow ? d.gtb : d.gt) + (int64_t)jr * ld),
+                                           qv, n, tid & 3, on);
+                    if (on && (tid & 3) == 0) tb[(slow ? ld : 0) + jr] = acc;
                 }
                 __syncthreads();
                 if (own && rows > 0) {

@@ -40,6 +40,7 @@ typedef __attribute__((address_space(1))) const v4f global_float4;
 typedef __attribute__((address_space(3))) const v4f lds_float4;
 typedef __attribute__((address_space(3))) const double lds_double;
 typedef __attribute__((address_space(3))) const float lds_float;
+typedef __attribute__((address_space(1))) const float global_float;
 
 template <int U, typename V4>
 __device__ __forceinline__ void chunk_rows4(V4 *G4, int row0, int ld, const double *x, int ja,
