@@ -86,6 +86,12 @@ def lib():
         L.or_adjoint.argtypes = [C.POINTER(_Net), dp, C.POINTER(_Stim), C.c_double,
                                  C.c_int64, C.c_int64, dp, dp, dp, dp, dp, dp]
         L.or_step_vjp.argtypes = [C.POINTER(_Net), dp, dp, C.c_double, dp, dp]
+        L.or_integrate_tab.argtypes = [C.POINTER(_Net), dp, C.POINTER(_Stim), C.c_double,
+                                       C.c_int64, C.c_int64, C.c_int64, C.c_int64, dp,
+                                       C.c_int32, C.POINTER(C.c_int32), dp, C.c_int32, dp, dp]
+        L.or_adjoint_tab.argtypes = [C.POINTER(_Net), dp, C.POINTER(_Stim), C.c_double,
+                                     C.c_int64, C.c_int64, dp, dp, dp, dp, dp, dp,
+                                     C.c_int32, dp, dp]
         _lib = L
     return _lib
 
@@ -193,9 +199,22 @@ def rhs(net, y, i_nA) -> np.ndarray:
     return f
 
 
+def _tableau(tab):
+    """(stages, a[4][4] row-major, b[4]) as float64 arrays from a tableau
+    given as dict(a=[[...]], b=[...]) (explicit: a strictly lower triangular)."""
+    b = np.asarray(tab["b"], np.float64)
+    s = len(b)
+    a = np.zeros((4, 4))
+    a[:s, :s] = np.asarray(tab["a"], np.float64).reshape(s, s)
+    bb = np.zeros(4)
+    bb[:s] = b
+    return s, np.ascontiguousarray(a.ravel()), bb
+
+
 def integrate(net, y, stim, dt, n_steps, step0=0, rec_stride=1, rec_cap=None,
-              spike_cap=0, euler=False):
-    """Advance state y ([7, n] float64, modified in place) by n_steps.
+              spike_cap=0, euler=False, tableau=None):
+    """Advance state y ([7, n] float64, modified in place) by n_steps of RK4
+    (or forward Euler, or the explicit method `tableau` = dict(a, b)).
 
     Returns dict(v=[rows, n] recorded potentials after each stride-th global
     step, spike_count=[n], spike_t=[n, spike_cap] in ms).
@@ -208,7 +227,16 @@ def integrate(net, y, stim, dt, n_steps, step0=0, rec_stride=1, rec_cap=None,
     v = np.zeros((max(rec_cap, 1), on.n))
     cnt = np.zeros(on.n, np.int32)
     spk = np.zeros((on.n, max(spike_cap, 1)))
-    if euler:
+    if tableau is not None:
+        s, a, b = _tableau(tableau)
+        rc = lib().or_integrate_tab(C.byref(on.c), _dptr(y), C.byref(st.c), float(dt),
+                                    int(n_steps), int(step0), int(rec_stride), int(rec_cap),
+                                    _dptr(v), int(spike_cap),
+                                    cnt.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(spk),
+                                    int(s), _dptr(a), _dptr(b))
+        if rc != 0:
+            raise ValueError("tableau needs 1 to 4 stages")
+    elif euler:
         lib().or_integrate_euler(C.byref(on.c), _dptr(y), C.byref(st.c), float(dt),
                                  int(n_steps), int(step0), int(rec_stride), int(rec_cap),
                                  _dptr(v))
@@ -232,16 +260,16 @@ def integrate_persyn(net, y, stim, dt, n_steps, step0=0):
     return v
 
 
-def run(inst, n_steps, dt=0.01, rec_stride=1, spike_cap=0, step0=0):
+def run(inst, n_steps, dt=0.01, rec_stride=1, spike_cap=0, step0=0, tableau=None):
     """Initial state from inst.v0, then integrate; returns (result, final y)."""
     on = OracleNet(inst.net)
     y = init_state(on, inst.v0)
     res = integrate(on, y, inst.stim, dt, n_steps, step0, rec_stride,
-                    spike_cap=spike_cap)
+                    spike_cap=spike_cap, tableau=tableau)
     return res, y
 
 
-def adjoint(net, y0, stim, dt, n_steps, dLdV, step0=0):
+def adjoint(net, y0, stim, dt, n_steps, dLdV, step0=0, tableau=None):
     """Discrete adjoint of the RK4 map.  dLdV: [n_steps, n] (dL/dV after each
     step).  Returns dict(g=[packed pathway blocks, nS], g_Na, g_K, g_L [n],
     lambda0 [7, n])."""
@@ -253,9 +281,15 @@ def adjoint(net, y0, stim, dt, n_steps, dLdV, step0=0):
     gg = np.zeros(max(on.g.size, 1))
     gna, gk, gl = np.zeros(on.n), np.zeros(on.n), np.zeros(on.n)
     lam = np.zeros((NVAR, on.n))
-    lib().or_adjoint(C.byref(on.c), _dptr(y0), C.byref(st.c), float(dt), int(n_steps),
-                     int(step0), _dptr(d), _dptr(gg), _dptr(gna), _dptr(gk), _dptr(gl),
-                     _dptr(lam))
+    if tableau is None:
+        lib().or_adjoint(C.byref(on.c), _dptr(y0), C.byref(st.c), float(dt), int(n_steps),
+                         int(step0), _dptr(d), _dptr(gg), _dptr(gna), _dptr(gk), _dptr(gl),
+                         _dptr(lam))
+    else:
+        s, a, b = _tableau(tableau)
+        lib().or_adjoint_tab(C.byref(on.c), _dptr(y0), C.byref(st.c), float(dt),
+                             int(n_steps), int(step0), _dptr(d), _dptr(gg), _dptr(gna),
+                             _dptr(gk), _dptr(gl), _dptr(lam), int(s), _dptr(a), _dptr(b))
     # only existing synapses are parameters: zero where the mask is 0
     g = np.where(on.mask[:on.g.size] != 0, gg[:on.g.size], 0.0)
     return dict(g=g, g_Na=gna, g_K=gk, g_L=gl, lambda0=lam)
@@ -271,12 +305,13 @@ def step_vjp(net, yn, i_nA, dt, lam):
     return out
 
 
-def run_many(insts, n_steps, dt=0.01, rec_stride=0, spike_cap=0, threads=None):
+def run_many(insts, n_steps, dt=0.01, rec_stride=0, spike_cap=0, threads=None, tableau=None):
     """Independent instances in parallel threads (ctypes releases the GIL)."""
     threads = threads or os.cpu_count() or 1
 
     def one(inst):
-        return run(inst, n_steps, dt, rec_stride=rec_stride, spike_cap=spike_cap)
+        return run(inst, n_steps, dt, rec_stride=rec_stride, spike_cap=spike_cap,
+                   tableau=tableau)
 
     with ThreadPoolExecutor(max_workers=threads) as ex:
         return list(ex.map(one, insts))

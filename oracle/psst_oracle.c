@@ -356,6 +356,26 @@ int or_integrate(const or_net *net, double *y, const or_stim *st, double dt,
                          rec_cap, v_out, spike_cap, spike_count, spike_t);
 }
 
+/* Any explicit tableau of up to 4 stages: a is 4 x 4 row-major (only
+ * a[s][q], q < s, is read), b has 4 entries. */
+int or_integrate_tab(const or_net *net, double *y, const or_stim *st, double dt,
+                     int64_t n_steps, int64_t step0, int64_t rec_stride,
+                     int64_t rec_cap, double *v_out, int32_t spike_cap,
+                     int32_t *spike_count, double *spike_t, int32_t stages,
+                     const double *a, const double *b)
+{
+    tableau tb;
+    memset(&tb, 0, sizeof tb);
+    if (stages < 1 || stages > 4) return -1;
+    tb.stages = stages;
+    for (int i = 0; i < stages; ++i) {
+        for (int q = 0; q < i; ++q) tb.a[i][q] = a[4 * i + q];
+        tb.b[i] = b[i];
+    }
+    return integrate_tab(net, &tb, y, st, dt, n_steps, step0, rec_stride,
+                         rec_cap, v_out, spike_cap, spike_count, spike_t);
+}
+
 int or_integrate_euler(const or_net *net, double *y, const or_stim *st,
                        double dt, int64_t n_steps, int64_t step0,
                        int64_t rec_stride, int64_t rec_cap, double *v_out)
@@ -583,6 +603,80 @@ int or_adjoint(const or_net *net, const double *y0, const or_stim *st,
         }
         for (int64_t w = 0; w < W; ++w)
             lam[w] += u[w] + u[W + w] + u[2 * W + w] + u[3 * W + w];
+    }
+    if (lambda0) memcpy(lambda0, lam, sizeof(double) * W);
+    free(traj); free(work); free(I); free(y); free(lam); free(Ys); free(k);
+    free(kb); free(u);
+    return 0;
+}
+
+/*
+ * Discrete adjoint of any explicit tableau (up to 4 stages).  Stage inputs
+ * Y_s = y + dt sum_{q<s} a_{sq} k_q, k_s = f(Y_s), y' = y + dt sum_s b_s k_s.
+ * With lam = dL/dy', going through the stages last to first:
+ *   kbar_s = dt b_s lam + dt sum_{r>s} a_{rs} u_r,   u_s = J(Y_s)^T kbar_s,
+ * and dL/dy = lam + sum_s u_s; parameter cotangents collect
+ * (df/dtheta)(Y_s)^T kbar_s.  For RK4 (a_{s,s-1} = c_s only) this is the
+ * recursion of or_adjoint above.
+ */
+int or_adjoint_tab(const or_net *net, const double *y0, const or_stim *st,
+                   double dt, int64_t n_steps, int64_t step0, const double *dLdV,
+                   double *grad_g, double *grad_gna, double *grad_gk,
+                   double *grad_gl, double *lambda0, int32_t stages,
+                   const double *a, const double *b)
+{
+    if (stages < 1 || stages > 4) return -1;
+    tableau tb;
+    memset(&tb, 0, sizeof tb);
+    tb.stages = stages;
+    for (int i = 0; i < stages; ++i) {
+        for (int q = 0; q < i; ++q) tb.a[i][q] = a[4 * i + q];
+        tb.b[i] = b[i];
+    }
+    int n = net->n;
+    int64_t W = NVAR * (int64_t)n;
+    int64_t ng = path_offset(net, net->n_path);
+    double *traj = (double *)malloc(sizeof(double) * W * (n_steps > 0 ? n_steps : 1));
+    double *work = (double *)malloc(sizeof(double) * 5 * W);
+    double *I = (double *)malloc(sizeof(double) * n);
+    double *y = (double *)malloc(sizeof(double) * W);
+    memcpy(y, y0, sizeof(double) * W);
+    for (int64_t s = 0; s < n_steps; ++s) {
+        memcpy(traj + s * W, y, sizeof(double) * W);
+        for (int i = 0; i < n; ++i) I[i] = stim_nA(st, i, step0 + s);
+        rk_step(net, &tb, y, I, dt, work);
+    }
+    memset(grad_g, 0, sizeof(double) * (ng > 0 ? ng : 1));
+    memset(grad_gna, 0, sizeof(double) * n);
+    memset(grad_gk, 0, sizeof(double) * n);
+    memset(grad_gl, 0, sizeof(double) * n);
+    double *lam = (double *)calloc(W, sizeof(double));
+    double *Ys = (double *)malloc(sizeof(double) * 4 * W);
+    double *k = (double *)malloc(sizeof(double) * 4 * W);
+    double *kb = (double *)malloc(sizeof(double) * W);
+    double *u = (double *)malloc(sizeof(double) * 4 * W);
+    for (int64_t s = n_steps - 1; s >= 0; --s) {
+        for (int i = 0; i < n; ++i) lam[YV * n + i] += dLdV[s * n + i];
+        const double *yn = traj + s * W;
+        for (int i = 0; i < n; ++i) I[i] = stim_nA(st, i, step0 + s);
+        for (int q = 0; q < stages; ++q) {
+            for (int64_t w = 0; w < W; ++w) {
+                double v = yn[w];
+                for (int r = 0; r < q; ++r) v += dt * tb.a[q][r] * k[r * W + w];
+                Ys[q * W + w] = v;
+            }
+            or_rhs(net, Ys + q * W, I, k + q * W);
+        }
+        for (int q = stages - 1; q >= 0; --q) {
+            for (int64_t w = 0; w < W; ++w) {
+                double v = dt * tb.b[q] * lam[w];
+                for (int r = q + 1; r < stages; ++r) v += dt * tb.a[r][q] * u[r * W + w];
+                kb[w] = v;
+            }
+            rhs_vjp(net, Ys + q * W, kb, u + q * W, grad_g, grad_gna, grad_gk, grad_gl);
+        }
+        for (int64_t w = 0; w < W; ++w)
+            for (int q = 0; q < stages; ++q) lam[w] += u[q * W + w];
     }
     if (lambda0) memcpy(lambda0, lam, sizeof(double) * W);
     free(traj); free(work); free(I); free(y); free(lam); free(Ys); free(k);

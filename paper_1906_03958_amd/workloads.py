@@ -280,6 +280,29 @@ def config3_uncoupled(n_instances: int = 4096, first: int = 0) -> List[Instance]
     return out
 
 
+# Butcher tableaux of explicit Runge-Kutta methods (a strictly lower
+# triangular, rows = stages; b = weights) and their classical orders.  Inputs
+# for both the library and the oracle, like the kinetic constants.
+TABLEAUX = {
+    "euler": dict(a=[[0.0]], b=[1.0]),
+    "midpoint": dict(a=[[0.0, 0.0], [0.5, 0.0]], b=[0.0, 1.0]),
+    "heun": dict(a=[[0.0, 0.0], [1.0, 0.0]], b=[0.5, 0.5]),
+    "ralston": dict(a=[[0.0, 0.0], [2.0 / 3.0, 0.0]], b=[0.25, 0.75]),
+    "kutta3": dict(a=[[0.0, 0.0, 0.0], [0.5, 0.0, 0.0], [-1.0, 2.0, 0.0]],
+                   b=[1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0]),
+    "ssprk3": dict(a=[[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.25, 0.25, 0.0]],
+                   b=[1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0]),
+    "rk4": dict(a=[[0.0, 0.0, 0.0, 0.0], [0.5, 0.0, 0.0, 0.0], [0.0, 0.5, 0.0, 0.0],
+                   [0.0, 0.0, 1.0, 0.0]],
+                b=[1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0]),
+    "rk38": dict(a=[[0.0, 0.0, 0.0, 0.0], [1.0 / 3.0, 0.0, 0.0, 0.0],
+                    [-1.0 / 3.0, 1.0, 0.0, 0.0], [1.0, -1.0, 1.0, 0.0]],
+                 b=[0.125, 0.375, 0.375, 0.125]),
+}
+TABLEAU_ORDER = {"euler": 1, "midpoint": 2, "heun": 2, "ralston": 2, "kutta3": 3,
+                 "ssprk3": 3, "rk4": 4, "rk38": 4}
+
+
 CONFIG3_INSTANCES = 4096
 CONFIG3_STEPS = 50_000
 

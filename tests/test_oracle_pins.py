@@ -475,3 +475,99 @@ def test_pathway_block_orientation():
     f = oracle.rhs(oracle.OracleNet(net), y, np.zeros(3))
     assert abs((f[0, 1] - f0[0, 1]) - (-0.125 * 0.5 * (-30.0 - k[2]) * CG)) < 1e-13
     assert abs((f[0, 2] - f0[0, 2]) - (-0.375 * 0.5 * (-10.0 - k[2]) * CG)) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# General explicit tableaux (the RK4 paragraph's step as one member of the
+# explicit Runge-Kutta family): stability polynomials, observed orders, and
+# the tableau adjoint against finite differences.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", sorted(W.TABLEAUX))
+def test_tableau_amplification_passive_membrane(name):
+    # an explicit s-stage method of order s (s <= 4) multiplies y - y_inf by
+    # the degree-s Taylor polynomial of e^z on y' = lam (y - y_inf)
+    tab, p = W.TABLEAUX[name], W.TABLEAU_ORDER[name]
+    g_L, dt, I = 150.0, 0.01, 2.0
+    inst = _passive(g_L=g_L, i_nA=I, v0=-65.0)
+    prm = {k: float(np.float32(v[0])) for k, v in inst.net.params.items()}
+    res, _ = oracle.run(inst, 10, dt=dt, tableau=tab)
+    z = -prm["g_L"] * dt / prm["C_m"]
+    R = sum(z ** k / np.prod(np.arange(1, k + 1)) for k in range(p + 1))
+    vinf = prm["E_L"] + CI * float(np.float32(I)) / prm["g_L"]
+    np.testing.assert_allclose(res["v"][:, 0], vinf + R ** np.arange(1, 11) * (-65.0 - vinf),
+                               rtol=0, atol=1e-12)
+
+
+def test_tableau_observed_orders():
+    # step halving on a repetitively firing neuron against a fine RK4 run
+    inst = W.single_neuron(1.0)
+    T, sample = 20.0, 0.04
+
+    def traj(dt, tab):
+        n = int(round(T / dt))
+        res, _ = oracle.run(inst, n, dt=dt, rec_stride=int(round(sample / dt)), tableau=tab)
+        return res["v"][:, 0]
+
+    ref = traj(1.5625e-4, W.TABLEAUX["rk4"])
+    for name, tab in W.TABLEAUX.items():
+        p = W.TABLEAU_ORDER[name]
+        errs = [np.abs(traj(dt, tab) - ref).max() for dt in (0.01, 0.005, 0.0025, 0.00125)]
+        orders = [np.log2(errs[i] / errs[i + 1]) for i in range(3)]
+        assert all(abs(o - p) <= 0.2 for o in orders), (name, orders)
+
+
+def test_tableau_adjoint_reduces_to_rk4_adjoint():
+    inst = W.config1(4)
+    n_steps = 150
+    on = oracle.OracleNet(inst.net)
+    coef = np.random.default_rng(2).standard_normal((n_steps, on.n))
+    y0 = oracle.init_state(on, inst.v0)
+    a = oracle.adjoint(on, y0, inst.stim, 0.01, n_steps, coef)
+    b = oracle.adjoint(on, y0, inst.stim, 0.01, n_steps, coef, tableau=W.TABLEAUX["rk4"])
+    # same recursion; only the order of the final lambda += sum u_s differs
+    for k in ("g", "g_Na", "g_K", "g_L", "lambda0"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-12, atol=1e-14 * np.abs(a[k]).max())
+
+
+@pytest.mark.parametrize("name", ["euler", "heun", "ssprk3", "kutta3", "rk38"])
+def test_tableau_adjoint_matches_central_differences(name):
+    # slow-GABA network (all three synapse classes): the adjoint of the
+    # tableau's discrete map against central differences of that map
+    tab = W.TABLEAUX[name]
+    inst = W.config2(0, t_ms=3.0)
+    n_steps = 200
+    on = oracle.OracleNet(inst.net)
+    rng = np.random.default_rng(7)
+    coef = rng.standard_normal((n_steps, on.n))
+    y0 = oracle.init_state(on, inst.v0)
+    y0[5:7, on.n_pn:] = rng.uniform(0.1, 1.0, (2, on.n - on.n_pn)) * np.array([[0.5], [4.0]])
+    adj = oracle.adjoint(on, y0, inst.stim, 0.01, n_steps, coef, tableau=tab)
+
+    def L(net_, prm=None):
+        y = y0.copy()
+        v = oracle.integrate(net_, y, inst.stim, 0.01, n_steps, tableau=tab)["v"]
+        return float((coef * (v + 65.0)).sum()), float(np.abs(coef * (v + 65.0)).sum())
+
+    sizes = [a * b for a, b in on.block_shapes]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    h = 1e-3
+    for p in range(len(sizes)):
+        blk = np.flatnonzero(on.mask[offs[p]:offs[p + 1]])
+        e = int(offs[p] + blk[len(blk) // 3])
+        gp, gm = on.g.copy(), on.g.copy()
+        gp[e] += h
+        gm[e] -= h
+        (lp, mag), (lm, _) = L(on.with_params(g=gp)), L(on.with_params(g=gm))
+        fd = (lp - lm) / (2 * h)
+        roundoff = 8 * np.finfo(float).eps * mag / (2 * h)
+        assert abs(adj["g"][e] - fd) <= 1e-5 * abs(fd) + roundoff, (name, p, adj["g"][e], fd)
+    for kind, idx in (("g_Na", 5), ("g_K", 40), ("g_L", 100)):
+        row = oracle.PARAM_NAMES.index(kind)
+        pp, pm = on.prm.copy(), on.prm.copy()
+        pp[row, idx] += h
+        pm[row, idx] -= h
+        (lp, mag), (lm, _) = L(on.with_params(prm=pp)), L(on.with_params(prm=pm))
+        fd = (lp - lm) / (2 * h)
+        roundoff = 8 * np.finfo(float).eps * mag / (2 * h)
+        assert abs(adj[kind][idx] - fd) <= 1e-5 * abs(fd) + roundoff, (name, kind, adj[kind][idx], fd)
