@@ -248,6 +248,39 @@ psst_status psst_adjoint(psst_batch *batch, const float *checkpoints, int32_t K,
  * occupies in grad_g. */
 psst_status psst_network_grad_size(const psst_network *net, int64_t *n_entries);
 
+/* ------------------------------------------------------------------------ */
+/* Explicit Runge-Kutta tableaux                                             */
+/* ------------------------------------------------------------------------ */
+
+/* An explicit Runge-Kutta method of 1 to 4 stages, the family the classical
+ * RK4 step belongs to ("Brain simulations as computational graphs", RK4
+ * paragraph; the same section's IVP equation): stage inputs
+ * Y_s = y + dt sum_{q<s} a[s][q] k_q, k_s = f(Y_s) with the injected current
+ * held at t_n, and y' = y + dt sum_s b[s] k_s.  a must be strictly lower
+ * triangular (a[s][q] = 0 for q >= s), and every a and b entry of an unused
+ * stage (s >= stages) must be 0; all entries finite. */
+typedef struct {
+    int32_t stages;        /* 1..4 */
+    double a[4][4];        /* a[s][q]: weight of k_q in stage s's input */
+    double b[4];           /* weight of k_s in the step */
+} psst_tableau;
+
+/* Set the method used by psst_integrate on this network and inherited by
+ * batches created from it afterwards.  NULL restores classical RK4; a tableau
+ * equal to classical RK4 (a[1][0] = a[2][1] = 1/2, a[3][2] = 1,
+ * b = 1/6, 1/3, 1/3, 1/6) is treated as NULL (same kernels, same bits).
+ * Networks on the per-stage path (more than 1024 neurons) accept only RK4:
+ * other tableaux return PSST_ERR_UNSUPPORTED here.  Synchronous; errors:
+ * INVALID_ARGUMENT for a NULL network or a tableau that breaks the rules
+ * above. */
+psst_status psst_network_set_tableau(psst_network *net, const psst_tableau *tab);
+
+/* The same for a batch: its integrate and adjoint calls use this method.
+ * psst_batch_create takes the method of its networks, which must all agree
+ * (else INVALID_ARGUMENT).  Batches of a large shared network accept only
+ * RK4 (UNSUPPORTED otherwise). */
+psst_status psst_batch_set_tableau(psst_batch *batch, const psst_tableau *tab);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,7 @@ struct AdjArgs {
     int32_t ld_max;
     int64_t lds_bytes;
     int32_t *flag;
+    Tab tab;                    // method of the generic-step variants
 };
 
 // workspace layout of one instance (doubles), ld = padded neuron count
@@ -137,7 +138,7 @@ __device__ __forceinline__ double row_dot_quad(F *row, const double *q, int n, i
     return p + __shfl_xor(p, 2);
 }
 
-template <int BS>
+template <int BS, bool GEN>
 __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
 {
     constexpr int NPT = 1;
@@ -223,7 +224,10 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
             stash.sS = W.sS + (int64_t)s * 12 * ld;
             stash.ld = ld;
             double Iu[NPT] = {d.ci * stim_nA(a.stim, Ic, p0, p1, a.step0 + s0 + s)};
-            rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, &stash);
+            if constexpr (GEN)
+                rk_step_wg_tab<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, &stash, a.tab);
+            else
+                rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, &stash);
         }
         // ---- reverse steps
         for (int s = L - 1; s >= 0; --s) {
@@ -247,17 +251,31 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
                 sSs = stg + 28 * ld;
             }
             double un[NVAR], usum[NVAR];
+            double uh[GEN ? 4 : 1][NVAR];      // generic method: u of the later stages
 #pragma unroll
             for (int v = 0; v < NVAR; ++v) {
                 un[v] = 0.0;
                 usum[v] = 0.0;
             }
+            // classical RK4: kbar_q = dt b_q lam + dt c_{q+1} u_{q+1}; a generic
+            // tableau: kbar_q = dt b_q lam + dt sum_{r>q} a_rq u_r (stages last
+            // to first, unrolled so the u_r stay in registers)
+#pragma unroll(GEN ? 4 : 1)
             for (int q = 3; q >= 0; --q) {
+                if (GEN && q >= a.tab.s) continue;
                 double Yq[NVAR], kb[NVAR], u[NVAR], qq[3], dg[3];
 #pragma unroll
                 for (int v = 0; v < NVAR; ++v) {
                     Yq[v] = own ? sYs[(q * NVAR + v) * ld + i] : 0.0;
-                    kb[v] = dt * bq[q] * lam[v] + (q < 3 ? dt * cq[q + 1] * un[v] : 0.0);
+                    if constexpr (GEN) {
+                        double t = dt * a.tab.b[q] * lam[v];
+#pragma unroll
+                        for (int r = q + 1; r < 4; ++r)
+                            if (r < a.tab.s) t += dt * a.tab.a[r][q] * uh[r][v];
+                        kb[v] = t;
+                    } else {
+                        kb[v] = dt * bq[q] * lam[v] + (q < 3 ? dt * cq[q + 1] * un[v] : 0.0);
+                    }
                 }
                 if (!own) Yq[YM] = Yq[YH] = Yq[YN] = 0.5;   // keep idle lanes finite
                 const double sa = own ? sSs[(q * 3 + 0) * ld + i] : 0.0;
@@ -311,6 +329,7 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
 #pragma unroll
                 for (int v = 0; v < NVAR; ++v) {
                     un[v] = u[v];
+                    if constexpr (GEN) uh[q][v] = u[v];
                     usum[v] += u[v];
                 }
             }
@@ -541,13 +560,13 @@ static psst_status ensure(void **p, size_t *have, size_t need)
     return PSST_OK;
 }
 
-static const void *adj_fn(int bs)
+static const void *adj_fn(int bs, bool gen)
 {
     switch (bs) {
-    case 64: return (const void *)adjoint_wg_kernel<64>;
-    case 128: return (const void *)adjoint_wg_kernel<128>;
-    case 256: return (const void *)adjoint_wg_kernel<256>;
-    case 512: return (const void *)adjoint_wg_kernel<512>;
+    case 64: return gen ? (const void *)adjoint_wg_kernel<64, true> : (const void *)adjoint_wg_kernel<64, false>;
+    case 128: return gen ? (const void *)adjoint_wg_kernel<128, true> : (const void *)adjoint_wg_kernel<128, false>;
+    case 256: return gen ? (const void *)adjoint_wg_kernel<256, true> : (const void *)adjoint_wg_kernel<256, false>;
+    case 512: return gen ? (const void *)adjoint_wg_kernel<512, true> : (const void *)adjoint_wg_kernel<512, false>;
     }
     return nullptr;
 }
@@ -557,7 +576,7 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
                         const float *ckpt, int32_t K, const psst_stimulus *stim, float dt,
                         int64_t n_steps, int64_t step0, const float *dLdV, float *grad_g,
                         float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
-                        size_t lds_max, void *stream)
+                        size_t lds_max, bool gen, const Tab &tab, void *stream)
 {
     const int32_t n = (int32_t)nets.size();
     int max_n = 0, max_ld = 0;
@@ -574,7 +593,7 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
     int bs = max_n <= 256 ? 256 : 512;
     if (const char *e = std::getenv("PSST_ADJ_BS")) {     // launch-shape override
         const int v = std::atoi(e);
-        if (adj_fn(v) && v >= max_n) bs = v;
+        if (adj_fn(v, gen) && v >= max_n) bs = v;
     }
     if (4 * bs < max_ld) return fail(PSST_ERR_UNSUPPORTED, "no adjoint launch shape for n=%d", max_n);
     if (!*work) *work = new AdjWork();
@@ -592,7 +611,7 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
     }
     if (need > lds_max) return fail(PSST_ERR_UNSUPPORTED, "adjoint LDS buffers exceed the LDS");
     const size_t lds = lds_max;     // the rest holds conductance columns
-    const void *fn = adj_fn(bs);
+    const void *fn = adj_fn(bs, gen);
     if (lds > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     AdjArgs a{};
     a.desc = d_desc;
@@ -617,6 +636,7 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
     a.ld_max = max_ld;
     a.lds_bytes = (int64_t)lds;
     a.flag = flag;
+    a.tab = tab;
     hipStream_t st = (hipStream_t)stream;
     void *args[] = {&a};
     if (n_steps > 0) HIPCHK(hipLaunchKernel(fn, dim3(n), dim3(bs), args, lds, st));

@@ -23,6 +23,14 @@ struct RecDev {
     int32_t spike_cap;
 };
 
+// Explicit Runge-Kutta tableau (stages <= 4, a strictly lower triangular)
+// for the kernels' generic step; classical RK4 has kernels of its own.
+struct Tab {
+    int32_t s;
+    double a[4][4];
+    double b[4];
+};
+
 // Arguments of the persistent per-instance kernel (one workgroup integrates
 // one instance for all steps of the call).
 struct WGArgs {
@@ -39,13 +47,16 @@ struct WGArgs {
     int64_t lds_bytes;          // dynamic LDS of the launch; instances whose
                                 // conductances fit keep them in LDS
     int32_t *flag;              // set to 1 when a state turns non-finite
+    Tab tab;                    // method of the generic-step variants
 };
 
 typedef void (*wg_kernel_t)(WGArgs);
 
-// Kernel variant: threads per workgroup, neurons per thread.
+// Kernel variant: threads per workgroup, neurons per thread, and whether it
+// runs the generic tableau step (else classical RK4).
 struct WGVariant {
     int bs, npt;
+    bool gen;
     const void *fn;
 };
 

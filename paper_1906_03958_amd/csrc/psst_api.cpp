@@ -320,10 +320,10 @@ extern "C" psst_status psst_state_init(const psst_network *net, const float *v0,
 // the per-instance persistent kernel: variant choice and launch
 // ---------------------------------------------------------------------------
 
-static const WGVariant *find_variant(int bs, int npt)
+static const WGVariant *find_variant(int bs, int npt, bool gen)
 {
     for (const WGVariant *v = wg_variants(); v->fn; ++v)
-        if (v->bs == bs && v->npt == npt) return v;
+        if (v->bs == bs && v->npt == npt && v->gen == gen) return v;
     return nullptr;
 }
 
@@ -433,7 +433,7 @@ extern "C" psst_status psst_integrate(psst_network *net, float *state, const pss
     const char *env = std::getenv("PSST_LDS_G");
     const size_t lds = (env && env[0] == '0') ? wg_lds_bytes(false, net->ld, net->nch, 0)
                                               : max_lds_per_block();
-    const WGVariant *v = find_variant(bs, npt);
+    const WGVariant *v = find_variant(bs, npt, net->gen);
     if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant for n=%d", net->n);
     if ((s = set_lds_attr(v->fn, lds)) != PSST_OK) return s;
     WGArgs a{};
@@ -450,6 +450,7 @@ extern "C" psst_status psst_integrate(psst_network *net, float *state, const pss
     a.K = 1;
     a.lds_bytes = (int64_t)lds;
     a.flag = net->d_flag;
+    a.tab = net->tab;
     void *args[] = {&a};
     HIPCHK(hipLaunchKernel(v->fn, dim3(1), dim3(bs), args, lds, (hipStream_t)stream));
     return PSST_OK;
@@ -509,12 +510,13 @@ static WGArgs group_args(psst_batch *b, const Group &g, float *states, const pss
     a.K = K > 0 ? K : 1;
     a.lds_bytes = (int64_t)g.lds;
     a.flag = b->d_flag;
+    a.tab = b->tab;
     return a;
 }
 
-static psst_status launch_group(const Group &g, WGArgs &a, hipStream_t s)
+static psst_status launch_group(const Group &g, bool gen, WGArgs &a, hipStream_t s)
 {
-    const WGVariant *v = find_variant(g.bs, g.npt);
+    const WGVariant *v = find_variant(g.bs, g.npt, gen);
     if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant bs=%d npt=%d", g.bs, g.npt);
     psst_status st = set_lds_attr(v->fn, g.lds);
     if (st != PSST_OK) return st;
@@ -529,6 +531,7 @@ static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream
 {
     std::vector<std::pair<int, int>> cands;
     for (const WGVariant *v = wg_variants(); v->fn; ++v) {
+        if (v->gen != b->gen) continue;
         const int cap = v->bs * v->npt;
         if (cap < g.max_n || cap >= 4 * std::max(g.max_n, 64)) continue;
         if (4 * v->bs < g.max_ld) continue;     // every row quad needs a thread
@@ -545,11 +548,11 @@ static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream
         t.bs = c.first;
         t.npt = c.second;
         WGArgs a = group_args(b, t, scratch, nullptr, 0.01f, 4, 0, nullptr, nullptr, 1);
-        psst_status st = launch_group(t, a, s);        // warm-up
+        psst_status st = launch_group(t, b->gen, a, s);        // warm-up
         if (st != PSST_OK) return st;
         a.n_steps = 16;
         HIPCHK(hipEventRecord(e0, s));
-        if ((st = launch_group(t, a, s)) != PSST_OK) return st;
+        if ((st = launch_group(t, b->gen, a, s)) != PSST_OK) return st;
         HIPCHK(hipEventRecord(e1, s));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
@@ -586,6 +589,16 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
         b->shared &= nets[k] == nets[0];
     }
     b->nt = b->offsets[n];
+    // the method of the networks, which must agree
+    b->gen = nets[0]->gen;
+    b->tab = nets[0]->tab;
+    for (int32_t k = 1; k < n; ++k)
+        if (nets[k]->gen != b->gen ||
+            (b->gen && std::memcmp(&nets[k]->tab, &b->tab, sizeof(psst::Tab)) != 0)) {
+            delete b;
+            return fail(PSST_ERR_INVALID_ARGUMENT,
+                        "nets[%d] uses a different Runge-Kutta tableau than nets[0]", k);
+        }
 
 #define BCHK(call)                                                                \
     do {                                                                          \
@@ -618,6 +631,10 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
                         kMaxWGNeurons);
         }
         b->stage_path = true;
+        if (b->gen) {
+            batch_free(b);
+            return fail(PSST_ERR_UNSUPPORTED, "the per-stage path integrates with classical RK4 only");
+        }
         s = stage_batch_create(nets[0], n, &b->stage);
         if (s != PSST_OK) {
             batch_free(b);
@@ -660,7 +677,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     bool fixed = false;
     if (const char *shp = std::getenv("PSST_WG_SHAPE")) {
         int bs = 0, npt = 0;
-        if (std::sscanf(shp, "%dx%d", &bs, &npt) == 2 && find_variant(bs, npt) &&
+        if (std::sscanf(shp, "%dx%d", &bs, &npt) == 2 && find_variant(bs, npt, b->gen) &&
             bs * npt >= g.max_n && 4 * bs >= g.max_ld) {
             g.bs = bs;
             g.npt = npt;
@@ -747,7 +764,7 @@ static psst_status submit_graph(psst_batch *b, std::vector<WGArgs> &args, hipStr
         b->node_args = args;
         for (size_t k = 0; k < G; ++k) {
             const Group &g = b->groups[k];
-            const WGVariant *v = find_variant(g.bs, g.npt);
+            const WGVariant *v = find_variant(g.bs, g.npt, b->gen);
             if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant");
             psst_status st = set_lds_attr(v->fn, g.lds);
             if (st != PSST_OK) return st;
@@ -767,7 +784,7 @@ static psst_status submit_graph(psst_batch *b, std::vector<WGArgs> &args, hipStr
             if (std::memcmp(&b->node_args[k], &args[k], sizeof(WGArgs)) == 0) continue;
             b->node_args[k] = args[k];
             const Group &g = b->groups[k];
-            const WGVariant *v = find_variant(g.bs, g.npt);
+            const WGVariant *v = find_variant(g.bs, g.npt, b->gen);
             void *kp[] = {&b->node_args[k]};
             hipKernelNodeParams p{};
             p.func = const_cast<void *>(v->fn);
@@ -830,5 +847,78 @@ extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
         return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available on the per-stage path");
     return adjoint_run(b->nets, b->d_desc, b->nt, b->offsets, &b->adj, ckpt, K, stim, dt, n_steps,
                        step0, dLdV, grad_g, grad_gNa, grad_gK, grad_gL, per_instance, b->d_flag,
-                       max_lds_per_block(), stream);
+                       max_lds_per_block(), b->gen, b->tab, stream);
+}
+
+// ---------------------------------------------------------------------------
+// explicit Runge-Kutta tableaux
+// ---------------------------------------------------------------------------
+
+// Check the rules of psst_tableau; on success *gen says whether it differs
+// from classical RK4 and *t holds its device form.
+static psst_status read_tableau(const psst_tableau *tab, bool *gen, psst::Tab *t)
+{
+    *gen = false;
+    *t = psst::Tab{};
+    if (!tab) return PSST_OK;
+    const int S = tab->stages;
+    if (S < 1 || S > 4) return fail(PSST_ERR_INVALID_ARGUMENT, "tableau: stages=%d not in 1..4", S);
+    for (int i = 0; i < 4; ++i) {
+        for (int q = 0; q < 4; ++q) {
+            const double v = tab->a[i][q];
+            if (!std::isfinite(v)) return fail(PSST_ERR_INVALID_ARGUMENT, "tableau: a[%d][%d] not finite", i, q);
+            if ((q >= i || i >= S) && v != 0.0)
+                return fail(PSST_ERR_INVALID_ARGUMENT,
+                            "tableau: a[%d][%d] must be 0 (explicit, %d stages)", i, q, S);
+        }
+        if (!std::isfinite(tab->b[i])) return fail(PSST_ERR_INVALID_ARGUMENT, "tableau: b[%d] not finite", i);
+        if (i >= S && tab->b[i] != 0.0) return fail(PSST_ERR_INVALID_ARGUMENT, "tableau: b[%d] must be 0", i);
+    }
+    const bool rk4 = S == 4 && tab->a[1][0] == 0.5 && tab->a[2][0] == 0.0 &&
+                     tab->a[2][1] == 0.5 && tab->a[3][0] == 0.0 && tab->a[3][1] == 0.0 &&
+                     tab->a[3][2] == 1.0 && tab->b[0] == 1.0 / 6.0 && tab->b[1] == 1.0 / 3.0 &&
+                     tab->b[2] == 1.0 / 3.0 && tab->b[3] == 1.0 / 6.0;
+    if (rk4) return PSST_OK;
+    *gen = true;
+    t->s = S;
+    for (int i = 0; i < 4; ++i) {
+        for (int q = 0; q < 4; ++q) t->a[i][q] = tab->a[i][q];
+        t->b[i] = tab->b[i];
+    }
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_network_set_tableau(psst_network *net, const psst_tableau *tab)
+{
+    if (!net) return fail(PSST_ERR_INVALID_ARGUMENT, "network is NULL");
+    bool gen;
+    psst::Tab t;
+    psst_status s = read_tableau(tab, &gen, &t);
+    if (s != PSST_OK) return s;
+    if (gen && !fits_wg(net))
+        return fail(PSST_ERR_UNSUPPORTED, "the per-stage path integrates with classical RK4 only");
+    net->gen = gen;
+    net->tab = t;
+    return PSST_OK;
+}
+
+extern "C" psst_status psst_batch_set_tableau(psst_batch *b, const psst_tableau *tab)
+{
+    if (!b) return fail(PSST_ERR_INVALID_ARGUMENT, "batch is NULL");
+    bool gen;
+    psst::Tab t;
+    psst_status s = read_tableau(tab, &gen, &t);
+    if (s != PSST_OK) return s;
+    if (gen && b->stage_path)
+        return fail(PSST_ERR_UNSUPPORTED, "the per-stage path integrates with classical RK4 only");
+    if (gen != b->gen && b->exec) {
+        // the graph's kernel changes: build it again on the next call
+        HIPCHK(hipGraphExecDestroy(b->exec));
+        HIPCHK(hipGraphDestroy(b->graph));
+        b->exec = nullptr;
+        b->graph = nullptr;
+    }
+    b->gen = gen;
+    b->tab = t;
+    return PSST_OK;
 }

@@ -30,7 +30,7 @@
 
 namespace psst {
 
-template <int BS, int NPT>
+template <int BS, int NPT, bool GEN>
 __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
 {
     extern __shared__ double lds_d[];
@@ -98,7 +98,10 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
             Iu[k] = d.ci * stim_nA(a.stim, Ic[k], p0[k], p1[k], g);
             vold[k] = y[k][YV];
         }
-        rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr);
+        if constexpr (GEN)
+            rk_step_wg_tab<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr, a.tab);
+        else
+            rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr);
         // spikes, records
         const bool do_rec = (g + 1 == next_rec);
 #pragma unroll
@@ -160,11 +163,13 @@ __global__ __launch_bounds__(256) void init_state_kernel(InitArgs a)
     }
 }
 
-#define WGV(BS, NPT) {BS, NPT, (const void *)rk4_wg_kernel<BS, NPT>}
+#define WGV(BS, NPT) {BS, NPT, false, (const void *)rk4_wg_kernel<BS, NPT, false>}
+#define WGG(BS, NPT) {BS, NPT, true, (const void *)rk4_wg_kernel<BS, NPT, true>}
 
 static const WGVariant kVariants[] = {
     WGV(64, 1), WGV(128, 1), WGV(128, 2), WGV(256, 1), WGV(256, 2), WGV(256, 4), WGV(512, 1),
-    {0, 0, nullptr},
+    WGG(64, 1), WGG(128, 1), WGG(128, 2), WGG(256, 1), WGG(256, 2), WGG(256, 4), WGG(512, 1),
+    {0, 0, false, nullptr},
 };
 
 const WGVariant *wg_variants() { return kVariants; }

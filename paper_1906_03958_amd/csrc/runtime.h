@@ -60,6 +60,9 @@ struct psst_network {
     // per-stage path (networks too large for one workgroup)
     StageNet *stage = nullptr;
     StageBatch *single = nullptr;   // one-trial stage batch for psst_integrate
+    // method: classical RK4 unless gen (then the explicit tableau tab)
+    bool gen = false;
+    psst::Tab tab{};
 };
 
 
@@ -89,6 +92,8 @@ struct psst_batch {
     std::vector<hipGraphNode_t> nodes;
     std::vector<WGArgs> node_args;
     AdjWork *adj = nullptr;         // adjoint workspace, sized on first use
+    bool gen = false;               // method: classical RK4 unless gen
+    psst::Tab tab{};
 };
 
 
@@ -98,5 +103,5 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
                         const float *ckpt, int32_t K, const psst_stimulus *stim, float dt,
                         int64_t n_steps, int64_t step0, const float *dLdV, float *grad_g,
                         float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
-                        size_t lds_max, void *stream);
+                        size_t lds_max, bool gen, const psst::Tab &tab, void *stream);
 void adjoint_free(AdjWork *w);

@@ -327,6 +327,78 @@ __device__ __forceinline__ void rk4_step_wg(const WGSyn &w, const Kin &K, double
     }
 }
 
+// One step of the explicit method T (1 to 4 stages) for the calling thread's
+// neurons: stage inputs Y_q = y + dt sum_{r<q} a_qr k_r (the sum over r in
+// order, from 0), k_q = f(Y_q), then y <- y + dt sum_q b_q k_q rounded to its
+// stored float32 pair.  The stage loop is unrolled so the earlier k stay in
+// registers; T.s is the same for the whole workgroup, so the barriers inside
+// the synaptic sums are reached by every thread.
+template <int BS, int NPT>
+__device__ __forceinline__ void rk_step_wg_tab(const WGSyn &w, const Kin &K, double cgf,
+                                               const float (&pr)[NPT][NPRM],
+                                               const double (&Iu)[NPT], double dt,
+                                               double (&y)[NPT][NVAR], const StageStash *stash,
+                                               const Tab &T)
+{
+    const int tid = threadIdx.x;
+    double inc[NPT][NVAR];
+    double kq[3][NPT][NVAR];
+    double Y[NPT][NVAR];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+            inc[k][v] = 0.0;
+            Y[k][v] = y[k][v];
+        }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= T.s) break;
+        if (q > 0) {
+#pragma unroll
+            for (int k = 0; k < NPT; ++k)
+#pragma unroll
+                for (int v = 0; v < NVAR; ++v) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int r = 0; r < q; ++r) acc += T.a[q][r] * kq[r][k][v];
+                    Y[k][v] = y[k][v] + dt * acc;
+                }
+        }
+        double sa[NPT], sg[NPT], sb[NPT];
+        syn_sums<BS, NPT>(w, K, Y, sa, sg, sb);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            if (k * BS >= w.n) continue;
+            const int i = tid + k * BS;
+            if (stash && i < w.n) {
+#pragma unroll
+                for (int v = 0; v < NVAR; ++v) stash->sY[(q * NVAR + v) * stash->ld + i] = Y[k][v];
+                stash->sS[(q * 3 + 0) * stash->ld + i] = sa[k];
+                stash->sS[(q * 3 + 1) * stash->ld + i] = sg[k];
+                stash->sS[(q * 3 + 2) * stash->ld + i] = sb[k];
+            }
+            double f[NVAR];
+            hh_rhs(Y[k], prm_of(pr[k]), K, cgf * sa[k], cgf * sg[k], cgf * sb[k], Iu[k],
+                   i >= w.n_pn, w.gabab, f);
+#pragma unroll
+            for (int v = 0; v < NVAR; ++v) {
+                inc[k][v] += T.b[q] * f[v];
+                if (q < 3) kq[q][k][v] = f[v];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        if (tid + k * BS >= w.n) continue;
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+            float hi, lo;
+            y[k][v] = split_store(y[k][v] + dt * inc[k][v], hi, lo);
+        }
+    }
+}
+
 // Set up the workgroup's view of instance d: LDS carve-up and the resident
 // part of the conductances -- as many leading columns of every chunk as the
 // launch's LDS allocation leaves room for (all of them when the instance fits).

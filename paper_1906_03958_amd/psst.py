@@ -33,6 +33,7 @@ EXPORTS = (
     "psst_batch_create", "psst_batch_destroy", "psst_batch_layout",
     "psst_batch_state_init", "psst_integrate_batch", "psst_batch_poll",
     "psst_batch_describe", "psst_adjoint", "psst_network_grad_size",
+    "psst_network_set_tableau", "psst_batch_set_tableau",
 )
 
 
@@ -54,6 +55,25 @@ class Pathway(C.Structure):
     _fields_ = [("type", C.c_int32), ("pre_begin", C.c_int32), ("pre_end", C.c_int32),
                 ("post_begin", C.c_int32), ("post_end", C.c_int32),
                 ("g_nS", C.POINTER(C.c_float)), ("mask", C.POINTER(C.c_uint8))]
+
+
+class Tableau(C.Structure):
+    _fields_ = [("stages", C.c_int32), ("a", (C.c_double * 4) * 4), ("b", C.c_double * 4)]
+
+
+def _tableau_struct(tab) -> Optional[Tableau]:
+    """psst_tableau from dict(a=[[...]] (stages x stages), b=[...]); None -> NULL."""
+    if tab is None:
+        return None
+    b = [float(x) for x in tab["b"]]
+    t = Tableau()
+    t.stages = len(b)
+    for i, row in enumerate(tab["a"]):
+        for q, v in enumerate(row):
+            t.a[i][q] = float(v)
+    for i, v in enumerate(b):
+        t.b[i] = v
+    return t
 
 
 class Kinetics(C.Structure):
@@ -106,6 +126,8 @@ def lib():
             "psst_adjoint": (i32, [vp, vp, i32, C.POINTER(Stimulus), f32, i64, i64, vp, vp, vp,
                                    vp, vp, i32, vp]),
             "psst_network_grad_size": (i32, [vp, C.POINTER(i64)]),
+            "psst_network_set_tableau": (i32, [vp, C.POINTER(Tableau)]),
+            "psst_batch_set_tableau": (i32, [vp, C.POINTER(Tableau)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -333,6 +355,18 @@ def integrate_batch(batch: Batch, states, stim: Optional[DeviceStimulus], dt_ms:
 
 def batch_poll(batch: Batch, stream=None):
     _check(lib().psst_batch_poll(batch.handle, _stream(stream)))
+
+
+def network_set_tableau(net: Network, tab=None):
+    """Explicit Runge-Kutta method of psst_integrate on this network (and of
+    batches created from it); tab = dict(a, b) or None for classical RK4."""
+    t = _tableau_struct(tab)
+    _check(lib().psst_network_set_tableau(net.handle, None if t is None else C.byref(t)))
+
+
+def batch_set_tableau(batch: Batch, tab=None):
+    t = _tableau_struct(tab)
+    _check(lib().psst_batch_set_tableau(batch.handle, None if t is None else C.byref(t)))
 
 
 def batch_describe(batch: Batch) -> str:

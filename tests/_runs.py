@@ -16,7 +16,7 @@ def torch_dev():
 
 
 def gpu_run(insts, n_steps, dt=0.01, rec_stride=1, spike_cap=0, batched=True,
-            chunks=None, nets=None, state=None, return_state=False):
+            chunks=None, nets=None, state=None, return_state=False, tableau=None):
     """Integrate instances on the GPU.  batched=True: one psst_batch of all
     instances; False: one psst_integrate per instance.  chunks: list of step
     counts summing to n_steps (resumed calls).  Returns dict with v [rows, NT],
@@ -24,6 +24,9 @@ def gpu_run(insts, n_steps, dt=0.01, rec_stride=1, spike_cap=0, batched=True,
     torch, dev = torch_dev()
     if nets is None:
         nets = [psst.network_create(i.net) for i in insts]
+        if tableau is not None:
+            for h in nets:
+                psst.network_set_tableau(h, tableau)
     sizes = np.array([i.net.n for i in insts])
     offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     nt = int(offs[-1])
@@ -80,9 +83,9 @@ def gpu_run(insts, n_steps, dt=0.01, rec_stride=1, spike_cap=0, batched=True,
     return out
 
 
-def oracle_run(insts, n_steps, dt=0.01, rec_stride=1, spike_cap=0, threads=None):
+def oracle_run(insts, n_steps, dt=0.01, rec_stride=1, spike_cap=0, threads=None, tableau=None):
     res = oracle.run_many(insts, n_steps, dt=dt, rec_stride=rec_stride, spike_cap=spike_cap,
-                          threads=threads)
+                          threads=threads, tableau=tableau)
     v = np.concatenate([r[0]["v"] for r in res], axis=1) if rec_stride else None
     cnt = np.concatenate([r[0]["spike_count"] for r in res])
     spk = np.concatenate([r[0]["spike_t"] for r in res], axis=0)

@@ -1,0 +1,190 @@
+"""General explicit Runge-Kutta tableaux on the GPU (psst_network_set_tableau,
+psst_batch_set_tableau): the same discrete map as the FP64 oracle run with
+the same tableau -- forward parity (max |dV| <= 1e-3 mV over the first
+50 ms, spike times within 0.05 ms), bitwise invariances (batched = plain,
+chunking, batch order), the discrete adjoint against the oracle's tableau
+adjoint, classical RK4 given as a tableau = the default path bit for bit,
+and the validation of the tableau rules."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_03958_amd import workloads as W
+from tests import _runs as R
+
+pytestmark = pytest.mark.gpu
+
+DV_TOL = 1e-3
+SPIKE_TOL = 0.05
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _c3_sample(k):
+    sizes = np.array([W.config3_size(b) for b in range(256)])
+    order = np.argsort(sizes, kind="stable")
+    return [int(b) for b in order[np.linspace(0, 255, k).astype(int)]]
+
+
+@pytest.mark.parametrize("name", ["euler", "midpoint", "heun", "ralston", "kutta3", "ssprk3",
+                                  "rk38"])
+def test_tableau_forward_parity(name):
+    tab = W.TABLEAUX[name]
+    insts = [W.config1(0), W.config2(0, t_ms=60.0)] + \
+        [W.config3_instance(b) for b in _c3_sample(4)]
+    n = 5000
+    _say(f"{name}: sizes {[i.net.n for i in insts]}")
+    g = R.gpu_run(insts, n, rec_stride=10, spike_cap=32, tableau=tab)
+    o = R.oracle_run(insts, n, rec_stride=10, spike_cap=32, tableau=tab)
+    dv = np.abs(g["v"] - o["v"]).max()
+    bad, worst, total = R.spike_match(g["spike_count"], g["spike_t"], o["spike_count"],
+                                      o["spike_t"], 50.0)
+    _say(f"  max|dV| {dv:.2e} mV, spikes {total}, count mismatches {bad}, worst dt {worst:.2e} ms")
+    assert dv <= DV_TOL
+    assert bad == 0 and worst <= SPIKE_TOL
+
+
+def test_tableau_batched_equals_plain_chunked_and_order_invariant_bitwise():
+    tab = W.TABLEAUX["ssprk3"]
+    insts = [W.config3_instance(b) for b in _c3_sample(6)] + [W.config2(0, t_ms=5.0)]
+    a = R.gpu_run(insts, 300, rec_stride=1, spike_cap=8, batched=True, tableau=tab)
+    p = R.gpu_run(insts, 300, rec_stride=1, spike_cap=8, batched=False, tableau=tab)
+    np.testing.assert_array_equal(a["state"], p["state"])
+    np.testing.assert_array_equal(a["v"], p["v"])
+    c = R.gpu_run(insts, 300, rec_stride=1, spike_cap=8, batched=True, tableau=tab,
+                  chunks=[100, 37, 163])
+    np.testing.assert_array_equal(a["state"], c["state"])
+    np.testing.assert_array_equal(a["v"], c["v"])
+    perm = np.random.default_rng(1).permutation(len(insts))
+    d = R.gpu_run([insts[k] for k in perm], 300, rec_stride=1, spike_cap=8, batched=True,
+                  tableau=tab)
+    for new, old in enumerate(perm):
+        a0, a1 = a["offsets"][old], a["offsets"][old + 1]
+        d0, d1 = d["offsets"][new], d["offsets"][new + 1]
+        np.testing.assert_array_equal(a["state"][:, :, a0:a1], d["state"][:, :, d0:d1])
+
+
+def test_rk4_tableau_is_the_default_path_bitwise():
+    insts = [W.config3_instance(b) for b in _c3_sample(3)]
+    a = R.gpu_run(insts, 200, rec_stride=1)
+    b = R.gpu_run(insts, 200, rec_stride=1, tableau=W.TABLEAUX["rk4"])
+    np.testing.assert_array_equal(a["state"], b["state"])
+    np.testing.assert_array_equal(a["v"], b["v"])
+
+
+def test_batch_set_tableau_switches_method():
+    import torch
+    from paper_1906_03958_amd import psst
+    insts = [W.config3_instance(b) for b in _c3_sample(3)]
+    ref = R.gpu_run(insts, 100, rec_stride=0, tableau=W.TABLEAUX["kutta3"])
+    nets = [psst.network_create(i.net) for i in insts]
+    batch = psst.batch_create(nets)                  # RK4 networks
+    dev = torch.device("cuda:0")
+    nt = batch.n_total
+    st = torch.zeros(14 * nt, dtype=torch.float32, device=dev)
+    psst.batch_state_init(batch, torch.from_numpy(np.concatenate([i.v0 for i in insts])).to(dev),
+                          st)
+    stim = psst.pack_stimulus([i.stim for i in insts], dev)
+    psst.integrate_batch(batch, st, stim, 0.01, 1, 0)      # builds the RK4 graph
+    psst.batch_state_init(batch, torch.from_numpy(np.concatenate([i.v0 for i in insts])).to(dev),
+                          st)
+    psst.batch_set_tableau(batch, W.TABLEAUX["kutta3"])
+    psst.integrate_batch(batch, st, stim, 0.01, 100, 0)
+    psst.batch_poll(batch)
+    np.testing.assert_array_equal(st.view(7, 2, nt).cpu().numpy(), ref["state"])
+
+
+def test_tableau_validation():
+    from paper_1906_03958_amd import psst
+    net = psst.network_create(W.config1(0).net)
+    bad = [
+        dict(a=[], b=[]),                                         # 0 stages
+        dict(a=[[0.0] * 5] * 5, b=[0.2] * 5),                     # 5 stages
+        dict(a=[[0.0, 1.0], [0.5, 0.0]], b=[0.5, 0.5]),           # implicit entry
+        dict(a=[[0.0, 0.0], [float("nan"), 0.0]], b=[0.5, 0.5]),  # not finite
+    ]
+    for tab in bad:
+        with pytest.raises(psst.PsstError) as e:
+            if len(tab["b"]) in (0, 5):
+                t = psst.Tableau()
+                t.stages = len(tab["b"])
+                import ctypes as C
+                psst._check(psst.lib().psst_network_set_tableau(net.handle, C.byref(t)))
+            else:
+                psst.network_set_tableau(net, tab)
+        assert e.value.status == psst.ERR_INVALID_ARGUMENT
+    t = psst.Tableau()                                            # unused stage's weight
+    t.stages = 2
+    t.a[1][0] = 1.0
+    t.b[0] = t.b[1] = 0.5
+    t.b[2] = 0.1
+    import ctypes as C
+    with pytest.raises(psst.PsstError) as e:
+        psst._check(psst.lib().psst_network_set_tableau(net.handle, C.byref(t)))
+    assert e.value.status == psst.ERR_INVALID_ARGUMENT
+    # mixing methods in one batch
+    n2 = psst.network_create(W.config1(1).net)
+    psst.network_set_tableau(n2, W.TABLEAUX["heun"])
+    with pytest.raises(psst.PsstError) as e:
+        psst.batch_create([net, n2])
+    assert e.value.status == psst.ERR_INVALID_ARGUMENT
+    # the per-stage path integrates with RK4 only
+    big = psst.network_create(W.config4_network(n_pn=1536, n_ln=512))
+    with pytest.raises(psst.PsstError) as e:
+        psst.network_set_tableau(big, W.TABLEAUX["heun"])
+    assert e.value.status == psst.ERR_UNSUPPORTED
+    psst.network_set_tableau(big, None)
+
+
+@pytest.mark.parametrize("name", ["ssprk3", "rk38", "heun"])
+def test_tableau_adjoint_matches_oracle(name):
+    import torch
+    from paper_1906_03958_amd import psst
+    tab = W.TABLEAUX[name]
+    B, n_steps, K = 3, 250, 80
+    hidden, ev, i_nA, v0 = W.config5(B)
+    dev = torch.device("cuda:0")
+    net = psst.network_create(ev)
+    psst.network_set_tableau(net, tab)
+    batch = psst.batch_create([net] * B)
+    nt = batch.n_total
+    st = torch.zeros(14 * nt, dtype=torch.float32, device=dev)
+    psst.batch_state_init(batch, torch.from_numpy(v0.ravel()).to(dev), st)
+    stim = psst.DeviceStimulus(torch.from_numpy(i_nA.ravel()).to(dev))
+    ck = torch.zeros(((n_steps + K - 1) // K, 14 * nt), dtype=torch.float32, device=dev)
+    psst.integrate_batch(batch, st, stim, 0.01, n_steps, 0, None, ck, K)
+    psst.batch_poll(batch)
+    dl = (np.random.default_rng(11).standard_normal((n_steps, nt)) * 1e-3).astype(np.float32)
+    gs = net.grad_size
+    gg = torch.zeros(B * gs, dtype=torch.float32, device=dev)
+    gna = torch.zeros(nt, dtype=torch.float32, device=dev)
+    gk, gl = torch.zeros_like(gna), torch.zeros_like(gna)
+    _say(f"adjoint {name}: {B} trials x {ev.n} neurons, {n_steps} steps, K={K}")
+    psst.adjoint(batch, ck, K, stim, 0.01, n_steps, 0, torch.from_numpy(dl).to(dev), gg, gna,
+                 gk, gl, per_instance=True)
+    psst.batch_poll(batch)
+    on = oracle.OracleNet(ev)
+    gg = gg.cpu().numpy().reshape(B, gs)
+    for t in range(B):
+        y0 = oracle.init_state(on, v0[t])
+        ref = oracle.adjoint(on, y0, W.Stimulus(i_nA[t]), 0.01, n_steps,
+                             dl[:, t * ev.n:(t + 1) * ev.n].astype(np.float64), tableau=tab)
+        for key, got in (("g", gg[t]), ("g_Na", gna.cpu().numpy()[t * ev.n:(t + 1) * ev.n]),
+                         ("g_K", gk.cpu().numpy()[t * ev.n:(t + 1) * ev.n]),
+                         ("g_L", gl.cpu().numpy()[t * ev.n:(t + 1) * ev.n])):
+            r = np.asarray(ref[key], np.float64)
+            nrm = np.linalg.norm(got - r) / np.linalg.norm(r)
+            _say(f"  trial {t} {key}: norm rel err {nrm:.2e}")
+            assert nrm <= 1e-3, (name, t, key, nrm)
