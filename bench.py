@@ -309,6 +309,9 @@ def main():
                     help="batched: the 4096-network batch (the default line); large: the "
                          "16384-neuron network x 64 trials on the per-stage MFMA path; "
                          "uncoupled: the batch with every synapse removed (compute only)")
+    ap.add_argument("--method", default="rk4",
+                    help="explicit Runge-Kutta method of the batched/uncoupled workloads: "
+                         "one of the named tableaux (rk4 = the classical kernels)")
     ap.add_argument("--write-flops", nargs=2, metavar=("KERNEL", "CSV"),
                     help="turn a rocprofv3 --pmc SQ_INSTS_VALU_FLOPS_FP64 "
                          "SQ_INSTS_VALU_FLOPS_FP64_TRANS counter file of a bench run (same "
@@ -368,6 +371,9 @@ def main():
         f"({time.time() - t0:.1f}s)")
     t0 = time.time()
     nets = [psst.network_create(i.net) for i in insts]
+    if args.method != "rk4":
+        for h in nets:
+            psst.network_set_tableau(h, W.TABLEAUX[args.method])
     batch = psst.batch_create(nets)
     log(f"networks + batch (tuned) in {time.time() - t0:.1f}s: {psst.batch_describe(batch)}")
     v0 = torch.from_numpy(np.concatenate([i.v0 for i in insts])).to(dev)
@@ -410,9 +416,11 @@ def main():
     log(f"batched: {value:.3e} neuron-steps/s, {ms_per_step:.2f} ms per bench step "
         f"({1e3 * ms_per_step / args.chunk:.1f} us per RK4 step)")
 
-    # algorithmic bytes per RK4 step: the conductances once per stage
-    # (16 sum N^2) plus state and compensation words in and out (80 sum N)
-    bytes_per_rk4 = 16 * sum_n2 + 80 * sum_n
+    # algorithmic bytes per step: the conductances once per stage (4 sum N^2
+    # per stage, 16 sum N^2 for RK4) plus state and compensation words in and
+    # out (80 sum N)
+    stages = len(W.TABLEAUX[args.method]["b"])
+    bytes_per_rk4 = 4 * stages * sum_n2 + 80 * sum_n
     bytes_per_launch = bytes_per_rk4 * args.chunk
     achieved = bytes_per_launch / avg_launch_s / 1e9
     traffic = read_traffic("rk4_wg_kernel", args)
@@ -471,7 +479,9 @@ def main():
         sub = [insts[b] for b in pick]
         threads = min(os.cpu_count() or 1, 16)
         t0 = time.perf_counter()
-        res = oracle.run_many(sub, args.cpu_steps, dt=DT, rec_stride=10, threads=threads)
+        otab = None if args.method == "rk4" else W.TABLEAUX[args.method]
+        res = oracle.run_many(sub, args.cpu_steps, dt=DT, rec_stride=10, threads=threads,
+                              tableau=otab)
         ct = time.perf_counter() - t0
         ns = sum(i.net.n for i in sub) * args.cpu_steps
         cpu = {"value": ns / ct, "unit": "neuron-steps/s", "cores": threads, "kind": "oracle",
@@ -481,7 +491,7 @@ def main():
         sub1 = sub[::8]
         steps1 = max(args.cpu_steps // 2, 1)
         t0 = time.perf_counter()
-        oracle.run_many(sub1, steps1, dt=DT, rec_stride=0, threads=1)
+        oracle.run_many(sub1, steps1, dt=DT, rec_stride=0, threads=1, tableau=otab)
         ct1 = time.perf_counter() - t0
         cpu["value_1thread"] = sum(i.net.n for i in sub1) * steps1 / ct1
         cpu["sample_1thread"] = f"{len(sub1)} of those instances, {steps1} RK4 steps, 1 thread"
@@ -537,6 +547,7 @@ def main():
                     "fast-GABA synapses, g ~ U(0,0.5) nS x LogNormal(0,0.1), "
                     "I ~ U(0,2) nA, dt 0.01 ms"),
                    "instances": len(insts), "neurons": sum_n, "rk4_steps_per_step": args.chunk,
+                   "method": args.method,
                    "dt_ms": DT, "recording": f"spikes + V every {REC_STRIDE} steps",
                    "launch": psst.batch_describe(batch)},
         "plain": plain,
