@@ -124,6 +124,31 @@ psst_status psst_network_create(const psst_neuron_params *params, int32_t n_neur
                                 const psst_kinetics kinetics[3], psst_network **out);
 psst_status psst_network_destroy(psst_network *net);
 
+/* Storage of the conductance matrices on the per-instance path.  DENSE keeps
+ * every [post x pre] entry (zeros included) and reads each once per stage;
+ * SPARSE keeps, per postsynaptic neuron, its present synapses sorted by
+ * presynaptic index ("Circumventing memory constraints", item 1: sparse
+ * matrices where connectivity is low), so a stage reads 8 bytes per synapse
+ * instead of 4 bytes per matrix entry.  Both sum the products in the same
+ * fixed order (64-column chunks in column order, partials in chunk order;
+ * absent synapses add exact zeros), so the two give the same trajectory bit
+ * for bit.  AUTO picks SPARSE when at most a quarter of the pathway entries
+ * are synapses and the network takes the per-instance path.  Networks above
+ * 1024 neurons are always dense (per-stage path). */
+typedef enum {
+    PSST_STORAGE_AUTO = 0,
+    PSST_STORAGE_DENSE = 1,
+    PSST_STORAGE_SPARSE = 2
+} psst_storage;
+
+/* psst_network_create with a storage choice (psst_network_create = AUTO).
+ * SPARSE for a network above 1024 neurons returns UNSUPPORTED; psst_adjoint
+ * on a batch holding a sparse network returns UNSUPPORTED. */
+psst_status psst_network_create_storage(const psst_neuron_params *params, int32_t n_neurons,
+                                        const psst_pathway *pathways, int32_t n_pathways,
+                                        const psst_kinetics kinetics[3], int32_t storage,
+                                        psst_network **out);
+
 /* State layout: 7 variables (V, m, h, n, s, r, G) x 2 float32 words (value,
  * compensation), plane-major: word (2 * var + c) * n_total + i.  n_words =
  * 14 * n_neurons for a network.  s is the neuron's own outgoing transmitter

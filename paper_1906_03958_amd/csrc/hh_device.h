@@ -34,11 +34,20 @@ struct InstDesc {
     const uint8_t *maskt;     // synapse mask laid out like gt (then gtb)
     int32_t n_paths;
     int64_t grad_entries;     // entries of one copy of the pathway blocks
+    // sparse storage (flag DESC_SPARSE): per postsynaptic row i, its synapses
+    // sorted by presynaptic index in ELL form, entry e at e * ld + i: the
+    // fast matrix (columns 0..n-1) in entries [0, sp_kf), the slow matrix
+    // (columns = LN index) in [sp_kf, sp_kf + sp_kb); short rows are padded
+    // with their last column and g = 0
+    const int32_t *sp_col;
+    const float *sp_val;
+    int32_t sp_kf, sp_kb;
 };
 
 // flags: bit 0 the network has slow GABA; bit 1 it has no synapses at all
-// (the synaptic products are skipped, every synaptic sum is 0)
-enum { DESC_GABAB = 1, DESC_NOSYN = 2 };
+// (the synaptic products are skipped, every synaptic sum is 0); bit 2 its
+// conductances are stored sparse (sp_col, sp_val)
+enum { DESC_GABAB = 1, DESC_NOSYN = 2, DESC_SPARSE = 4 };
 
 // Synapse kinetics widened to float64.
 struct Kin {

@@ -65,6 +65,7 @@ static bool is_finite_f(float x) { return std::isfinite(x); }
 
 static size_t max_lds_per_block();
 static bool fits_wg(const psst_network *q);
+static const int kMaxWGNeurons = 1024;   // largest network of the per-instance kernel
 
 // ---------------------------------------------------------------------------
 // networks
@@ -82,6 +83,8 @@ static void net_free(psst_network *n)
     hipFree(n->d_order);
     hipFree(n->d_flag);
     hipFree(n->d_paths);
+    hipFree(n->d_spcol);
+    hipFree(n->d_spval);
     stage_batch_free(n->single);
     stage_net_free(n->stage);
     delete n;
@@ -149,9 +152,10 @@ static psst_status validate_network(const psst_neuron_params *p, int32_t n,
     return PSST_OK;
 }
 
-extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t n,
-                                           const psst_pathway *paths, int32_t np,
-                                           const psst_kinetics kin[3], psst_network **out)
+static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
+                                       const psst_pathway *paths, int32_t np,
+                                       const psst_kinetics kin[3], int32_t storage,
+                                       psst_network **out)
 {
     if (!out) return fail(PSST_ERR_INVALID_ARGUMENT, "out is NULL");
     *out = nullptr;
@@ -180,14 +184,85 @@ extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t 
     net->grad_entries = goff;
     net->g_floats = (int64_t)n * ld + (net->gabab ? (int64_t)n_ln * ld : 0);
     net->nch = n_chunks(n, p->n_pn, net->gabab);
+
+    // storage: sparse rows when asked, or (AUTO) when at most a quarter of the
+    // pathway entries are synapses; only on the per-instance path
+    int64_t present = 0;
+    for (int q = 0; q < np; ++q) {
+        const psst_pathway &w = paths[q];
+        const int64_t cnt = (int64_t)(w.post_end - w.post_begin) * (w.pre_end - w.pre_begin);
+        if (!w.mask) present += cnt;
+        else
+            for (int64_t e = 0; e < cnt; ++e) present += w.mask[e] != 0;
+    }
+    bool sparse = false;
+    if (storage == PSST_STORAGE_SPARSE) {
+        if (n > kMaxWGNeurons) {
+            delete net;
+            return fail(PSST_ERR_UNSUPPORTED, "sparse storage is for networks of at most %d neurons",
+                        kMaxWGNeurons);
+        }
+        sparse = np > 0;
+    } else if (storage == PSST_STORAGE_AUTO) {
+        sparse = np > 0 && n <= kMaxWGNeurons && 4 * present <= goff;
+    }
+    std::vector<int32_t> sp_col;
+    std::vector<float> sp_val;
+    if (sparse) {
+        // ELL rows: per postsynaptic i its synapses sorted by presynaptic column
+        std::vector<std::vector<std::pair<int32_t, float>>> rf(n), rb(n);
+        for (int q = 0; q < np; ++q) {
+            const psst_pathway &w = paths[q];
+            const int npre = w.pre_end - w.pre_begin;
+            for (int i = w.post_begin; i < w.post_end; ++i)
+                for (int j = w.pre_begin; j < w.pre_end; ++j) {
+                    const int64_t e = (int64_t)(i - w.post_begin) * npre + (j - w.pre_begin);
+                    if (w.mask && w.mask[e] == 0) continue;
+                    if (w.type == PSST_SYN_GABA_B) rb[i].push_back({j - p->n_pn, w.g_nS[e]});
+                    else rf[i].push_back({j, w.g_nS[e]});
+                }
+        }
+        int kf = 1, kb = net->gabab ? 1 : 0;
+        for (int i = 0; i < n; ++i) {
+            std::stable_sort(rf[i].begin(), rf[i].end(),
+                             [](const std::pair<int32_t, float> &x, const std::pair<int32_t, float> &y) {
+                                 return x.first < y.first;
+                             });
+            std::stable_sort(rb[i].begin(), rb[i].end(),
+                             [](const std::pair<int32_t, float> &x, const std::pair<int32_t, float> &y) {
+                                 return x.first < y.first;
+                             });
+            kf = std::max(kf, (int)rf[i].size());
+            if (net->gabab) kb = std::max(kb, (int)rb[i].size());
+        }
+        sp_col.assign((size_t)(kf + kb) * ld, 0);
+        sp_val.assign((size_t)(kf + kb) * ld, 0.f);
+        for (int i = 0; i < n; ++i) {
+            for (int half = 0; half < 2; ++half) {
+                const auto &r = half ? rb[i] : rf[i];
+                const int k0 = half ? kf : 0, K = half ? kb : kf;
+                for (int e = 0; e < K; ++e) {
+                    const bool real = e < (int)r.size();
+                    sp_col[(size_t)(k0 + e) * ld + i] = real ? r[e].first : (r.empty() ? 0 : r.back().first);
+                    sp_val[(size_t)(k0 + e) * ld + i] = real ? r[e].second : 0.f;
+                }
+            }
+        }
+        net->sparse = true;
+        net->nch = 0;
+        net->g_floats = 2LL * (kf + kb) * ld;      // 8 bytes per stored entry
+        net->desc.sp_kf = kf;
+        net->desc.sp_kb = kb;
+    }
     const bool wg = fits_wg(net);
 
     // per-instance kernel layout: transposed conductance matrices with padded
     // rows, gt[j * ld + i] (pre j, post i), and the synapse mask alike
-    std::vector<float> gt(wg ? (size_t)n * ld : 0, 0.f);
-    std::vector<float> gtb(wg && net->gabab ? (size_t)n_ln * ld : 0, 0.f);
-    std::vector<uint8_t> mt(wg ? (size_t)n * ld + gtb.size() : 0, 0);
-    for (int q = 0; q < np && wg; ++q) {
+    const bool dense_wg = wg && !sparse;
+    std::vector<float> gt(dense_wg ? (size_t)n * ld : 0, 0.f);
+    std::vector<float> gtb(dense_wg && net->gabab ? (size_t)n_ln * ld : 0, 0.f);
+    std::vector<uint8_t> mt(dense_wg ? (size_t)n * ld + gtb.size() : 0, 0);
+    for (int q = 0; q < np && dense_wg; ++q) {
         const psst_pathway &w = paths[q];
         const int npre = w.pre_end - w.pre_begin;
         for (int i = w.post_begin; i < w.post_end; ++i)
@@ -221,7 +296,14 @@ extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t 
         }                                                                         \
     } while (0)
 
-    if (wg) {
+    if (sparse) {
+        NETCHK(hipMalloc(&net->d_spcol, sizeof(int32_t) * sp_col.size()));
+        NETCHK(hipMemcpy(net->d_spcol, sp_col.data(), sizeof(int32_t) * sp_col.size(),
+                         hipMemcpyHostToDevice));
+        NETCHK(hipMalloc(&net->d_spval, sizeof(float) * sp_val.size()));
+        NETCHK(hipMemcpy(net->d_spval, sp_val.data(), sizeof(float) * sp_val.size(),
+                         hipMemcpyHostToDevice));
+    } else if (wg) {
         NETCHK(hipMalloc(&net->d_gt, sizeof(float) * gt.size()));
         NETCHK(hipMemcpy(net->d_gt, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice));
         if (!gtb.empty()) {
@@ -263,7 +345,10 @@ extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t 
     d.n = n;
     d.n_pn = p->n_pn;
     d.ld = ld;
-    d.flags = (net->gabab ? DESC_GABAB : 0) | (np == 0 ? DESC_NOSYN : 0);
+    d.flags = (net->gabab ? DESC_GABAB : 0) | (np == 0 ? DESC_NOSYN : 0) |
+              (sparse ? DESC_SPARSE : 0);
+    d.sp_col = net->d_spcol;
+    d.sp_val = net->d_spval;
     d.cg = net->cg;
     d.ci = net->ci;
     NETCHK(hipMalloc(&net->d_desc, sizeof(InstDesc)));
@@ -276,6 +361,25 @@ extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t 
 #undef NETCHK
     *out = net;
     return PSST_OK;
+}
+
+extern "C" psst_status psst_network_create(const psst_neuron_params *p, int32_t n,
+                                           const psst_pathway *paths, int32_t np,
+                                           const psst_kinetics kin[3], psst_network **out)
+{
+    return network_create_impl(p, n, paths, np, kin, PSST_STORAGE_AUTO, out);
+}
+
+extern "C" psst_status psst_network_create_storage(const psst_neuron_params *p, int32_t n,
+                                                   const psst_pathway *paths, int32_t np,
+                                                   const psst_kinetics kin[3], int32_t storage,
+                                                   psst_network **out)
+{
+    if (storage < PSST_STORAGE_AUTO || storage > PSST_STORAGE_SPARSE) {
+        if (out) *out = nullptr;
+        return fail(PSST_ERR_INVALID_ARGUMENT, "storage=%d is not a psst_storage value", storage);
+    }
+    return network_create_impl(p, n, paths, np, kin, storage, out);
 }
 
 extern "C" psst_status psst_network_destroy(psst_network *net)
@@ -356,7 +460,6 @@ static void default_shape(int max_n, int *bs, int *npt)
     else { *bs = 256; *npt = 4; }
 }
 
-static const int kMaxWGNeurons = 1024;
 
 // Networks the per-instance kernel takes: at most 1024 neurons, and the
 // activation and partial-sum buffers fit the workgroup's LDS.
@@ -845,6 +948,9 @@ extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
         return fail(PSST_ERR_INVALID_ARGUMENT, "summed gradients need every instance to share one network");
     if (b->stage_path)
         return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available on the per-stage path");
+    for (auto *q : b->nets)
+        if (q->sparse)
+            return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available for sparse storage");
     return adjoint_run(b->nets, b->d_desc, b->nt, b->offsets, &b->adj, ckpt, K, stim, dt, n_steps,
                        step0, dLdV, grad_g, grad_gNa, grad_gK, grad_gL, per_instance, b->d_flag,
                        max_lds_per_block(), b->gen, b->tab, stream);

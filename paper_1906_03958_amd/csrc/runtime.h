@@ -63,6 +63,10 @@ struct psst_network {
     // method: classical RK4 unless gen (then the explicit tableau tab)
     bool gen = false;
     psst::Tab tab{};
+    // sparse storage (per-instance path): ELL rows of synapses
+    bool sparse = false;
+    int32_t *d_spcol = nullptr;
+    float *d_spval = nullptr;
 };
 
 

@@ -215,7 +215,64 @@ struct WGSyn {
     int n, n_pn, ld, nch, NCG, r4, cg;
     int R;                     // resident columns per chunk (CW = whole matrix in LDS)
     bool gabab;
+    bool sparse;               // conductances in sparse rows (sp_col, sp_val)
+    const int32_t *sp_col;
+    const float *sp_val;
+    int sp_kf, sp_kb;
 };
+
+// Sparse rows: postsynaptic row i's synapses e = k0 .. k1-1 (sorted by
+// presynaptic column, padded with the last column and g = 0), entry e at
+// e * ld + i.  The products are summed in the fixed structure of the dense
+// form -- each 64-column chunk's partial in column order from 0, partials
+// added in chunk order, class by class -- and an absent synapse adds an exact
+// zero there, so the totals equal the dense ones bit for bit.  split: first
+// column of the second class (n_pn for the fast matrix; past every column for
+// the slow matrix, one class).
+template <int U>
+__device__ __forceinline__ void sparse_row(const int32_t *col, const float *val, int ld, int i,
+                                           int k0, int k1, const double *x, int split,
+                                           double &t0, double &t1)
+{
+    typedef __attribute__((address_space(1))) const int32_t gint;
+    typedef __attribute__((address_space(1))) const float gflt;
+    gint *C = (gint *)col;
+    gflt *G = (gflt *)val;
+    lds_double *X = (lds_double *)x;
+    double cur = 0.0;
+    int key = -1;                  // chunk of the running partial (class 1 keys offset)
+    for (int e = k0; e < k1; e += U) {
+        int j[U];
+        float g[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ee = min(e + u, k1 - 1);
+            j[u] = C[(int64_t)ee * ld + i];
+            g[u] = G[(int64_t)ee * ld + i];
+        }
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = X[j[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (e + u >= k1) break;
+            const int kk = j[u] < split ? j[u] / CW : (1 << 24) + (j[u] - split) / CW;
+            if (kk != key) {
+                if (key >= 0) {
+                    if (key < (1 << 24)) t0 += cur;
+                    else t1 += cur;
+                }
+                cur = 0.0;
+                key = kk;
+            }
+            cur = fma((double)g[u], xv[u], cur);
+        }
+    }
+    if (key >= 0) {
+        if (key < (1 << 24)) t0 += cur;
+        else t1 += cur;
+    }
+}
 
 // Synaptic sums (nS) at stage input Y for the calling thread's neurons
 // i = tid + k * BS: write the activations, sync, form the chunk partials, sync,
@@ -225,6 +282,35 @@ __device__ __forceinline__ void syn_sums(const WGSyn &w, const Kin &K, const dou
                                          double (&sa)[NPT], double (&sg)[NPT], double (&sb)[NPT])
 {
     const int tid = threadIdx.x;
+    if (w.sparse) {
+        // activations, barrier, each thread its own rows, barrier (the
+        // activations are rewritten at the next stage)
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int i = tid + k * BS;
+            if (i < w.n) {
+                w.xf[i] = Y[k][YS];
+                if (w.gabab && i >= w.n_pn) w.xb[i - w.n_pn] = gabab_act(Y[k][YG], K);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int i = tid + k * BS;
+            double a = 0.0, g = 0.0, b = 0.0, unused = 0.0;
+            if (i < w.n) {
+                sparse_row<8>(w.sp_col, w.sp_val, w.ld, i, 0, w.sp_kf, w.xf, w.n_pn, a, g);
+                if (w.sp_kb > 0)
+                    sparse_row<8>(w.sp_col, w.sp_val, w.ld, i, w.sp_kf, w.sp_kf + w.sp_kb, w.xb,
+                                  1 << 30, b, unused);
+            }
+            sa[k] = a;
+            sg[k] = g;
+            sb[k] = b;
+        }
+        __syncthreads();
+        return;
+    }
     if (w.nch == 0) {      // no synapses (uniform over the workgroup: no barriers)
 #pragma unroll
         for (int k = 0; k < NPT; ++k) sa[k] = sg[k] = sb[k] = 0.0;
@@ -410,7 +496,13 @@ __device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int6
     w.n_pn = d.n_pn;
     w.ld = d.ld;
     w.gabab = (d.flags & DESC_GABAB) != 0;
-    w.ch = (d.flags & DESC_NOSYN) ? Chunks{0, 0, 0} : chunks_of(d.n, d.n_pn, w.gabab);
+    w.sparse = (d.flags & DESC_SPARSE) != 0;
+    w.sp_col = d.sp_col;
+    w.sp_val = d.sp_val;
+    w.sp_kf = d.sp_kf;
+    w.sp_kb = d.sp_kb;
+    w.ch = (d.flags & (DESC_NOSYN | DESC_SPARSE)) ? Chunks{0, 0, 0}
+                                                  : chunks_of(d.n, d.n_pn, w.gabab);
     w.nch = w.ch.na + w.ch.ng + w.ch.nb;
     w.xf = lds_d;
     w.xb = lds_d + d.ld;

@@ -33,8 +33,9 @@ EXPORTS = (
     "psst_batch_create", "psst_batch_destroy", "psst_batch_layout",
     "psst_batch_state_init", "psst_integrate_batch", "psst_batch_poll",
     "psst_batch_describe", "psst_adjoint", "psst_network_grad_size",
-    "psst_network_set_tableau", "psst_batch_set_tableau",
+    "psst_network_set_tableau", "psst_batch_set_tableau", "psst_network_create_storage",
 )
+STORAGE_AUTO, STORAGE_DENSE, STORAGE_SPARSE = 0, 1, 2
 
 
 class PsstError(RuntimeError):
@@ -127,6 +128,8 @@ def lib():
                                    vp, vp, i32, vp]),
             "psst_network_grad_size": (i32, [vp, C.POINTER(i64)]),
             "psst_network_set_tableau": (i32, [vp, C.POINTER(Tableau)]),
+            "psst_network_create_storage": (i32, [C.POINTER(NeuronParams), i32, C.POINTER(Pathway),
+                                                  i32, C.POINTER(Kinetics), i32, C.POINTER(vp)]),
             "psst_batch_set_tableau": (i32, [vp, C.POINTER(Tableau)]),
         }
         for name, (res, args) in sig.items():
@@ -197,8 +200,9 @@ class Network:
             pass
 
 
-def network_create(net) -> Network:
-    """psst_network_create from a workload ``Network`` (host arrays)."""
+def network_create(net, storage: Optional[int] = None) -> Network:
+    """psst_network_create (or, with a storage choice,
+    psst_network_create_storage) from a workload ``Network`` (host arrays)."""
     keep = []
     vecs = {}
     for k in ("C_m", "g_Na", "g_K", "g_L", "E_Na", "E_K", "E_L"):
@@ -220,8 +224,13 @@ def network_create(net) -> Network:
     for t in range(3):
         kin[t] = Kinetics(*[float(x) for x in kt[t]])
     h = C.c_void_p()
-    _check(lib().psst_network_create(C.byref(p), int(net.n), paths, len(net.pathways), kin,
-                                     C.byref(h)))
+    if storage is None:
+        _check(lib().psst_network_create(C.byref(p), int(net.n), paths, len(net.pathways), kin,
+                                         C.byref(h)))
+    else:
+        _check(lib().psst_network_create_storage(C.byref(p), int(net.n), paths,
+                                                 len(net.pathways), kin, int(storage),
+                                                 C.byref(h)))
     gs = C.c_int64()
     _check(lib().psst_network_grad_size(h, C.byref(gs)))
     return Network(h, int(net.n), int(net.n_pn), int(gs.value), net)

@@ -267,6 +267,23 @@ def config3(n_instances: int = 4096, first: int = 0) -> List[Instance]:
     return [config3_instance(b) for b in range(first, first + n_instances)]
 
 
+def config3_sparse_instance(b: int, p: float = 0.1) -> Instance:
+    """Instance b of the sparse batched workload: the batched recipe's size,
+    jitter, stimulus and V0 with connection probability p and g ~ U(0, 0.25 /
+    p) nS, so the expected conductance onto a neuron matches the p = 0.5
+    recipe (its own generator streams: workload id 6)."""
+    cfg = 6
+    n = config3_size(b)
+    k = n // 4
+    x = float(rng_for(cfg, b, S_JITTER).lognormal(0.0, 0.1))
+    net = all_pairs_network(cfg, b, 3 * k, k, g_max=0.25 / p, p=p, g_scale=x)
+    return Instance(net, _v0(cfg, b, n), _const_stim(cfg, b, n))
+
+
+def config3_sparse(n_instances: int = 4096, p: float = 0.1, first: int = 0) -> List[Instance]:
+    return [config3_sparse_instance(b, p) for b in range(first, first + n_instances)]
+
+
 def config3_uncoupled(n_instances: int = 4096, first: int = 0) -> List[Instance]:
     """The batched workload with every synapse removed (independent neurons,
     the compute-only counterpart): instance b keeps its size, neuron
