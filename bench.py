@@ -305,10 +305,12 @@ def main():
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter files of a "
                          "bench run (same --workload/--chunk/--instances) and of a "
                          "--copy-calibration run into profiles/KERNEL_traffic.txt and exit")
-    ap.add_argument("--workload", choices=("batched", "large", "uncoupled"), default="batched",
+    ap.add_argument("--workload", choices=("batched", "large", "uncoupled", "sparse"),
+                    default="batched",
                     help="batched: the 4096-network batch (the default line); large: the "
                          "16384-neuron network x 64 trials on the per-stage MFMA path; "
-                         "uncoupled: the batch with every synapse removed (compute only)")
+                         "uncoupled: the batch with every synapse removed (compute only); "
+                         "sparse: the batch at connection probability 0.1, sparse storage")
     ap.add_argument("--method", default="rk4",
                     help="explicit Runge-Kutta method of the batched/uncoupled workloads: "
                          "one of the named tableaux (rk4 = the classical kernels)")
@@ -362,8 +364,14 @@ def main():
 
     # ---------------- workload: batched config -----------------------------
     uncoupled = args.workload == "uncoupled"
+    sparse = args.workload == "sparse"
     t0 = time.time()
-    insts = W.config3_uncoupled(args.instances) if uncoupled else W.config3(args.instances)
+    if uncoupled:
+        insts = W.config3_uncoupled(args.instances)
+    elif sparse:
+        insts = W.config3_sparse(args.instances, 0.1)
+    else:
+        insts = W.config3(args.instances)
     sizes = np.array([i.net.n for i in insts])
     sum_n = int(sizes.sum())
     sum_n2 = int((sizes.astype(np.int64) ** 2).sum())
@@ -429,6 +437,35 @@ def main():
                 "kernel": "rk4_wg_kernel (batched persistent RK4)",
                 "avg_launch_ms": round(1e3 * avg_launch_s, 3),
                 "algorithmic_bytes_per_launch": bytes_per_launch}
+    if sparse:
+        # sparse rows: 8 bytes (column, g) per synapse per stage instead of 4
+        # per matrix entry; the same instances with dense storage alongside
+        nnz = sum(int(sum((p.mask != 0).sum() for p in i.net.pathways)) for i in insts)
+        bytes_per_rk4 = 4 * stages * 2 * nnz + 80 * sum_n
+        bytes_per_launch = bytes_per_rk4 * args.chunk
+        achieved = bytes_per_launch / avg_launch_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "rk4_wg_kernel (batched persistent RK4, sparse rows)",
+                    "avg_launch_ms": round(1e3 * avg_launch_s, 3),
+                    "algorithmic_bytes_per_launch": bytes_per_launch, "synapses": nnz}
+        dnets = [psst.network_create(i.net, storage=psst.STORAGE_DENSE) for i in insts]
+        dbatch = psst.batch_create(dnets)
+        dst = torch.zeros_like(states)
+        psst.batch_state_init(dbatch, v0, dst)
+        psst.integrate_batch(dbatch, dst, stim, DT, args.chunk, 0)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for k in range(args.steps):
+            psst.integrate_batch(dbatch, dst, stim, DT, args.chunk, (k + 1) * args.chunk)
+        ev1.record(stream)
+        ev1.synchronize()
+        dms = ev0.elapsed_time(ev1) / args.steps
+        roofline["dense_storage_same_instances"] = {
+            "value": sum_n * args.chunk / (dms / 1e3), "avg_launch_ms": round(dms, 3)}
+        log(f"same instances, dense storage: {roofline['dense_storage_same_instances']['value']:.3e}"
+            " neuron-steps/s")
+        del dbatch, dnets
     if uncoupled:
         # no conductances: the float64 right-hand side is the work; flops per
         # launch come from the float64 VALU flop counters of this kernel
@@ -446,7 +483,7 @@ def main():
 
     # ---------------- plain form: one network per launch ------------------
     plain = None
-    if not args.no_plain and not uncoupled:
+    if not args.no_plain and not uncoupled and not sparse:
         pick = stratified(sizes, min(args.plain_instances, len(insts)))
         tot_ns, tot_t = 0, 0.0
         for b in pick:
@@ -467,7 +504,7 @@ def main():
                            "steps each, one psst_integrate launch per network"}
         log(f"plain: {plain['value']:.3e} neuron-steps/s")
 
-    adjoint = None if (args.no_adjoint or uncoupled) else \
+    adjoint = None if (args.no_adjoint or uncoupled or sparse) else \
         bench_adjoint(args, torch, psst, W, dev, stream)
 
     # ---------------- CPU baseline (oracle) and parity spot check ---------
@@ -542,6 +579,10 @@ def main():
         "config": {"workload": (f"uncoupled: {len(insts)} batched instances of 60-480 HH "
                                 "neurons with no synapses, I ~ U(0,2) nA, dt 0.01 ms")
                    if uncoupled else
+                   (f"sparse: {len(insts)} independent antennal-lobe-shaped HH networks, "
+                    "60-480 neurons, Bernoulli(0.1) ACh + fast-GABA synapses, "
+                    "g ~ U(0,2.5) nS x LogNormal(0,0.1), sparse storage, dt 0.01 ms")
+                   if sparse else
                    (f"batched: {len(insts)} independent antennal-lobe-shaped HH "
                     "networks, 60-480 neurons (PN:LN 3:1), Bernoulli(0.5) ACh + "
                     "fast-GABA synapses, g ~ U(0,0.5) nS x LogNormal(0,0.1), "

@@ -216,6 +216,7 @@ struct WGSyn {
     int R;                     // resident columns per chunk (CW = whole matrix in LDS)
     bool gabab;
     bool sparse;               // conductances in sparse rows (sp_col, sp_val)
+    bool sp_lds;               // ... copied to LDS for the launch
     const int32_t *sp_col;
     const float *sp_val;
     int sp_kf, sp_kb;
@@ -229,13 +230,13 @@ struct WGSyn {
 // zero there, so the totals equal the dense ones bit for bit.  split: first
 // column of the second class (n_pn for the fast matrix; past every column for
 // the slow matrix, one class).
-template <int U>
+template <int U, int AS>
 __device__ __forceinline__ void sparse_row(const int32_t *col, const float *val, int ld, int i,
                                            int k0, int k1, const double *x, int split,
                                            double &t0, double &t1)
 {
-    typedef __attribute__((address_space(1))) const int32_t gint;
-    typedef __attribute__((address_space(1))) const float gflt;
+    typedef __attribute__((address_space(AS))) const int32_t gint;
+    typedef __attribute__((address_space(AS))) const float gflt;
     gint *C = (gint *)col;
     gflt *G = (gflt *)val;
     lds_double *X = (lds_double *)x;
@@ -299,10 +300,17 @@ __device__ __forceinline__ void syn_sums(const WGSyn &w, const Kin &K, const dou
             const int i = tid + k * BS;
             double a = 0.0, g = 0.0, b = 0.0, unused = 0.0;
             if (i < w.n) {
-                sparse_row<8>(w.sp_col, w.sp_val, w.ld, i, 0, w.sp_kf, w.xf, w.n_pn, a, g);
-                if (w.sp_kb > 0)
-                    sparse_row<8>(w.sp_col, w.sp_val, w.ld, i, w.sp_kf, w.sp_kf + w.sp_kb, w.xb,
-                                  1 << 30, b, unused);
+                if (w.sp_lds) {
+                    sparse_row<8, 3>(w.sp_col, w.sp_val, w.ld, i, 0, w.sp_kf, w.xf, w.n_pn, a, g);
+                    if (w.sp_kb > 0)
+                        sparse_row<8, 3>(w.sp_col, w.sp_val, w.ld, i, w.sp_kf, w.sp_kf + w.sp_kb,
+                                         w.xb, 1 << 30, b, unused);
+                } else {
+                    sparse_row<8, 1>(w.sp_col, w.sp_val, w.ld, i, 0, w.sp_kf, w.xf, w.n_pn, a, g);
+                    if (w.sp_kb > 0)
+                        sparse_row<8, 1>(w.sp_col, w.sp_val, w.ld, i, w.sp_kf, w.sp_kf + w.sp_kb,
+                                         w.xb, 1 << 30, b, unused);
+                }
             }
             sa[k] = a;
             sg[k] = g;
@@ -514,6 +522,22 @@ __device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int6
     const int64_t room = lds_bytes - (int64_t)sizeof(double) * (2 + w.nch) * d.ld;
     const int64_t per_col = (int64_t)sizeof(float) * w.nch * d.ld;
     int64_t R = per_col == 0 ? CW : (room > 0 ? room / per_col : 0);
+    // sparse rows: the whole ELL (columns then values) into LDS when it fits
+    w.sp_lds = false;
+    if (w.sparse) {
+        const int64_t ents = (int64_t)(d.sp_kf + d.sp_kb) * d.ld;
+        if (8 * ents <= room) {
+            int32_t *lc = reinterpret_cast<int32_t *>(gl);
+            float *lv = reinterpret_cast<float *>(lc + ents);
+            for (int64_t e = threadIdx.x; e < ents; e += BS) {
+                lc[e] = d.sp_col[e];
+                lv[e] = d.sp_val[e];
+            }
+            w.sp_col = lc;
+            w.sp_val = lv;
+            w.sp_lds = true;
+        }
+    }
     w.R = (int)(R < CW ? R : CW);
     const int tid = threadIdx.x;
     if (w.R > 0) {
