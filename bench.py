@@ -219,6 +219,65 @@ def bench_large(args, torch, psst, W, dev, stream):
     print(json.dumps(out), flush=True)
 
 
+def bench_streamed(args, torch, psst, W, dev, stream):
+    """The batched workload for steps x chunk RK4 steps with V after every
+    step (1.1 M floats per step) and spikes streamed to host memory in chunks
+    of --chunk steps, against the same steps with records on the device
+    every 100 steps."""
+    insts = W.config3(args.instances)
+    sum_n = int(sum(i.net.n for i in insts))
+    nets = [psst.network_create(i.net) for i in insts]
+    batch = psst.batch_create(nets)
+    v0 = torch.from_numpy(np.concatenate([i.v0 for i in insts])).to(dev)
+    stim = psst.pack_stimulus([i.stim for i in insts], dev)
+    st = torch.zeros(14 * sum_n, dtype=torch.float32, device=dev)
+    psst.batch_state_init(batch, v0, st)
+    n = args.steps * args.chunk
+    hv = np.empty((n, sum_n), np.float32)
+    hv.fill(0.0)             # resident host memory (first-touch page faults excluded)
+    hc = np.zeros(sum_n, np.int32)
+    hs = np.zeros((sum_n, SPIKE_CAP), np.float32)
+    # warm-up: one chunk streamed (the batch's streaming buffers are pinned
+    # once, on first use), then the timed run from the same initial state
+    psst.integrate_batch_streamed(batch, st, stim, DT, args.chunk, 0, args.chunk, 1,
+                                  hv[:args.chunk], hc, hs, SPIKE_CAP)
+    psst.batch_state_init(batch, v0, st)
+    hc[:] = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psst.integrate_batch_streamed(batch, st, stim, DT, n, 0, args.chunk, 1, hv, hc, hs,
+                                  SPIKE_CAP)
+    wall = time.perf_counter() - t0
+    # the same steps, records on the device every 100 steps
+    st2 = torch.zeros_like(st)
+    psst.batch_state_init(batch, v0, st2)
+    rows = args.chunk // REC_STRIDE
+    vt = torch.zeros((max(rows, 1), sum_n), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        psst.integrate_batch(batch, st2, stim, DT, args.chunk, args.chunk * k,
+                             psst.DeviceRecord(vt, REC_STRIDE, rows))
+    torch.cuda.synchronize()
+    wall2 = time.perf_counter() - t1
+    value = sum_n * n / wall
+    out = {"metric": METRIC, "value": value, "unit": "neuron-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * wall / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"streamed: the {len(insts)}-network batch, V after every "
+                                  f"step and spikes drained to host memory in chunks of "
+                                  f"{args.chunk} steps", "rk4_steps": n, "neurons": sum_n,
+                      "host_trace_bytes": int(hv.nbytes)},
+           "trace_rate_GBps": hv.nbytes / wall / 1e9,
+           "device_records_every_100_steps": {"value": sum_n * n / wall2,
+                                              "unit": "neuron-steps/s"},
+           "streaming_overhead": wall / wall2 - 1.0}
+    log(f"streamed: {value:.3e} neuron-steps/s ({hv.nbytes / 1e9:.1f} GB of trace at "
+        f"{hv.nbytes / wall / 1e9:.1f} GB/s); device records only: {sum_n * n / wall2:.3e}")
+    print(json.dumps(out), flush=True)
+
+
 def bench_adjoint(args, torch, psst, W, dev, stream):
     """Adjoint workload: trials of the 120-neuron network sharing one set of
     conductances; forward with checkpoints every K steps and the V trace,
@@ -305,12 +364,14 @@ def main():
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter files of a "
                          "bench run (same --workload/--chunk/--instances) and of a "
                          "--copy-calibration run into profiles/KERNEL_traffic.txt and exit")
-    ap.add_argument("--workload", choices=("batched", "large", "uncoupled", "sparse"),
+    ap.add_argument("--workload", choices=("batched", "large", "uncoupled", "sparse", "streamed"),
                     default="batched",
                     help="batched: the 4096-network batch (the default line); large: the "
                          "16384-neuron network x 64 trials on the per-stage MFMA path; "
                          "uncoupled: the batch with every synapse removed (compute only); "
-                         "sparse: the batch at connection probability 0.1, sparse storage")
+                         "sparse: the batch at connection probability 0.1, sparse storage; "
+                         "streamed: the batch with its full V trace (every step) and spikes "
+                         "drained to host memory chunk by chunk")
     ap.add_argument("--method", default="rk4",
                     help="explicit Runge-Kutta method of the batched/uncoupled workloads: "
                          "one of the named tableaux (rk4 = the classical kernels)")
@@ -360,6 +421,9 @@ def main():
 
     if args.workload == "large":
         bench_large(args, torch, psst, W, dev, stream)
+        return
+    if args.workload == "streamed":
+        bench_streamed(args, torch, psst, W, dev, stream)
         return
 
     # ---------------- workload: batched config -----------------------------

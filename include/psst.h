@@ -274,6 +274,36 @@ psst_status psst_adjoint(psst_batch *batch, const float *checkpoints, int32_t K,
 psst_status psst_network_grad_size(const psst_network *net, int64_t *n_entries);
 
 /* ------------------------------------------------------------------------ */
+/* Long runs streamed to host memory                                        */
+/* ------------------------------------------------------------------------ */
+
+/* psst_integrate_batch over n_steps in chunks of chunk_steps, the records of
+ * every chunk drained to host memory while the next chunk integrates (the
+ * paper's batches of time steps whose solution is moved off the device,
+ * "Circumventing memory constraints", item 2): two device record buffers and
+ * two pinned host staging buffers alternate; the GPU integrates chunk c + 1
+ * on the caller's stream while chunk c is copied out on a second stream and
+ * then into the caller's arrays by the host.  Device memory is bounded by two
+ * chunks, whatever n_steps.
+ *   host_v: host [n_steps / rec_stride][n_total] floats, V after every
+ *     rec_stride-th step (rows as in psst_record), or NULL;
+ *   host_spike_count: host [n_total] int32, spikes of the whole run (added to
+ *     the values it holds), or NULL; host_spike_t: host
+ *     [n_total][spike_cap] ms, each neuron's times appended after its
+ *     existing count, those beyond spike_cap dropped (counted).
+ * rec_stride must divide chunk_steps, and step0 must be a multiple of it.
+ * Returns when every record is in host memory (the call is synchronous);
+ * states holds the state after the last step.  Not for batches on the
+ * per-stage path (UNSUPPORTED).  Errors: INVALID_ARGUMENT, OUT_OF_MEMORY,
+ * DEVICE, NONFINITE (checked once at the end). */
+psst_status psst_integrate_batch_streamed(psst_batch *batch, float *states,
+                                          const psst_stimulus *stim, float dt_ms,
+                                          int64_t n_steps, int64_t step0, int64_t chunk_steps,
+                                          int64_t rec_stride, float *host_v,
+                                          int32_t *host_spike_count, float *host_spike_t,
+                                          int32_t spike_cap, void *hip_stream);
+
+/* ------------------------------------------------------------------------ */
 /* Explicit Runge-Kutta tableaux                                             */
 /* ------------------------------------------------------------------------ */
 

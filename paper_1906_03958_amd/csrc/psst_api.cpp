@@ -592,6 +592,7 @@ static void batch_free(psst_batch *b)
     if (b->graph) hipGraphDestroy(b->graph);
     stage_batch_free(b->stage);
     adjoint_free(b->adj);
+    stream_bufs_free(b->strm);
     delete b;
 }
 
@@ -922,6 +923,24 @@ extern "C" psst_status psst_integrate_batch(psst_batch *b, float *states, const 
     for (auto &g : b->groups)
         args.push_back(group_args(b, g, states, stim, dt, n_steps, step0, rec, ckpt, K));
     return submit_graph(b, args, (hipStream_t)stream);
+}
+
+// The batch's launches without the graph (the streamed path issues one per
+// chunk while earlier chunks are in flight; changing the graph's parameters
+// would wait for them).
+psst_status batch_launch_direct(psst_batch *b, float *states, const psst_stimulus *stim, float dt,
+                                int64_t n_steps, int64_t step0, const psst_record *rec,
+                                void *stream)
+{
+    psst_status s = validate_common(dt, n_steps, step0, rec);
+    if (s != PSST_OK) return s;
+    if ((s = validate_stim(stim)) != PSST_OK) return s;
+    if (n_steps == 0) return PSST_OK;
+    for (auto &g : b->groups) {
+        WGArgs a = group_args(b, g, states, stim, dt, n_steps, step0, rec, nullptr, 1);
+        if ((s = launch_group(g, b->gen, a, (hipStream_t)stream)) != PSST_OK) return s;
+    }
+    return PSST_OK;
 }
 
 extern "C" psst_status psst_batch_poll(psst_batch *b, void *stream)

@@ -28,6 +28,8 @@ psst_status fail(psst_status s, const char *fmt, ...);
 struct StageNet;
 struct StageBatch;
 struct AdjWork;
+struct StreamBufs;
+void stream_bufs_free(StreamBufs *s);
 
 using psst::InstDesc;
 using psst::WGArgs;
@@ -96,10 +98,16 @@ struct psst_batch {
     std::vector<hipGraphNode_t> nodes;
     std::vector<WGArgs> node_args;
     AdjWork *adj = nullptr;         // adjoint workspace, sized on first use
+    StreamBufs *strm = nullptr;     // streaming buffers, sized on first use
     bool gen = false;               // method: classical RK4 unless gen
     psst::Tab tab{};
 };
 
+
+// Launch a per-instance batch's kernels directly on a stream (no graph).
+psst_status batch_launch_direct(psst_batch *b, float *states, const psst_stimulus *stim, float dt,
+                                int64_t n_steps, int64_t step0, const psst_record *rec,
+                                void *stream);
 
 // Discrete adjoint over a batch of per-instance networks (adjoint.hip).
 psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc *d_desc,

@@ -34,6 +34,7 @@ EXPORTS = (
     "psst_batch_state_init", "psst_integrate_batch", "psst_batch_poll",
     "psst_batch_describe", "psst_adjoint", "psst_network_grad_size",
     "psst_network_set_tableau", "psst_batch_set_tableau", "psst_network_create_storage",
+    "psst_integrate_batch_streamed",
 )
 STORAGE_AUTO, STORAGE_DENSE, STORAGE_SPARSE = 0, 1, 2
 
@@ -128,6 +129,8 @@ def lib():
                                    vp, vp, i32, vp]),
             "psst_network_grad_size": (i32, [vp, C.POINTER(i64)]),
             "psst_network_set_tableau": (i32, [vp, C.POINTER(Tableau)]),
+            "psst_integrate_batch_streamed": (i32, [vp, vp, C.POINTER(Stimulus), f32, i64, i64,
+                                                    i64, i64, vp, vp, vp, i32, vp]),
             "psst_network_create_storage": (i32, [C.POINTER(NeuronParams), i32, C.POINTER(Pathway),
                                                   i32, C.POINTER(Kinetics), i32, C.POINTER(vp)]),
             "psst_batch_set_tableau": (i32, [vp, C.POINTER(Tableau)]),
@@ -364,6 +367,26 @@ def integrate_batch(batch: Batch, states, stim: Optional[DeviceStimulus], dt_ms:
 
 def batch_poll(batch: Batch, stream=None):
     _check(lib().psst_batch_poll(batch.handle, _stream(stream)))
+
+
+def integrate_batch_streamed(batch: Batch, states, stim: Optional[DeviceStimulus],
+                             dt_ms: float, n_steps: int, step0: int, chunk_steps: int,
+                             rec_stride: int = 0, host_v: Optional[np.ndarray] = None,
+                             host_spike_count: Optional[np.ndarray] = None,
+                             host_spike_t: Optional[np.ndarray] = None, spike_cap: int = 0,
+                             stream=None):
+    """psst_integrate_batch_streamed: records land in host numpy arrays
+    (host_v float32 [n_steps // rec_stride, n_total], host_spike_count int32
+    [n_total], host_spike_t float32 [n_total, spike_cap]), C-contiguous."""
+    for a, dt in ((host_v, np.float32), (host_spike_count, np.int32), (host_spike_t, np.float32)):
+        if a is not None and (a.dtype != dt or not a.flags.c_contiguous):
+            raise PsstError(ERR_INVALID_ARGUMENT, "host arrays must be C-contiguous of the stated dtype")
+    s = None if stim is None else stim.c()
+    hp = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+    _check(lib().psst_integrate_batch_streamed(
+        batch.handle, _ptr(states), None if s is None else C.byref(s), float(dt_ms),
+        int(n_steps), int(step0), int(chunk_steps), int(rec_stride), hp(host_v),
+        hp(host_spike_count), hp(host_spike_t), int(spike_cap), _stream(stream)))
 
 
 def network_set_tableau(net: Network, tab=None):
