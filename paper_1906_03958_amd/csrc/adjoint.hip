@@ -22,6 +22,7 @@
 // float64 and folded into a float32 (value, compensation) pair per entry;
 // per-neuron gradients likewise.
 #include <cstdlib>
+#include <cstring>
 
 #include "runtime.h"
 #include "wg_common.h"
@@ -47,6 +48,7 @@ struct AdjArgs {
     int64_t lds_bytes;
     int32_t *flag;
     Tab tab;                    // method of the generic-step variants
+    int32_t mode;               // 0 choose, 1 no matrix-core contraction, 2 prefer it
 };
 
 // workspace layout of one instance (doubles), ld = padded neuron count
@@ -109,6 +111,114 @@ __device__ __forceinline__ double row_dot(V4 *row, const double *q, int n)
     return (s0 + s1) + (s2 + s3);
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// dL/dg of one segment on the matrix cores: for each synapse class the
+// product X^T Q over the segment's T stage records (rows j presynaptic,
+// columns i postsynaptic; x_j and q(i) as stashed by the reverse sweep), added
+// to the compensated accumulators.  Records go through LDS TT at a time; a
+// wavefront owns a strip of one 16-row tile by kStripTiles 16-column tiles
+// (v_mfma_f64_16x16x4f64: A lane l = X[row l%16][rec l/16], B lane l =
+// Q[rec l/16][col l%16], D lane l item r = [row 4r + l/16][col l%16]).
+constexpr int kStripTiles = 4;     // 16-column tiles per wavefront strip
+template <int BS>
+__device__ void contract_mma(const WsLayout &W, int T, int n, int n_pn, int n_ln, bool gabab,
+                             int ld, double *lds, int64_t room, float *gacc, int64_t half,
+                             int64_t sec_f)
+{
+    constexpr int NW = BS / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rt0 = (n_pn + 15) / 16, rt1 = (n_ln + 15) / 16, rt2 = gabab ? rt1 : 0;
+    const int CT = (n + 15) / 16;
+    const int CS = (CT + kStripTiles - 1) / kStripTiles;
+    const int strips = (rt0 + rt1 + rt2) * CS;
+    int TT = (int)(room / (5LL * ld)) & ~3;
+    TT = TT > 64 ? 64 : TT;
+    double *sx = lds;                          // [TT][2][ld]
+    double *sq = lds + (int64_t)TT * 2 * ld;   // [TT][3][ld]
+    for (int g0 = 0; g0 < strips; g0 += NW) {
+        const int sidx = g0 + wave;
+        const bool act = sidx < strips;
+        int ty = 0, trow = 0, c0 = 0;
+        if (act) {
+            const int rt = sidx / CS;
+            c0 = (sidx % CS) * kStripTiles;
+            if (rt < rt0) {
+                ty = 0;
+                trow = rt * 16;
+            } else if (rt < rt0 + rt1) {
+                ty = 1;
+                trow = n_pn + (rt - rt0) * 16;
+            } else {
+                ty = 2;
+                trow = (rt - rt0 - rt1) * 16;
+            }
+        }
+        const int row_end = ty == 0 ? n_pn : (ty == 1 ? n : n_ln);
+        const int xs = ty == 2 ? 1 : 0;
+        dbl4 acc[kStripTiles];
+#pragma unroll
+        for (int c = 0; c < kStripTiles; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int t0 = 0; t0 < T; t0 += TT) {
+            const int tn = T - t0 < TT ? T - t0 : TT;
+            __syncthreads();                   // previous block consumed
+            // stage records t0 .. t0 + TT - 1 as pairs of columns: every load
+            // in bounds (record index clamped, columns < ld), then entries past
+            // the segment, past n (q, fast x) or past n_ln (slow x) set to 0
+            const int ld2 = ld >> 1;
+            for (int e = tid; e < TT * ld2; e += BS) {
+                const int rr = e / ld2, c = 2 * (e - rr * ld2);
+                const bool ok = t0 + rr < T;
+                const int64_t rec = ok ? t0 + rr : T - 1;
+                const bool in0 = ok && c < n, in1 = ok && c + 1 < n;
+                const double2 xa = *reinterpret_cast<const double2 *>(W.Xs + (rec * 2 + 0) * ld + c);
+                double2 *dx0 = reinterpret_cast<double2 *>(sx + (rr * 2 + 0) * ld + c);
+                *dx0 = double2{in0 ? xa.x : 0.0, in1 ? xa.y : 0.0};
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    if (t == 2 && !gabab) break;
+                    const double2 qv = *reinterpret_cast<const double2 *>(W.Qs + (rec * 3 + t) * ld + c);
+                    *reinterpret_cast<double2 *>(sq + (rr * 3 + t) * ld + c) =
+                        double2{in0 ? qv.x : 0.0, in1 ? qv.y : 0.0};
+                }
+                if (gabab) {
+                    const double2 xb = *reinterpret_cast<const double2 *>(W.Xs + (rec * 2 + 1) * ld + c);
+                    *reinterpret_cast<double2 *>(sx + (rr * 2 + 1) * ld + c) =
+                        double2{(ok && c < n_ln) ? xb.x : 0.0, (ok && c + 1 < n_ln) ? xb.y : 0.0};
+                }
+            }
+            __syncthreads();
+            if (act) {
+                const int row = trow + (lane & 15);
+                for (int k0 = 0; k0 < TT; k0 += 4) {
+                    const int rk = k0 + (lane >> 4);
+                    const double av = row < row_end ? sx[(rk * 2 + xs) * ld + row] : 0.0;
+#pragma unroll
+                    for (int c = 0; c < kStripTiles; ++c) {
+                        const int col = (c0 + c) * 16 + (lane & 15);
+                        const double bv = col < n ? sq[(rk * 3 + ty) * ld + col] : 0.0;
+                        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[c], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < kStripTiles; ++c) {
+                const int col = (c0 + c) * 16 + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = trow + 4 * r + (lane >> 4);
+                    if (row < row_end && col < n) {
+                        const int64_t e = (ty == 2 ? sec_f : 0) + (int64_t)row * ld + col;
+                        comp_add(gacc + e, gacc + half + e, acc[c][r]);
+                    }
+                }
+            }
+        }
+    }
+}
+
 // One residue class of row_dot, for four lanes sharing a row: lane k of the
 // group sums row[i] q[i] over i = k, k + 4, ... below 4 ceil(n / 4) in index
 // order; the group then forms (s0 + s1) + (s2 + s3), so the result equals
@@ -159,7 +269,14 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
     const int64_t fwd_min = (int64_t)sizeof(double) * (2 + ch0.na + ch0.ng + ch0.nb) * ld;
     const int64_t lacc_bytes = (int64_t)sizeof(double) * (5 + 20) * ld +
                                (int64_t)sizeof(float) * 2 * rows * ld;
-    const bool lacc = lacc_bytes + fwd_min <= a.lds_bytes;
+    // mma: every conductance column in LDS for the recomputation and the
+    // transposed products, dL/dg contracted once per segment on the matrix
+    // cores; chosen when the whole matrix fits beside the q/product vectors
+    const int64_t res_bytes =
+        (int64_t)sizeof(float) * (ch0.na + ch0.ng + ch0.nb) * CW * ld;
+    const int64_t base5 = (int64_t)sizeof(double) * 5 * ld;
+    const bool mma = a.mode != 1 && rows > 0 && base5 + fwd_min + res_bytes <= a.lds_bytes;
+    const bool lacc = !mma && lacc_bytes + fwd_min <= a.lds_bytes;
     double *qb = lds_d;
     double *tb = lds_d + 3 * ld;
     double *recs = lds_d + 5 * ld;                         // lacc: [4][5][ld]
@@ -167,11 +284,13 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
     // staging of one step's stage data (40 doubles per neuron) when it takes
     // at most half of the LDS: one global round trip per reverse step
     const int64_t stage_d = 40LL * ld;
-    const bool staged = !lacc && (int64_t)sizeof(double) * (5 * ld + stage_d) * 2 <= a.lds_bytes;
+    const bool staged =
+        mma ? base5 + (int64_t)sizeof(double) * stage_d + fwd_min + res_bytes <= a.lds_bytes
+            : !lacc && (int64_t)sizeof(double) * (5 * ld + stage_d) * 2 <= a.lds_bytes;
     double *stg = lds_d + 5 * ld;
     const int64_t used_b = lacc ? lacc_bytes
                                 : (int64_t)sizeof(double) * (5 * ld + (staged ? stage_d : 0));
-    const WGSyn w = wg_setup<BS>(d, lds_d + used_b / sizeof(double), a.lds_bytes - used_b);
+    WGSyn w = wg_setup<BS>(d, lds_d + used_b / sizeof(double), a.lds_bytes - used_b);
     const bool gabab = w.gabab;
     const Kin K = load_kin(d.kin);
     const double dt = a.dt;
@@ -252,6 +371,7 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
             }
             double un[NVAR], usum[NVAR];
             double uh[GEN ? 4 : 1][NVAR];      // generic method: u of the later stages
+            constexpr int kStageUnroll = GEN ? 4 : 1;
 #pragma unroll
             for (int v = 0; v < NVAR; ++v) {
                 un[v] = 0.0;
@@ -260,7 +380,7 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
             // classical RK4: kbar_q = dt b_q lam + dt c_{q+1} u_{q+1}; a generic
             // tableau: kbar_q = dt b_q lam + dt sum_{r>q} a_rq u_r (stages last
             // to first, unrolled so the u_r stay in registers)
-#pragma unroll(GEN ? 4 : 1)
+#pragma unroll kStageUnroll
             for (int q = 3; q >= 0; --q) {
                 if (GEN && q >= a.tab.s) continue;
                 double Yq[NVAR], kb[NVAR], u[NVAR], qq[3], dg[3];
@@ -385,8 +505,12 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
         {
             const int q4 = ld >> 2;
             const int T = 4 * L;
-            const int items = lacc ? 0 : rows * q4;
-            if (staged) {
+            const int items = (lacc || mma) ? 0 : rows * q4;
+            if (mma) {
+                contract_mma<BS>(W, T, n, n_pn, n_ln, gabab, ld, lds_d + 5 * ld,
+                                 a.lds_bytes / (int64_t)sizeof(double) - 5LL * ld, gacc, half,
+                                 sec_f);
+            } else if (staged) {
                 constexpr int IPT = 8, TT = 8;
                 for (int base = 0; base < items; base += BS * IPT) {
                     double acc[IPT][4];
@@ -472,6 +596,12 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
             }
         }
         __syncthreads();
+        // the contraction used the conductances' LDS: copy them back for the
+        // next segment's recomputation
+        if (mma && seg > 0) {
+            w = wg_setup<BS>(d, lds_d + used_b / sizeof(double), a.lds_bytes - used_b);
+            __syncthreads();
+        }
     }
     if (lacc) {
         // value plane -> gacc[0 .. rows*ld), compensation plane -> gacc[half ..]
@@ -637,6 +767,10 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
     a.lds_bytes = (int64_t)lds;
     a.flag = flag;
     a.tab = tab;
+    // PSST_ADJ_MODE=lacc keeps dL/dg in the per-step LDS accumulator even when
+    // the matrix-core contraction is possible (comparison runs)
+    if (const char *e = std::getenv("PSST_ADJ_MODE"))
+        a.mode = std::strcmp(e, "lacc") == 0 ? 1 : (std::strcmp(e, "mma") == 0 ? 2 : 0);
     hipStream_t st = (hipStream_t)stream;
     void *args[] = {&a};
     if (n_steps > 0) HIPCHK(hipLaunchKernel(fn, dim3(n), dim3(bs), args, lds, st));
