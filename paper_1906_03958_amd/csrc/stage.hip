@@ -9,12 +9,13 @@
 //   acc += w_q f; Y_{q+1} = y + c_{q+1} dt f; X_{q+1} = x(Y_{q+1})
 // and at q = 3 the combine y <- y + dt/6 acc, spikes and records.
 //
-// GEMM tiling: a workgroup (4 wavefronts) owns 64 postsynaptic rows x NTILE
-// trials over the whole presynaptic axis, so each conductance is read from
-// HBM once per stage.  Tiles of 128 presynaptic columns are staged through
-// LDS (double-buffered) with the next tile loaded into registers -- 64 KiB in
-// flight per workgroup -- while the current one feeds v_mfma_f32_16x16x4f32.  Within a 16-column group, lane l at sub-step s
-// takes column 4 (l / 16) + s, so each lane reads its four A and four B
+// GEMM tiling: a workgroup (8 wavefronts, 4 x 2, for NTILE = 64) owns 64
+// postsynaptic rows x NTILE trials over the whole presynaptic axis, so each
+// conductance is read from HBM once per stage.  Tiles of 128 presynaptic
+// columns are staged through LDS (double-buffered) with the next tile loaded
+// into registers -- 64 KiB in flight per workgroup -- while the current one
+// feeds v_mfma_f32_16x16x4f32.  Within a 16-column group, lane l at sub-step
+// s takes column 4 (l / 16) + s, so each lane reads its four A and four B
 // values with one 16-byte LDS load; the column order of the sum is fixed, so
 // results are deterministic.
 //
@@ -71,8 +72,8 @@ __device__ __forceinline__ void write_x(const StageFixed &fx, float *X, int b, i
     if (fx.gabab && i >= fx.n_pn) xr[fx.ka + fx.kg + (i - fx.n_pn)] = (float)gabab_act(Y[YG], K);
 }
 
-// Per call: publish the call's control block, then stage-0 inputs from the
-// carried state.
+// Per call: publish the call's control block, then the stage-0 activations
+// from the carried state (stage 0 reads its input from the state itself).
 __global__ __launch_bounds__(256) void stage_prologue(StageFixed fx, StageCtl c, StageCtl *dctl)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) *dctl = c;
@@ -82,11 +83,8 @@ __global__ __launch_bounds__(256) void stage_prologue(StageFixed fx, StageCtl c,
         const int b = (int)(p / fx.n), i = (int)(p % fx.n);
         double y[NVS];
 #pragma unroll
-        for (int v = 0; v < NVS; ++v) {
+        for (int v = 0; v < NVS; ++v)
             y[v] = (double)c.state[(2 * v) * fx.nt + p] + (double)c.state[(2 * v + 1) * fx.nt + p];
-            fx.Yw[v * fx.nt + p] = y[v];
-            fx.accw[v * fx.nt + p] = 0.0;
-        }
         write_x(fx, fx.X0, b, i, y, K);
     }
 }
@@ -165,6 +163,11 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
             __syncthreads();
             if (t + 1 < ntile)
                 tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, kbeg + (t + 1) * KT);
+            // ask the scheduler to interleave the LDS operand reads of the next
+            // sub-step with the matrix-core instructions of the current one
+            // instead of grouping every read ahead of its products
+            // (single-wave small-GEMM strategy)
+            __builtin_amdgcn_iglp_opt(1);
 #pragma unroll
             for (int kk = 0; kk < KT / 16; ++kk) {
                 floatx4 a[BR], bv[BC];
@@ -214,16 +217,23 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
     const int64_t g = c.g;
     const int64_t nt = fx.nt;
     bool bad = false;
+    // without slow GABA the r, G planes have zero derivative: they are neither
+    // read nor written (the state keeps them as they are)
+    const int nv = fx.gabab ? NVS : YR;
     for (int p = tid; p < MT * NTILE; p += NTH) {
         const int il = p % MT, bl = p / MT;
         const int i = m0 + il, b = n0 + bl;
         if (i >= fx.n || b >= fx.B) continue;
         const int64_t gi = (int64_t)b * fx.n + i;
-        double Y[NVS], a[NVS];
+        // y: the step's start state; Y: this stage's input (y itself at stage
+        // 0); a: the weighted sum of the earlier stages' derivatives
+        double Y[NVS], a[NVS], y[NVS];
 #pragma unroll
         for (int v = 0; v < NVS; ++v) {
-            Y[v] = fx.Yw[v * nt + gi];
-            a[v] = fx.accw[v * nt + gi];
+            y[v] = v < nv ? (double)c.state[(2 * v) * nt + gi] + (double)c.state[(2 * v + 1) * nt + gi]
+                          : 0.0;
+            Y[v] = (q == 0 || v >= nv) ? y[v] : fx.Yw[v * nt + gi];
+            a[v] = (q == 0 || v >= nv) ? 0.0 : fx.accw[v * nt + gi];
         }
         Prm P = load_prm(fx.prm, fx.ld, i);
         double I = c.stim.i_const ? (double)c.stim.i_const[gi] : 0.0;
@@ -237,19 +247,17 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
         hh_rhs(Y, P, K, fx.cg * sa, fx.cg * sg, fx.cg * sb, fx.ci * I, i >= fx.n_pn,
                fx.gabab != 0, f);
         const double w = (q == 0 || q == 3) ? 1.0 : 2.0;
-        double y[NVS];
 #pragma unroll
-        for (int v = 0; v < NVS; ++v) {
-            a[v] += w * f[v];
-            y[v] = (double)c.state[(2 * v) * nt + gi] + (double)c.state[(2 * v + 1) * nt + gi];
-        }
+        for (int v = 0; v < NVS; ++v) a[v] += w * f[v];
         if (q < 3) {
             const double cq = (q == 2) ? dt : 0.5 * dt;
 #pragma unroll
             for (int v = 0; v < NVS; ++v) {
                 Y[v] = y[v] + cq * f[v];
-                fx.Yw[v * nt + gi] = Y[v];
-                fx.accw[v * nt + gi] = a[v];
+                if (v < nv) {
+                    fx.Yw[v * nt + gi] = Y[v];
+                    fx.accw[v * nt + gi] = a[v];
+                }
             }
             write_x(fx, Xn, b, i, Y, K);
         } else {
@@ -257,12 +265,11 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
             double chk = 0.0;
 #pragma unroll
             for (int v = 0; v < NVS; ++v) {
+                if (v >= nv) continue;
                 float hi, lo;
                 y[v] = split_store(y[v] + (dt / 6.0) * a[v], hi, lo);
                 c.state[(2 * v) * nt + gi] = hi;
                 c.state[(2 * v + 1) * nt + gi] = lo;
-                fx.Yw[v * nt + gi] = y[v];
-                fx.accw[v * nt + gi] = 0.0;
                 chk += y[v];
             }
             bad |= !finite_d(chk);
