@@ -91,7 +91,9 @@ __global__ __launch_bounds__(256) void stage_prologue(StageFixed fx, StageCtl c,
 
 __global__ void stage_advance(StageCtl *dctl) { dctl->g += 1; }
 
-// Global -> register part of the tile pipeline.
+// Global -> register part of the tile pipeline.  The conductances are read
+// once per stage and exceed the caches, so they are loaded non-temporally and
+// leave L2 and the infinity cache to the activations and the workspace.
 template <int GV, int XVT, int RPP>
 __device__ __forceinline__ void tile_load(floatx4 (&rg)[GV], floatx4 (&rx)[XVT], const float *G,
                                           const float *X, int Kp, int m0, int n0, int lr, int lk,
@@ -99,7 +101,8 @@ __device__ __forceinline__ void tile_load(floatx4 (&rg)[GV], floatx4 (&rx)[XVT],
 {
 #pragma unroll
     for (int u = 0; u < GV; ++u)
-        rg[u] = *reinterpret_cast<const floatx4 *>(G + (int64_t)(m0 + lr + RPP * u) * Kp + k0 + lk);
+        rg[u] = __builtin_nontemporal_load(
+            reinterpret_cast<const floatx4 *>(G + (int64_t)(m0 + lr + RPP * u) * Kp + k0 + lk));
 #pragma unroll
     for (int u = 0; u < XVT; ++u)
         rx[u] = *reinterpret_cast<const floatx4 *>(X + (int64_t)(n0 + lr + RPP * u) * Kp + k0 + lk);
