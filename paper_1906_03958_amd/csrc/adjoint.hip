@@ -127,6 +127,7 @@ __device__ void contract_mma(const WsLayout &W, int T, int n, int n_pn, int n_ln
                              int64_t sec_f)
 {
     constexpr int NW = BS / 64;
+    constexpr int SPW = BS >= 512 ? 2 : 4;     // strips per wavefront and pass
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int rt0 = (n_pn + 15) / 16, rt1 = (n_ln + 15) / 16, rt2 = gabab ? rt1 : 0;
     const int CT = (n + 15) / 16;
@@ -134,86 +135,114 @@ __device__ void contract_mma(const WsLayout &W, int T, int n, int n_pn, int n_ln
     const int strips = (rt0 + rt1 + rt2) * CS;
     int TT = (int)(room / (5LL * ld)) & ~3;
     TT = TT > 64 ? 64 : TT;
-    double *sx = lds;                          // [TT][2][ld]
-    double *sq = lds + (int64_t)TT * 2 * ld;   // [TT][3][ld]
-    for (int g0 = 0; g0 < strips; g0 += NW) {
-        const int sidx = g0 + wave;
-        const bool act = sidx < strips;
-        int ty = 0, trow = 0, c0 = 0;
-        if (act) {
-            const int rt = sidx / CS;
-            c0 = (sidx % CS) * kStripTiles;
-            if (rt < rt0) {
-                ty = 0;
-                trow = rt * 16;
-            } else if (rt < rt0 + rt1) {
-                ty = 1;
-                trow = n_pn + (rt - rt0) * 16;
-            } else {
-                ty = 2;
-                trow = (rt - rt0 - rt1) * 16;
-            }
-        }
-        const int row_end = ty == 0 ? n_pn : (ty == 1 ? n : n_ln);
-        const int xs = ty == 2 ? 1 : 0;
-        dbl4 acc[kStripTiles];
+    // explicit address spaces: global loads may then pass LDS stores
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) const d2v gdbl2;
+    typedef __attribute__((address_space(3))) d2v ldbl2;
+    typedef __attribute__((address_space(3))) const double ldbl;
+    ldbl *sx = (ldbl *)lds;                          // [TT][2][ld]
+    ldbl *sq = (ldbl *)(lds + (int64_t)TT * 2 * ld);   // [TT][3][ld]
+    // each pass over the records serves NW * SPW strips: a wavefront keeps the
+    // accumulators of SPW strips, so a record block is staged once per pass
+    for (int g0 = 0; g0 < strips; g0 += NW * SPW) {
+        int ty[SPW], trow[SPW], c0[SPW];
+        bool act[SPW];
+        dbl4 acc[SPW][kStripTiles];
 #pragma unroll
-        for (int c = 0; c < kStripTiles; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int sp = 0; sp < SPW; ++sp) {
+            const int sidx = g0 + sp * NW + wave;
+            act[sp] = sidx < strips;
+            ty[sp] = 0;
+            trow[sp] = 0;
+            c0[sp] = 0;
+            if (act[sp]) {
+                const int rt = sidx / CS;
+                c0[sp] = (sidx % CS) * kStripTiles;
+                if (rt < rt0) {
+                    trow[sp] = rt * 16;
+                } else if (rt < rt0 + rt1) {
+                    ty[sp] = 1;
+                    trow[sp] = n_pn + (rt - rt0) * 16;
+                } else {
+                    ty[sp] = 2;
+                    trow[sp] = (rt - rt0 - rt1) * 16;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kStripTiles; ++c) acc[sp][c] = dbl4{0.0, 0.0, 0.0, 0.0};
+        }
         for (int t0 = 0; t0 < T; t0 += TT) {
             const int tn = T - t0 < TT ? T - t0 : TT;
             __syncthreads();                   // previous block consumed
-            // stage records t0 .. t0 + TT - 1 as pairs of columns: every load
-            // in bounds (record index clamped, columns < ld), then entries past
-            // the segment, past n (q, fast x) or past n_ln (slow x) set to 0
-            const int ld2 = ld >> 1;
-            for (int e = tid; e < TT * ld2; e += BS) {
-                const int rr = e / ld2, c = 2 * (e - rr * ld2);
-                const bool ok = t0 + rr < T;
-                const int64_t rec = ok ? t0 + rr : T - 1;
-                const bool in0 = ok && c < n, in1 = ok && c + 1 < n;
-                const double2 xa = *reinterpret_cast<const double2 *>(W.Xs + (rec * 2 + 0) * ld + c);
-                double2 *dx0 = reinterpret_cast<double2 *>(sx + (rr * 2 + 0) * ld + c);
-                *dx0 = double2{in0 ? xa.x : 0.0, in1 ? xa.y : 0.0};
+            // stage records t0 .. t0 + tn - 1: the x and q blocks of these
+            // records are contiguous in the workspace and in LDS, so this is a
+            // flat copy with SU loads in flight per thread.  Entries never
+            // written (columns past n, slow x past n_ln) are copied too but
+            // never used: the operand reads below mask them.
+            {
+                constexpr int SU = 8;
+                const int nx2 = tn * ld;                 // double2 of the x block
+                const int ntot = nx2 + tn * 3 * ld / 2;  // plus the q block
+                gdbl2 *gx = (gdbl2 *)(W.Xs + (int64_t)t0 * 2 * ld);
+                gdbl2 *gq = (gdbl2 *)(W.Qs + (int64_t)t0 * 3 * ld);
+                ldbl2 *lx = (ldbl2 *)lds;
+                ldbl2 *lq = (ldbl2 *)(lds + (int64_t)TT * 2 * ld);
+                // indices past the block are clamped to its last pair: those
+                // lanes load and store that pair's own value again, so every
+                // access is in bounds and no branch keeps a load from issuing
+                for (int e0 = tid; e0 < ntot; e0 += SU * BS) {
+                    d2v v[SU];
 #pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    if (t == 2 && !gabab) break;
-                    const double2 qv = *reinterpret_cast<const double2 *>(W.Qs + (rec * 3 + t) * ld + c);
-                    *reinterpret_cast<double2 *>(sq + (rr * 3 + t) * ld + c) =
-                        double2{in0 ? qv.x : 0.0, in1 ? qv.y : 0.0};
-                }
-                if (gabab) {
-                    const double2 xb = *reinterpret_cast<const double2 *>(W.Xs + (rec * 2 + 1) * ld + c);
-                    *reinterpret_cast<double2 *>(sx + (rr * 2 + 1) * ld + c) =
-                        double2{(ok && c < n_ln) ? xb.x : 0.0, (ok && c + 1 < n_ln) ? xb.y : 0.0};
+                    for (int u = 0; u < SU; ++u) {
+                        const int e = e0 + u * BS < ntot ? e0 + u * BS : ntot - 1;
+                        v[u] = e < nx2 ? gx[e] : gq[e - nx2];
+                    }
+#pragma unroll
+                    for (int u = 0; u < SU; ++u) {
+                        const int e = e0 + u * BS < ntot ? e0 + u * BS : ntot - 1;
+                        ldbl2 *dst = e < nx2 ? lx + e : lq + (e - nx2);
+                        *dst = v[u];
+                    }
                 }
             }
             __syncthreads();
-            if (act) {
-                const int row = trow + (lane & 15);
-                for (int k0 = 0; k0 < TT; k0 += 4) {
+            // T = 4 L, so every block holds whole groups of four records
+#pragma unroll
+            for (int sp = 0; sp < SPW; ++sp) {
+                if (!act[sp]) continue;
+                const int row = trow[sp] + (lane & 15);
+                const int row_end = ty[sp] == 0 ? n_pn : (ty[sp] == 1 ? n : n_ln);
+                const int xs = ty[sp] == 2 ? 1 : 0;
+                for (int k0 = 0; k0 < tn; k0 += 4) {
                     const int rk = k0 + (lane >> 4);
                     const double av = row < row_end ? sx[(rk * 2 + xs) * ld + row] : 0.0;
 #pragma unroll
                     for (int c = 0; c < kStripTiles; ++c) {
-                        const int col = (c0 + c) * 16 + (lane & 15);
-                        const double bv = col < n ? sq[(rk * 3 + ty) * ld + col] : 0.0;
-                        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[c], 0, 0, 0);
+                        const int col = (c0[sp] + c) * 16 + (lane & 15);
+                        const double bv = col < n ? sq[(rk * 3 + ty[sp]) * ld + col] : 0.0;
+                        acc[sp][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[sp][c], 0, 0, 0);
                     }
                 }
             }
         }
-        if (act) {
+#pragma unroll
+        for (int sp = 0; sp < SPW; ++sp) {
+            if (!act[sp]) continue;
+            const int row_end = ty[sp] == 0 ? n_pn : (ty[sp] == 1 ? n : n_ln);
 #pragma unroll
             for (int c = 0; c < kStripTiles; ++c) {
-                const int col = (c0 + c) * 16 + (lane & 15);
+                const int col = (c0[sp] + c) * 16 + (lane & 15);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = trow + 4 * r + (lane >> 4);
+                    const int row = trow[sp] + 4 * r + (lane >> 4);
                     if (row < row_end && col < n) {
-                        const int64_t e = (ty == 2 ? sec_f : 0) + (int64_t)row * ld + col;
-                        comp_add(gacc + e, gacc + half + e, acc[c][r]);
+                        const int64_t e = (ty[sp] == 2 ? sec_f : 0) + (int64_t)row * ld + col;
+                        comp_add(gacc + e, gacc + half + e, acc[sp][c][r]);
                     }
                 }
+                // one tile at a time: keeps the scheduler from hoisting every
+                // tile's accumulator loads (and their addresses) at once
+                __asm__ volatile("" ::: "memory");
             }
         }
     }
@@ -382,7 +411,18 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
             // to first, unrolled so the u_r stay in registers)
 #pragma unroll kStageUnroll
             for (int q = 3; q >= 0; --q) {
-                if (GEN && q >= a.tab.s) continue;
+                if (GEN && q >= a.tab.s) {
+                    // a stage the method lacks: its records enter the segment
+                    // contraction as zeros (the workspace keeps older contents)
+                    if (!lacc && own) {
+                        const int64_t rz = (ls - s0) * 4 + q;
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) W.Qs[(rz * 3 + t) * ld + i] = 0.0;
+                        W.Xs[(rz * 2 + 0) * ld + i] = 0.0;
+                        if (gabab && is_ln) W.Xs[(rz * 2 + 1) * ld + (i - n_pn)] = 0.0;
+                    }
+                    continue;
+                }
                 double Yq[NVAR], kb[NVAR], u[NVAR], qq[3], dg[3];
 #pragma unroll
                 for (int v = 0; v < NVAR; ++v) {

@@ -188,3 +188,46 @@ def test_tableau_adjoint_matches_oracle(name):
             nrm = np.linalg.norm(got - r) / np.linalg.norm(r)
             _say(f"  trial {t} {key}: norm rel err {nrm:.2e}")
             assert nrm <= 1e-3, (name, t, key, nrm)
+
+
+def test_tableau_adjoint_after_rk4_on_the_same_batch():
+    """A method with fewer stages than RK4, differentiated on a batch whose
+    workspace still holds an RK4 adjoint's stage records: the stages the
+    method lacks must add nothing to dL/dg (against the oracle's adjoint of
+    the same method)."""
+    import torch
+    from paper_1906_03958_amd import psst
+    B, n_steps, K = 2, 160, 40
+    hidden, ev, i_nA, v0 = W.config5(B)
+    dev = torch.device("cuda:0")
+    net = psst.network_create(ev)
+    batch = psst.batch_create([net] * B)
+    nt = batch.n_total
+    stim = psst.DeviceStimulus(torch.from_numpy(i_nA.ravel()).to(dev))
+    dl = (np.random.default_rng(12).standard_normal((n_steps, nt)) * 1e-3).astype(np.float32)
+    gs = net.grad_size
+    outs = {}
+    for name in ("rk4", "heun"):
+        if name != "rk4":
+            psst.batch_set_tableau(batch, W.TABLEAUX[name])
+        st = torch.zeros(14 * nt, dtype=torch.float32, device=dev)
+        psst.batch_state_init(batch, torch.from_numpy(v0.ravel()).to(dev), st)
+        ck = torch.zeros(((n_steps + K - 1) // K, 14 * nt), dtype=torch.float32, device=dev)
+        psst.integrate_batch(batch, st, stim, 0.01, n_steps, 0, None, ck, K)
+        gg = torch.zeros(B * gs, dtype=torch.float32, device=dev)
+        gna = torch.zeros(nt, dtype=torch.float32, device=dev)
+        gk, gl = torch.zeros_like(gna), torch.zeros_like(gna)
+        _say(f"adjoint {name} on the shared batch: {B} trials x {ev.n} neurons, {n_steps} steps")
+        psst.adjoint(batch, ck, K, stim, 0.01, n_steps, 0, torch.from_numpy(dl).to(dev), gg,
+                     gna, gk, gl, per_instance=True)
+        psst.batch_poll(batch)
+        outs[name] = gg.cpu().numpy().reshape(B, gs)
+    on = oracle.OracleNet(ev)
+    for t in range(B):
+        y0 = oracle.init_state(on, v0[t])
+        ref = np.asarray(oracle.adjoint(on, y0, W.Stimulus(i_nA[t]), 0.01, n_steps,
+                                        dl[:, t * ev.n:(t + 1) * ev.n].astype(np.float64),
+                                        tableau=W.TABLEAUX["heun"])["g"], np.float64)
+        nrm = np.linalg.norm(outs["heun"][t] - ref) / np.linalg.norm(ref)
+        _say(f"  trial {t} g: norm rel err {nrm:.2e}")
+        assert nrm <= 1e-3, (t, nrm)
