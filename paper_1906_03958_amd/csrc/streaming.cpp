@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "runtime.h"
@@ -38,6 +39,30 @@ static psst_status grow(void **d, void **h, size_t *have, size_t need)
     HIPCHK(hipHostMalloc(h, need, hipHostMallocDefault));
     *have = need;
     return PSST_OK;
+}
+
+// staging -> caller copy of a chunk's trace: one thread moves a few GB/s, a
+// chunk of the 1.1 M-neuron batch is ~0.4 GB, so large copies are split over
+// several threads to stay shorter than the next chunk's integration
+static void host_copy(void *dst, const void *src, size_t bytes)
+{
+    constexpr size_t kMinPart = size_t(16) << 20;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t parts = std::min<size_t>(std::min(8u, hw), std::max<size_t>(1, bytes / kMinPart));
+    if (parts <= 1) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t step = (bytes / parts + 4095) & ~size_t(4095);
+    std::vector<std::thread> pool;
+    for (size_t k = 1; k < parts; ++k) {
+        const size_t off = k * step;
+        if (off >= bytes) break;
+        const size_t len = std::min(step, bytes - off);
+        pool.emplace_back([=] { std::memcpy((char *)dst + off, (const char *)src + off, len); });
+    }
+    std::memcpy(dst, src, std::min(step, bytes));
+    for (auto &t : pool) t.join();
 }
 
 }  // namespace
@@ -111,12 +136,11 @@ extern "C" psst_status psst_integrate_batch_streamed(psst_batch *b, float *state
     }
 
     // host side of one finished chunk: staging -> the caller's arrays
-    auto drain = [&](Side &s) -> psst_status {
-        if (s.chunk < 0) return PSST_OK;
+    auto drain = [&](Side &s, int64_t c_done, int64_t rows) -> psst_status {
+        if (c_done < 0) return PSST_OK;
         HIPCHK(hipEventSynchronize(s.copied));
-        if (host_v && s.rows > 0)
-            std::memcpy(host_v + (s.chunk * chunk / stride) * nt, s.h_v,
-                        sizeof(float) * s.rows * nt);
+        if (host_v && rows > 0)
+            host_copy(host_v + (c_done * chunk / stride) * nt, s.h_v, sizeof(float) * rows * nt);
         if (host_cnt) {
             for (int64_t i = 0; i < nt; ++i) {
                 const int32_t k = s.h_cnt[i];
@@ -127,31 +151,37 @@ extern "C" psst_status psst_integrate_batch_streamed(psst_batch *b, float *state
                 host_cnt[i] = base + k;
             }
         }
-        s.chunk = -1;
         return PSST_OK;
     };
 
+    // chunk c: its integration is queued first (after the copy-out of chunk
+    // c - 2, which used the same device buffers, on the device side), then
+    // the host drains chunk c - 2 while chunk c integrates, then chunk c's
+    // copy-out is queued behind its integration
     const int64_t n_chunks = (n_steps + chunk - 1) / chunk;
     for (int64_t c = 0; c < n_chunks && st == PSST_OK; ++c) {
         Side &s = S.side[c & 1];
-        if ((st = drain(s)) != PSST_OK) break;          // chunk c - 2's records
+        const int64_t prev = s.chunk, prev_rows = s.rows;
+        if (prev >= 0) HIPCHK(hipStreamWaitEvent(cs, s.copied, 0));
         const int64_t len = std::min(chunk, n_steps - c * chunk);
         const int64_t s0 = step0 + c * chunk;
-        s.rows = host_v ? (s0 + len) / stride - s0 / stride : 0;
+        const int64_t rows = host_v ? (s0 + len) / stride - s0 / stride : 0;
         if (host_cnt) HIPCHK(hipMemsetAsync(s.d_cnt, 0, sizeof(int32_t) * nt, cs));
         psst_record rec{};
         rec.v_out = host_v ? s.d_v : nullptr;
         rec.stride = host_v ? stride : 0;
-        rec.capacity = s.rows;
+        rec.capacity = rows;
         rec.spike_count = host_cnt ? s.d_cnt : nullptr;
         rec.spike_t_ms = host_cnt && cap > 0 ? s.d_spk : nullptr;
         rec.spike_cap = host_cnt ? cap : 0;
         if ((st = batch_launch_direct(b, states, stim, dt, len, s0, &rec, stream)) != PSST_OK)
             break;
         HIPCHK(hipEventRecord(s.computed, cs));
+        if ((st = drain(s, prev, prev_rows)) != PSST_OK) break;   // chunk c - 2's records
+        s.chunk = -1;
         HIPCHK(hipStreamWaitEvent(S.copy, s.computed, 0));
-        if (host_v && s.rows > 0)
-            HIPCHK(hipMemcpyAsync(s.h_v, s.d_v, sizeof(float) * s.rows * nt,
+        if (host_v && rows > 0)
+            HIPCHK(hipMemcpyAsync(s.h_v, s.d_v, sizeof(float) * rows * nt,
                                   hipMemcpyDeviceToHost, S.copy));
         if (host_cnt) {
             HIPCHK(hipMemcpyAsync(s.h_cnt, s.d_cnt, sizeof(int32_t) * nt, hipMemcpyDeviceToHost,
@@ -162,12 +192,17 @@ extern "C" psst_status psst_integrate_batch_streamed(psst_batch *b, float *state
         }
         HIPCHK(hipEventRecord(s.copied, S.copy));
         s.chunk = c;
+        s.rows = rows;
     }
     // the last two chunks, in order
-    if (st == PSST_OK && n_chunks >= 2) st = drain(S.side[(n_chunks - 2) & 1]);
-    if (st == PSST_OK) st = drain(S.side[(n_chunks - 1) & 1]);
+    for (int64_t c = std::max<int64_t>(0, n_chunks - 2); c < n_chunks && st == PSST_OK; ++c) {
+        Side &s = S.side[c & 1];
+        st = drain(s, s.chunk, s.rows);
+        s.chunk = -1;
+    }
     if (st != PSST_OK) {
         (void)hipStreamSynchronize(cs);
+        (void)hipStreamSynchronize(S.copy);   // no copy into the staging buffers outlives the call
         return st;
     }
     return psst_batch_poll(b, stream);
