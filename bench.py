@@ -396,7 +396,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(instances are independent: a multi-GPU run would shard them with no "
               "communication)", file=sys.stderr)
         sys.exit(2)

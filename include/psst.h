@@ -58,7 +58,7 @@ typedef enum {
     PSST_ERR_OUT_OF_MEMORY = 2,     /* a device or host allocation failed */
     PSST_ERR_DEVICE = 3,            /* no usable gfx950 device, or a HIP call failed */
     PSST_ERR_NONFINITE = 4,         /* a state variable became NaN or infinite */
-    PSST_ERR_UNSUPPORTED = 5        /* valid request this build does not implement */
+    PSST_ERR_UNSUPPORTED = 5        /* valid request the library does not implement */
 } psst_status;
 
 /* Thread-local text describing the last failure of a call on this thread. */
