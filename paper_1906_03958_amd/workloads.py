@@ -181,6 +181,17 @@ def _v0(cfg, instance, n) -> np.ndarray:
     return _f32(rng_for(cfg, instance, S_V0).uniform(-70.0, -60.0, n))
 
 
+def sized_instance(instance: int, n_pn: int, n_ln: int) -> Instance:
+    """A network of any size built with the config-1 recipe (all ordered
+    pairs Bernoulli(0.5), g ~ U(0, 0.5) nS, I ~ U(0, 2) nA, V0 ~ U(-70, -60)
+    mV), seeded by (9, instance): sizes at the kernels' boundaries.  A cell
+    type with no neurons contributes no pathway."""
+    cfg = 9
+    net = all_pairs_network(cfg, instance, n_pn, n_ln)
+    net.pathways = [w for w in net.pathways if w.pre_end > w.pre_begin and w.post_end > w.post_begin]
+    return Instance(net, _v0(cfg, instance, net.n), _const_stim(cfg, instance, net.n))
+
+
 # ---------------------------------------------------------------------------
 # The five workloads
 # ---------------------------------------------------------------------------

@@ -215,3 +215,30 @@ def test_edge_cases():
         psst.network_poll(net)
     assert e.value.status == psst.ERR_NONFINITE
     psst.network_poll(net)                           # flag was cleared
+
+
+def test_ragged_extremes_parity_and_batch_equals_plain():
+    """Sizes at the kernels' boundaries in one ragged batch: a lone neuron
+    (no synapses), 63/64/65 and 127/129 neurons around the 64-column chunk
+    edges, 202/203 around the whole-matrix-in-LDS limit, and 1024, the
+    largest network of the per-instance kernel (mostly streamed).  Oracle
+    parity over 3 ms (max |dV| <= 1e-3 mV) and batch = plain bit for bit."""
+    sizes = [(1, 0), (48, 15), (48, 16), (49, 16), (96, 31), (97, 32), (152, 50), (152, 51),
+             (768, 256)]
+    insts = [W.sized_instance(k, a, b) for k, (a, b) in enumerate(sizes)]
+    n = 300
+    _say(f"ragged extremes: sizes {[i.net.n for i in insts]}, {n} steps")
+    g = R.gpu_run(insts, n, rec_stride=1, spike_cap=8)
+    p = R.gpu_run(insts, n, rec_stride=1, spike_cap=8, batched=False)
+    np.testing.assert_array_equal(g["state"], p["state"])
+    np.testing.assert_array_equal(g["v"], p["v"])
+    o = R.oracle_run(insts, n, rec_stride=1, spike_cap=8)
+    offs = np.concatenate([[0], np.cumsum([i.net.n for i in insts])])
+    for k, inst in enumerate(insts):
+        a, b = offs[k], offs[k + 1]
+        dv = np.abs(g["v"][:, a:b].astype(np.float64) - o["v"][:, a:b]).max()
+        _say(f"  n={inst.net.n}: max|dV| {dv:.2e} mV")
+        assert dv <= 1e-3, (inst.net.n, dv)
+    bad, worst, total = R.spike_match(g["spike_count"], g["spike_t"], o["spike_count"],
+                                      o["spike_t"], 3.0)
+    assert bad == 0 and worst <= 0.05, (bad, worst, total)
