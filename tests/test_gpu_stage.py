@@ -128,3 +128,25 @@ def test_config4_full_size_sampled_trials():
         dv = np.abs(gv - ov).max()
         _say(f"  trial {t}: max|dV| over {steps} steps = {dv:.3e}")
         assert dv <= 1e-3
+
+
+def test_stage_path_ragged_tiles():
+    # 1025 neurons (770 PN + 255 LN): one neuron past the per-workgroup limit,
+    # a last 64-row tile holding one real row, K blocks padded (770 -> 896,
+    # 255 -> 256); 70 trials: a second 64-trial tile holding 6.  The oracle
+    # follows trials at both tiles' edges.
+    net = W.all_pairs_network(43, 0, 770, 255, g_max=0.1)
+    insts = _trials(net, 43, 70)
+    n = 150
+    _say("stage path, ragged tiles: 1025 neurons x 70 trials,", n, "steps")
+    g = _gpu_trials(net, insts, n, rec_stride=1, spike_cap=16)
+    picks = [0, 63, 64, 69]
+    o = R.oracle_run([insts[t] for t in picks], n, rec_stride=1, spike_cap=16)
+    for k, t in enumerate(picks):
+        a = t * net.n
+        dv = np.abs(g["v"][:, a:a + net.n].astype(np.float64)
+                    - o["v"][:, k * net.n:(k + 1) * net.n]).max()
+        _say(f"  trial {t}: max|dV| {dv:.2e} mV")
+        assert dv <= 1e-3, (t, dv)
+        np.testing.assert_array_equal(g["spike_count"][a:a + net.n],
+                                      o["spike_count"][k * net.n:(k + 1) * net.n])
