@@ -211,6 +211,8 @@ def bench_large(args, torch, psst, W, dev, stream):
                         "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4),
                         "traffic": read_traffic("stage_kernel", args),
+                        "traffic_GBps": (round(read_traffic("stage_kernel", args) / stage_s / 1e9, 1)
+                                         if read_traffic("stage_kernel", args) else None),
                         "kernel": "stage_kernel<4,2,1,2> (fp32 MFMA GEMM, 8 wavefronts, + fused RK4 stage)",
                         "avg_launch_ms": round(1e3 * stage_s, 4),
                         "algorithmic_flops_per_launch": flops_stage,
@@ -501,6 +503,11 @@ def main():
                 "kernel": "rk4_wg_kernel (batched persistent RK4)",
                 "avg_launch_ms": round(1e3 * avg_launch_s, 3),
                 "algorithmic_bytes_per_launch": bytes_per_launch}
+    if traffic:
+        # the measured HBM bytes over the same launch time: what the kernel
+        # really moves (conductances kept in LDS are not re-read)
+        roofline["traffic_GBps"] = round(traffic / avg_launch_s / 1e9, 1)
+        roofline["traffic_frac"] = round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
     if sparse:
         # sparse rows: 8 bytes (column, g) per synapse per stage instead of 4
         # per matrix entry; the same instances with dense storage alongside

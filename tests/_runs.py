@@ -114,3 +114,4 @@ def spike_match(gc, gt, oc, ot, t_max, tol=0.05):
         if len(a):
             worst = max(worst, float(np.abs(a.astype(np.float64) - b).max()))
     return bad, worst, total
+

@@ -10,6 +10,7 @@ import pytest
 
 from paper_1906_03958_amd import workloads as W
 from tests import _runs as R
+from tests._floor import conditioning_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +50,12 @@ def test_config1_parity_50ms_and_spikes_100ms():
         o = R.oracle_run([inst], W.CONFIG1_STEPS, rec_stride=1, spike_cap=64)
         dv = np.abs(g["v"][:5000] - o["v"][:5000]).max()
         _say("  max|dV| 0-50 ms", dv)
+        # reported beside the gate: each neuron's error against the oracle's
+        # own change under one float32 ulp of that neuron's inputs
+        floor = conditioning_floor(inst, 5000)
+        dvi = np.abs(g["v"][:5000] - o["v"][:5000]).max(axis=0)
+        _say(f"  per neuron: max|dV| / floor {np.max(dvi / floor):.2f}, neurons above "
+             f"their floor {int((dvi > floor).sum())} of {len(floor)}, floor max {floor.max():.2e}")
         assert dv <= DV_TOL
         bad, worst, total = R.spike_match(g["spike_count"], g["spike_t"], o["spike_count"],
                                           o["spike_t"], 100.0)

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from paper_1906_03958_amd import workloads as W
+from tests._floor import conditioning_floor
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -571,3 +572,22 @@ def test_tableau_adjoint_matches_central_differences(name):
         fd = (lp - lm) / (2 * h)
         roundoff = 8 * np.finfo(float).eps * mag / (2 * h)
         assert abs(adj[kind][idx] - fd) <= 1e-5 * abs(fd) + roundoff, (name, kind, adj[kind][idx], fd)
+
+
+def test_conditioning_floor_of_the_20_neuron_network():
+    """The oracle's own sensitivity to one float32 ulp of a neuron's inputs
+    over the 50 ms parity window, reported next to the literal 1e-3 mV gate:
+    neurons that stay below threshold move by a few microvolts, firing
+    neurons by 1e-4 to 2e-3 mV (a tiny shift of a spike's timing shows up
+    multiplied by the steep slope of its upstroke)."""
+    floors = []
+    for seed in (0, 1):
+        inst = W.config1(seed)
+        f = conditioning_floor(inst, 5000)
+        floors.append(f)
+        print(f"seed {seed}: floor median {np.median(f):.2e} max {f.max():.2e} mV", flush=True)
+        assert np.all(np.isfinite(f)) and np.all(f > 0)
+        assert f.max() < 1e-2
+    f = np.concatenate(floors)
+    # silent and firing neurons both present, at well separated levels
+    assert f.min() < 1e-5 and np.median(f) > 1e-4
