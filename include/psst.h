@@ -324,16 +324,15 @@ typedef struct {
  * batches created from it afterwards.  NULL restores classical RK4; a tableau
  * equal to classical RK4 (a[1][0] = a[2][1] = 1/2, a[3][2] = 1,
  * b = 1/6, 1/3, 1/3, 1/6) is treated as NULL (same kernels, same bits).
- * Networks on the per-stage path (more than 1024 neurons) accept only RK4:
- * other tableaux return PSST_ERR_UNSUPPORTED here.  Synchronous; errors:
- * INVALID_ARGUMENT for a NULL network or a tableau that breaks the rules
- * above. */
+ * Networks on the per-stage path (more than 1024 neurons) take one launch
+ * per stage of the method.  Synchronous; errors: INVALID_ARGUMENT for a NULL
+ * network or a tableau that breaks the rules above. */
 psst_status psst_network_set_tableau(psst_network *net, const psst_tableau *tab);
 
 /* The same for a batch: its integrate and adjoint calls use this method.
  * psst_batch_create takes the method of its networks, which must all agree
- * (else INVALID_ARGUMENT).  Batches of a large shared network accept only
- * RK4 (UNSUPPORTED otherwise). */
+ * (else INVALID_ARGUMENT).  The adjoint needs a per-instance batch (the
+ * per-stage path of a large network has none). */
 psst_status psst_batch_set_tableau(psst_batch *batch, const psst_tableau *tab);
 
 #ifdef __cplusplus

@@ -735,10 +735,6 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
                         kMaxWGNeurons);
         }
         b->stage_path = true;
-        if (b->gen) {
-            batch_free(b);
-            return fail(PSST_ERR_UNSUPPORTED, "the per-stage path integrates with classical RK4 only");
-        }
         s = stage_batch_create(nets[0], n, &b->stage);
         if (s != PSST_OK) {
             batch_free(b);
@@ -1020,10 +1016,9 @@ extern "C" psst_status psst_network_set_tableau(psst_network *net, const psst_ta
     psst::Tab t;
     psst_status s = read_tableau(tab, &gen, &t);
     if (s != PSST_OK) return s;
-    if (gen && !fits_wg(net))
-        return fail(PSST_ERR_UNSUPPORTED, "the per-stage path integrates with classical RK4 only");
     net->gen = gen;
     net->tab = t;
+    if (net->single) stage_batch_set_method(net->single, gen, t);   // plain calls, large network
     return PSST_OK;
 }
 
@@ -1034,8 +1029,10 @@ extern "C" psst_status psst_batch_set_tableau(psst_batch *b, const psst_tableau 
     psst::Tab t;
     psst_status s = read_tableau(tab, &gen, &t);
     if (s != PSST_OK) return s;
-    if (gen && b->stage_path)
-        return fail(PSST_ERR_UNSUPPORTED, "the per-stage path integrates with classical RK4 only");
+    if (b->stage_path) {
+        stage_batch_set_method(b->stage, gen, t);
+        b->describe = stage_batch_describe(b->stage);
+    }
     if (gen != b->gen && b->exec) {
         // the graph's kernel changes: build it again on the next call
         HIPCHK(hipGraphExecDestroy(b->exec));

@@ -32,3 +32,6 @@ psst_status stage_batch_integrate(StageBatch *sb, float *states, const psst_stim
                                   float dt, int64_t n_steps, int64_t step0,
                                   const psst_record *rec, float *ckpt, int32_t K, void *stream);
 psst_status stage_batch_poll(StageBatch *sb, void *stream);
+// Switch between classical RK4 (gen = false) and a generic explicit method;
+// the step graph is rebuilt on the next call.
+void stage_batch_set_method(StageBatch *sb, bool gen, const psst::Tab &tab);

@@ -40,8 +40,10 @@ constexpr int NVS = NVAR;
 struct StageFixed {
     const float *G;
     int Kp, ka, kg;           // K blocks [0,ka) ACh, [ka,ka+kg) fast GABA, [ka+kg,Kp) slow GABA
-    float *X0, *X1;           // [Bp][Kp] activations (double-buffered by stage parity)
+    float *X0, *X1;           // [Bp][Kp] activations (double-buffered by stage launch)
     double *Yw, *accw;        // [NVAR][nt] stage input and RK4 accumulator
+    double *P2, *P3;          // generic method: partial inputs of stages 2, 3
+    Tab tab;                  // generic method (stages, a, b)
     const float *prm;         // [NPRM][ld]
     const float *kin;
     int ld, n, n_pn, B, Bp;
@@ -110,7 +112,7 @@ __device__ __forceinline__ void tile_load(floatx4 (&rg)[GV], floatx4 (&rx)[XVT],
 
 // One workgroup per CU (its LDS tiles take most of the CU's LDS); WR x WC
 // wavefronts, each owning BR x BC blocks of 16 x 16 outputs.
-template <int WR, int WC, int BR, int BC>
+template <int WR, int WC, int BR, int BC, bool GEN>
 __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR * WC / 4, WR * WC / 4))) void stage_kernel(StageFixed fx, const StageCtl *__restrict__ dctl,
                                                     int q)
 {
@@ -126,8 +128,12 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
     const int m0 = blockIdx.x * MT, n0 = blockIdx.y * NTILE;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / WC, wc = wave % WC;
-    const float *X = (q & 1) ? fx.X1 : fx.X0;
-    float *Xn = (q & 1) ? fx.X0 : fx.X1;
+    // activations alternate between the two buffers at every stage launch of
+    // the call (the prologue fills X0 for the first): the launch's position
+    // is (step - first step) * stages + q, whatever the method's stage count
+    const int64_t k_launch = (dctl->g - dctl->step0) * (GEN ? fx.tab.s : 4) + q;
+    const float *X = (k_launch & 1) ? fx.X1 : fx.X0;
+    float *Xn = (k_launch & 1) ? fx.X0 : fx.X1;
 
     floatx4 acc[3][BR][BC];
 #pragma unroll
@@ -229,13 +235,19 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
         if (i >= fx.n || b >= fx.B) continue;
         const int64_t gi = (int64_t)b * fx.n + i;
         // y: the step's start state; Y: this stage's input (y itself at stage
-        // 0); a: the weighted sum of the earlier stages' derivatives
+        // 0); a: the weighted sum of the earlier stages' derivatives.  The
+        // generic method keeps, per variable, B = sum_r b_r k_r in accw and
+        // in the slot of each later stage m the partial input
+        // sum_r a_mr k_r, replaced by the input y + dt * sum itself once
+        // stage m - 1 has added the last term.
+        auto slot = [&](int m) { return m == 1 ? fx.Yw : (m == 2 ? fx.P2 : fx.P3); };
+        const int last = GEN ? fx.tab.s - 1 : 3;
         double Y[NVS], a[NVS], y[NVS];
 #pragma unroll
         for (int v = 0; v < NVS; ++v) {
             y[v] = v < nv ? (double)c.state[(2 * v) * nt + gi] + (double)c.state[(2 * v + 1) * nt + gi]
                           : 0.0;
-            Y[v] = (q == 0 || v >= nv) ? y[v] : fx.Yw[v * nt + gi];
+            Y[v] = (q == 0 || v >= nv) ? y[v] : slot(GEN ? q : 1)[v * nt + gi];
             a[v] = (q == 0 || v >= nv) ? 0.0 : fx.accw[v * nt + gi];
         }
         Prm P = load_prm(fx.prm, fx.ld, i);
@@ -249,28 +261,55 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
         double f[NVS];
         hh_rhs(Y, P, K, fx.cg * sa, fx.cg * sg, fx.cg * sb, fx.ci * I, i >= fx.n_pn,
                fx.gabab != 0, f);
-        const double w = (q == 0 || q == 3) ? 1.0 : 2.0;
+        double yn[NVS];                       // the step's result (last stage)
+        if constexpr (GEN) {
 #pragma unroll
-        for (int v = 0; v < NVS; ++v) a[v] += w * f[v];
-        if (q < 3) {
-            const double cq = (q == 2) ? dt : 0.5 * dt;
+            for (int v = 0; v < NVS; ++v) a[v] += fx.tab.b[q] * f[v];
+            if (q < last) {
 #pragma unroll
-            for (int v = 0; v < NVS; ++v) {
-                Y[v] = y[v] + cq * f[v];
-                if (v < nv) {
-                    fx.Yw[v * nt + gi] = Y[v];
-                    fx.accw[v * nt + gi] = a[v];
+                for (int v = 0; v < NVS; ++v) {
+                    for (int m = q + 1; m <= last; ++m) {
+                        const double pm = (q == 0 || v >= nv ? 0.0 : slot(m)[v * nt + gi]) +
+                                          fx.tab.a[m][q] * f[v];
+                        const double val = m == q + 1 ? y[v] + dt * pm : pm;
+                        if (m == q + 1) Y[v] = val;
+                        if (v < nv) slot(m)[v * nt + gi] = val;
+                    }
+                    if (v < nv) fx.accw[v * nt + gi] = a[v];
                 }
+                write_x(fx, Xn, b, i, Y, K);
+            } else {
+#pragma unroll
+                for (int v = 0; v < NVS; ++v) yn[v] = y[v] + dt * a[v];
             }
-            write_x(fx, Xn, b, i, Y, K);
         } else {
+            const double w = (q == 0 || q == 3) ? 1.0 : 2.0;
+#pragma unroll
+            for (int v = 0; v < NVS; ++v) a[v] += w * f[v];
+            if (q < 3) {
+                const double cq = (q == 2) ? dt : 0.5 * dt;
+#pragma unroll
+                for (int v = 0; v < NVS; ++v) {
+                    Y[v] = y[v] + cq * f[v];
+                    if (v < nv) {
+                        fx.Yw[v * nt + gi] = Y[v];
+                        fx.accw[v * nt + gi] = a[v];
+                    }
+                }
+                write_x(fx, Xn, b, i, Y, K);
+            } else {
+#pragma unroll
+                for (int v = 0; v < NVS; ++v) yn[v] = y[v] + (dt / 6.0) * a[v];
+            }
+        }
+        if (q == last) {
             const double vold = y[YV];
             double chk = 0.0;
 #pragma unroll
             for (int v = 0; v < NVS; ++v) {
                 if (v >= nv) continue;
                 float hi, lo;
-                y[v] = split_store(y[v] + (dt / 6.0) * a[v], hi, lo);
+                y[v] = split_store(yn[v], hi, lo);
                 c.state[(2 * v) * nt + gi] = hi;
                 c.state[(2 * v + 1) * nt + gi] = lo;
                 chk += y[v];
@@ -307,6 +346,7 @@ struct StageBatch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int q_arg[4] = {0, 1, 2, 3};
+    bool gen = false;                 // generic explicit method (fx.tab)
     std::string desc;
 };
 
@@ -376,7 +416,9 @@ psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch *
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
     chk(hipMalloc(&sb->X, sizeof(float) * 2 * (size_t)sb->Bp * sn->Kp));
     chk(hipMemset(sb->X, 0, sizeof(float) * 2 * (size_t)sb->Bp * sn->Kp));
-    chk(hipMalloc(&sb->work, sizeof(double) * 2 * NVAR * (size_t)nt));
+    // four float64 planes per (variable, neuron, trial): classical RK4 uses
+    // the first two (stage input, accumulator), a generic method all four
+    chk(hipMalloc(&sb->work, sizeof(double) * 4 * NVAR * (size_t)nt));
     chk(hipMalloc(&sb->d_ctl, sizeof(StageCtl)));
     chk(hipMalloc(&sb->d_flag, sizeof(int32_t)));
     chk(hipMemset(sb->d_flag, 0, sizeof(int32_t)));
@@ -394,6 +436,8 @@ psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch *
     fx.X1 = sb->X + (size_t)sb->Bp * sn->Kp;
     fx.Yw = sb->work;
     fx.accw = sb->work + (size_t)NVAR * nt;
+    fx.P2 = sb->work + 2 * (size_t)NVAR * nt;
+    fx.P3 = sb->work + 3 * (size_t)NVAR * nt;
     fx.prm = net->d_prm;
     fx.kin = net->d_kin;
     fx.ld = net->ld;
@@ -405,13 +449,28 @@ psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch *
     fx.gabab = net->gabab ? 1 : 0;
     fx.cg = net->cg;
     fx.ci = net->ci;
-    char buf[256];
-    snprintf(buf, sizeof buf,
-             "[per-stage fp32 MFMA GEMM: %d rows x %d trials (tile 64 x %d), K %d, 4 launches per step]",
-             sn->Mp, sb->Bp, sb->ntile, sn->Kp);
-    sb->desc = buf;
+    stage_batch_set_method(sb, net->gen, net->tab);
     *out = sb;
     return PSST_OK;
+}
+
+void stage_batch_set_method(StageBatch *sb, bool gen, const Tab &tab)
+{
+    if (sb->exec) {
+        // the graph's kernel and stage count change: build it on the next call
+        (void)hipGraphExecDestroy(sb->exec);
+        (void)hipGraphDestroy(sb->graph);
+        sb->exec = nullptr;
+        sb->graph = nullptr;
+    }
+    sb->gen = gen;
+    sb->fx.tab = gen ? tab : Tab{};
+    const StageNet *sn = sb->net->stage;
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "[per-stage fp32 MFMA GEMM: %d rows x %d trials (tile 64 x %d), K %d, %d launches per step]",
+             sn->Mp, sb->Bp, sb->ntile, sn->Kp, gen ? tab.s : 4);
+    sb->desc = buf;
 }
 
 void stage_batch_free(StageBatch *sb)
@@ -428,10 +487,13 @@ void stage_batch_free(StageBatch *sb)
 
 const char *stage_batch_describe(const StageBatch *sb) { return sb ? sb->desc.c_str() : ""; }
 
-static const void *stage_fn(int ntile)
+static const void *stage_fn(int ntile, bool gen)
 {
-    return ntile == 16 ? (const void *)stage_kernel<4, 1, 1, 1>
-                       : (const void *)stage_kernel<4, 2, 1, 2>;
+    if (gen)
+        return ntile == 16 ? (const void *)stage_kernel<4, 1, 1, 1, true>
+                           : (const void *)stage_kernel<4, 2, 1, 2, true>;
+    return ntile == 16 ? (const void *)stage_kernel<4, 1, 1, 1, false>
+                       : (const void *)stage_kernel<4, 2, 1, 2, false>;
 }
 
 static int stage_threads(int ntile) { return ntile == 16 ? 256 : 512; }
@@ -443,19 +505,20 @@ static size_t stage_lds_bytes(int ntile)
     return sizeof(float) * (tile > accf ? tile : accf);
 }
 
-// One RK4 step as a graph: stages 0..3 then the step-counter advance.
+// One step as a graph: its stages (4 for RK4) then the step-counter advance.
 static psst_status build_graph(StageBatch *sb)
 {
     const size_t lds = stage_lds_bytes(sb->ntile);
-    HIPCHK(hipFuncSetAttribute(stage_fn(sb->ntile), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
+    const void *fn = stage_fn(sb->ntile, sb->gen);
+    HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     HIPCHK(hipGraphCreate(&sb->graph, 0));
     hipGraphNode_t prev = nullptr;
     const dim3 grid(sb->net->stage->Mp / MT, sb->Bp / sb->ntile);
-    for (int q = 0; q < 4; ++q) {
+    const int stages = sb->gen ? sb->fx.tab.s : 4;
+    for (int q = 0; q < stages; ++q) {
         void *kp[] = {&sb->fx, &sb->d_ctl, &sb->q_arg[q]};
         hipKernelNodeParams p{};
-        p.func = const_cast<void *>(stage_fn(sb->ntile));
+        p.func = const_cast<void *>(fn);
         p.gridDim = grid;
         p.blockDim = dim3(stage_threads(sb->ntile));
         p.sharedMemBytes = (unsigned)lds;

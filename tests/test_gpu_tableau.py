@@ -2,7 +2,7 @@
 psst_batch_set_tableau): the same discrete map as the FP64 oracle run with
 the same tableau -- forward parity (max |dV| <= 1e-3 mV over the first
 50 ms, spike times within 0.05 ms), bitwise invariances (batched = plain,
-chunking, batch order), the discrete adjoint against the oracle's tableau
+chunking, batch order), the per-stage path of large networks, the discrete adjoint against the oracle's tableau
 adjoint, classical RK4 given as a tableau = the default path bit for bit,
 and the validation of the tableau rules."""
 import sys
@@ -140,12 +140,6 @@ def test_tableau_validation():
     with pytest.raises(psst.PsstError) as e:
         psst.batch_create([net, n2])
     assert e.value.status == psst.ERR_INVALID_ARGUMENT
-    # the per-stage path integrates with RK4 only
-    big = psst.network_create(W.config4_network(n_pn=1536, n_ln=512))
-    with pytest.raises(psst.PsstError) as e:
-        psst.network_set_tableau(big, W.TABLEAUX["heun"])
-    assert e.value.status == psst.ERR_UNSUPPORTED
-    psst.network_set_tableau(big, None)
 
 
 @pytest.mark.parametrize("name", ["ssprk3", "rk38", "heun"])
@@ -231,3 +225,66 @@ def test_tableau_adjoint_after_rk4_on_the_same_batch():
         nrm = np.linalg.norm(outs["heun"][t] - ref) / np.linalg.norm(ref)
         _say(f"  trial {t} g: norm rel err {nrm:.2e}")
         assert nrm <= 1e-3, (t, nrm)
+
+
+def _big_trials(n_trials):
+    net = W.all_pairs_network(44, 0, 1536, 512, g_max=0.1)
+    i_nA, v0 = W.trial_inputs(44, net.n, n_trials)
+    return net, [W.Instance(net, v0[t], W.Stimulus(i_nA[t])) for t in range(n_trials)]
+
+
+@pytest.mark.parametrize("name", ["euler", "heun", "kutta3", "rk38"])
+def test_tableau_on_the_per_stage_path(name):
+    """2048 neurons shared by 20 trials (one 64-trial GEMM tile), one launch
+    per stage of the method: oracle parity on two trials and on trial 0 run
+    alone through psst_integrate (a 16-trial tile), chunking bit for bit."""
+    from paper_1906_03958_amd import psst
+    tab = W.TABLEAUX[name]
+    net, insts = _big_trials(20)
+    h = psst.network_create(net)
+    psst.network_set_tableau(h, tab)
+    n = 200
+    _say(f"per-stage path, {name}: 2048 neurons x 20 trials, {n} steps")
+    g = R.gpu_run(insts, n, rec_stride=1, spike_cap=16, nets=[h] * 20)
+    c = R.gpu_run(insts, n, rec_stride=1, spike_cap=16, nets=[h] * 20, chunks=[70, 130])
+    np.testing.assert_array_equal(g["state"], c["state"])
+    np.testing.assert_array_equal(g["v"], c["v"])
+    o = R.oracle_run(insts[:2], n, rec_stride=1, spike_cap=16, tableau=tab)
+    dv = np.abs(g["v"][:, :2 * net.n].astype(np.float64) - o["v"]).max()
+    _say(f"  max|dV| {dv:.2e} mV")
+    assert dv <= DV_TOL
+    np.testing.assert_array_equal(g["spike_count"][:2 * net.n], o["spike_count"])
+    # trial 0 alone through psst_integrate (a one-trial stage batch)
+    p = R.gpu_run(insts[:1], n, rec_stride=1, batched=False, nets=[h])
+    dv1 = np.abs(p["v"].astype(np.float64) - o["v"][:, :net.n]).max()
+    _say(f"  plain call, trial 0: max|dV| {dv1:.2e} mV")
+    assert dv1 <= DV_TOL
+
+
+def test_per_stage_batch_switches_method():
+    """A large-network batch switched RK4 -> Heun -> RK4 with
+    psst_batch_set_tableau gives the bits of batches built with each method."""
+    import torch
+    from paper_1906_03958_amd import psst
+    net, insts = _big_trials(8)
+    n = 60
+    ref = {}
+    for name in ("rk4", "heun"):
+        h = psst.network_create(net)
+        if name != "rk4":
+            psst.network_set_tableau(h, W.TABLEAUX[name])
+        ref[name] = R.gpu_run(insts, n, rec_stride=0, nets=[h] * 8)["state"]
+    h = psst.network_create(net)
+    batch = psst.batch_create([h] * 8)
+    dev = torch.device("cuda:0")
+    nt = batch.n_total
+    v0 = torch.from_numpy(np.concatenate([i.v0 for i in insts])).to(dev)
+    stim = psst.pack_stimulus([i.stim for i in insts], dev)
+    for name, tab in (("rk4", None), ("heun", W.TABLEAUX["heun"]), ("rk4", None)):
+        psst.batch_set_tableau(batch, tab)
+        st = torch.zeros(14 * nt, dtype=torch.float32, device=dev)
+        psst.batch_state_init(batch, v0, st)
+        psst.integrate_batch(batch, st, stim, 0.01, n, 0)
+        psst.batch_poll(batch)
+        _say(f"  switched to {name}: {psst.batch_describe(batch)}")
+        np.testing.assert_array_equal(st.view(7, 2, nt).cpu().numpy(), ref[name])
