@@ -142,8 +142,12 @@ typedef enum {
 } psst_storage;
 
 /* psst_network_create with a storage choice (psst_network_create = AUTO).
- * SPARSE for a network above 1024 neurons returns UNSUPPORTED; psst_adjoint
- * on a batch holding a sparse network returns UNSUPPORTED. */
+ * SPARSE for a network above 1024 neurons returns UNSUPPORTED.  A sparse
+ * network of at most 512 neurons (the adjoint's limit) also keeps the dense
+ * transposed matrices and the synapse mask on the device (5 bytes per
+ * matrix entry) for psst_adjoint's transposed products and gradient mask;
+ * its forward reads only the sparse rows, and its adjoint equals that of the
+ * same network stored dense bit for bit. */
 psst_status psst_network_create_storage(const psst_neuron_params *params, int32_t n_neurons,
                                         const psst_pathway *pathways, int32_t n_pathways,
                                         const psst_kinetics kinetics[3], int32_t storage,

@@ -473,7 +473,10 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
                     const int jr = slow ? rr - n : rr;
                     const double *qv = qv0 + (slow ? 2 : (jr < n_pn ? 0 : 1)) * ld;
                     double acc;
-                    if (w.R >= CW)
+                    // rows of the transposed matrix: from LDS when the dense
+                    // layout is resident there, else from global memory (also
+                    // for sparse storage, whose LDS holds the forward's rows)
+                    if (w.R >= CW && !w.sparse)
                         acc = row_dot_quad((lds_float *)lds_row(w, slow ? 1 : 0, jr), qv, n,
                                            tid & 3, on);
                     else

@@ -66,6 +66,7 @@ static bool is_finite_f(float x) { return std::isfinite(x); }
 static size_t max_lds_per_block();
 static bool fits_wg(const psst_network *q);
 static const int kMaxWGNeurons = 1024;   // largest network of the per-instance kernel
+static const int kMaxAdjointNeurons = 512;  // largest network of the adjoint
 
 // ---------------------------------------------------------------------------
 // networks
@@ -257,8 +258,10 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
     const bool wg = fits_wg(net);
 
     // per-instance kernel layout: transposed conductance matrices with padded
-    // rows, gt[j * ld + i] (pre j, post i), and the synapse mask alike
-    const bool dense_wg = wg && !sparse;
+    // rows, gt[j * ld + i] (pre j, post i), and the synapse mask alike.  A
+    // sparse network small enough for the adjoint keeps them as well: the
+    // adjoint's transposed products and its gradient mask read them.
+    const bool dense_wg = wg && (!sparse || n <= kMaxAdjointNeurons);
     std::vector<float> gt(dense_wg ? (size_t)n * ld : 0, 0.f);
     std::vector<float> gtb(dense_wg && net->gabab ? (size_t)n_ln * ld : 0, 0.f);
     std::vector<uint8_t> mt(dense_wg ? (size_t)n * ld + gtb.size() : 0, 0);
@@ -303,7 +306,8 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
         NETCHK(hipMalloc(&net->d_spval, sizeof(float) * sp_val.size()));
         NETCHK(hipMemcpy(net->d_spval, sp_val.data(), sizeof(float) * sp_val.size(),
                          hipMemcpyHostToDevice));
-    } else if (wg) {
+    }
+    if (dense_wg) {
         NETCHK(hipMalloc(&net->d_gt, sizeof(float) * gt.size()));
         NETCHK(hipMemcpy(net->d_gt, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice));
         if (!gtb.empty()) {
@@ -312,7 +316,7 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
         }
         NETCHK(hipMalloc(&net->d_maskt, mt.size()));
         NETCHK(hipMemcpy(net->d_maskt, mt.data(), mt.size(), hipMemcpyHostToDevice));
-    } else {
+    } else if (!wg) {
         psst_status st = stage_net_create(net, paths, np);
         if (st != PSST_OK) {
             net_free(net);
@@ -963,9 +967,6 @@ extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
         return fail(PSST_ERR_INVALID_ARGUMENT, "summed gradients need every instance to share one network");
     if (b->stage_path)
         return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available on the per-stage path");
-    for (auto *q : b->nets)
-        if (q->sparse)
-            return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available for sparse storage");
     return adjoint_run(b->nets, b->d_desc, b->nt, b->offsets, &b->adj, ckpt, K, stim, dt, n_steps,
                        step0, dLdV, grad_g, grad_gNa, grad_gK, grad_gL, per_instance, b->d_flag,
                        max_lds_per_block(), b->gen, b->tab, stream);

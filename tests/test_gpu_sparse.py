@@ -1,7 +1,9 @@
 """Sparse conductance storage on the per-instance path
 (psst_network_create_storage): the same fixed summation order as dense
 storage, so sparse and dense runs of one network agree bit for bit; parity
-of the sparse workload (p = 0.1) with the FP64 oracle; storage validation."""
+of the sparse workload (p = 0.1) with the FP64 oracle; the adjoint of
+sparse storage (bitwise the dense one, and against the oracle); storage
+validation."""
 import sys
 
 import numpy as np
@@ -85,15 +87,56 @@ def test_storage_validation():
     with pytest.raises(psst.PsstError) as e:
         psst.network_create(big, storage=psst.STORAGE_SPARSE)
     assert e.value.status == psst.ERR_UNSUPPORTED
-    # the adjoint does not take sparse storage
-    net = psst.network_create(inst.net, storage=psst.STORAGE_SPARSE)
-    batch = psst.batch_create([net])
+
+
+def _adjoint(insts, nets, n_steps, K, dl):
+    import torch
+    from paper_1906_03958_amd import psst
     dev = torch.device("cuda:0")
-    ck = torch.zeros((1, 14 * inst.net.n), dtype=torch.float32, device=dev)
-    dl = torch.zeros((10, inst.net.n), dtype=torch.float32, device=dev)
-    g = torch.zeros(max(net.grad_size, 1), dtype=torch.float32, device=dev)
-    a = torch.zeros(inst.net.n, dtype=torch.float32, device=dev)
-    with pytest.raises(psst.PsstError) as e:
-        psst.adjoint(batch, ck, 10, None, 0.01, 10, 0, dl, g, a, a.clone(), a.clone(),
-                     per_instance=True)
-    assert e.value.status == psst.ERR_UNSUPPORTED
+    batch = psst.batch_create(nets)
+    nt = batch.n_total
+    st = torch.zeros(14 * nt, dtype=torch.float32, device=dev)
+    psst.batch_state_init(batch, torch.from_numpy(np.concatenate([i.v0 for i in insts])).to(dev),
+                          st)
+    stim = psst.pack_stimulus([i.stim for i in insts], dev)
+    ck = torch.zeros(((n_steps + K - 1) // K, 14 * nt), dtype=torch.float32, device=dev)
+    psst.integrate_batch(batch, st, stim, 0.01, n_steps, 0, None, ck, K)
+    gg = torch.zeros(sum(h.grad_size for h in nets), dtype=torch.float32, device=dev)
+    gna = torch.zeros(nt, dtype=torch.float32, device=dev)
+    gk, gl = torch.zeros_like(gna), torch.zeros_like(gna)
+    psst.adjoint(batch, ck, K, stim, 0.01, n_steps, 0, torch.from_numpy(dl).to(dev), gg, gna,
+                 gk, gl, per_instance=True)
+    psst.batch_poll(batch)
+    return [x.cpu().numpy() for x in (gg, gna, gk, gl)]
+
+
+def test_sparse_adjoint_equals_dense_bitwise_and_oracle():
+    """The adjoint of sparsely stored networks (p = 0.1 instances of 60-480
+    neurons and the 120-neuron network with slow GABA): the recomputed
+    forward is bitwise the dense one and the transposed products read the
+    same dense rows, so the gradients equal the dense-storage ones bit for
+    bit; one instance against the oracle's reverse sweep."""
+    import oracle
+    from paper_1906_03958_amd import psst
+    insts = [W.config3_sparse_instance(b) for b in _sample(4)] + [W.config2(1, t_ms=10.0)]
+    n_steps, K = 150, 40
+    nt = sum(i.net.n for i in insts)
+    dl = (np.random.default_rng(21).standard_normal((n_steps, nt)) * 1e-3).astype(np.float32)
+    _say("sparse adjoint: sizes", [i.net.n for i in insts])
+    d = _adjoint(insts, _nets(insts, psst.STORAGE_DENSE), n_steps, K, dl)
+    s = _adjoint(insts, _nets(insts, psst.STORAGE_SPARSE), n_steps, K, dl)
+    for a, b in zip(d, s):
+        np.testing.assert_array_equal(a, b)
+    k = len(insts) - 1                          # the slow-GABA network
+    inst = insts[k]
+    off = nt - inst.net.n
+    on = oracle.OracleNet(inst.net)
+    ref = oracle.adjoint(on, oracle.init_state(on, inst.v0), inst.stim, 0.01, n_steps,
+                         dl[:, off:].astype(np.float64))
+    gsz = sum(int(p.g_nS.size) for p in inst.net.pathways)
+    got = {"g": s[0][-gsz:], "g_Na": s[1][off:], "g_K": s[2][off:], "g_L": s[3][off:]}
+    for key, v in got.items():
+        r = np.asarray(ref[key], np.float64)
+        nrm = np.linalg.norm(v - r) / np.linalg.norm(r)
+        _say(f"  {key}: norm rel err {nrm:.2e}")
+        assert nrm <= 1e-3, (key, nrm)
