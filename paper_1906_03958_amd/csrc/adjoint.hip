@@ -15,12 +15,15 @@
 // segment from checkpoints taken every K steps: the segment's K steps are
 // recomputed with the forward kernel's own routines (bitwise the forward
 // trajectory) and each step's four stage inputs and synaptic sums are kept in
-// a float64 workspace; each reverse step then walks its stages backwards.  J^T has an
-// elementwise part per neuron and a presynaptic part sum_i g_ij q(i) -- a
-// transposed product, one thread per presynaptic row summing in index order.  dL/dg_ij = sum over steps and stages of q(i) x_j is a
-// contraction over the segment's 4K stage records, formed once per segment in
-// float64 and folded into a float32 (value, compensation) pair per entry;
-// per-neuron gradients likewise.
+// a float64 workspace; each reverse step then walks its stages backwards.
+// J^T has an elementwise part per neuron and a presynaptic part
+// sum_i g_ij q(i) -- a transposed product, four lanes per presynaptic row,
+// each summing one residue class of i in index order.  dL/dg_ij = sum over
+// steps and stages of q(i) x_j is a contraction over the segment's 4K stage
+// records, formed once per segment in float64 (on the float64 matrix cores
+// when the LDS allows) and folded into a float32 (value, compensation) pair
+// per entry; per-neuron gradients likewise.  A generic explicit method
+// (general tableau) runs the same scheme with its own a and b.
 #include <cstdlib>
 #include <cstring>
 

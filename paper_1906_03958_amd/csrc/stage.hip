@@ -1,4 +1,4 @@
-// stage.hip -- one launch per RK4 stage for large shared networks.
+// stage.hip -- one launch per Runge-Kutta stage for large shared networks.
 //
 // Stage q of step g (paper, "Brain simulations as computational graphs": RK4;
 // "Circumventing memory constraints", item 1: the synaptic update as a
@@ -7,7 +7,9 @@
 //                                          one accumulator set per synapse class
 //   f = rhs(Y_q, cg * A, I(g))             float64, fused epilogue
 //   acc += w_q f; Y_{q+1} = y + c_{q+1} dt f; X_{q+1} = x(Y_{q+1})
-// and at q = 3 the combine y <- y + dt/6 acc, spikes and records.
+// and at q = 3 the combine y <- y + dt/6 acc, spikes and records.  A generic
+// explicit method (template flag) takes its stage count, a and b from a
+// tableau instead.
 //
 // GEMM tiling: a workgroup (8 wavefronts, 4 x 2, for NTILE = 64) owns 64
 // postsynaptic rows x NTILE trials over the whole presynaptic axis, so each
