@@ -285,6 +285,47 @@ def bench_streamed(args, torch, psst, W, dev, stream):
     print(json.dumps(out), flush=True)
 
 
+def bench_al(args, torch, psst, W, dev, stream):
+    """One 120-neuron antennal-lobe-shaped network (90 PN + 30 LN, cholinergic,
+    fast- and slow-GABA pathways, pulse-train stimuli) through psst_integrate:
+    one persistent launch on one workgroup, --steps x --chunk RK4 steps with
+    V recorded every step.  A latency-bound case: the figure is the absolute
+    rate of one network."""
+    inst = W.config2(0, t_ms=1000.0)
+    h = psst.network_create(inst.net)
+    n = inst.net.n
+    st = torch.zeros(14 * n, dtype=torch.float32, device=dev)
+    psst.state_init(h, torch.from_numpy(inst.v0).to(dev), st)
+    stim = psst.pack_stimulus([inst.stim], dev)
+    total = args.steps * args.chunk
+    v = torch.zeros((args.chunk, n), dtype=torch.float32, device=dev)
+    psst.integrate(h, st, stim, DT, args.chunk, 0, psst.DeviceRecord(v, 1, args.chunk))
+    torch.cuda.synchronize()
+    psst.state_init(h, torch.from_numpy(inst.v0).to(dev), st)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(args.steps):
+        psst.integrate(h, st, stim, DT, args.chunk, k * args.chunk,
+                       psst.DeviceRecord(v, 1, args.chunk))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    psst.network_poll(h)
+    ms = ev0.elapsed_time(ev1)
+    out = {"metric": METRIC, "value": n * total / wall, "unit": "neuron-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * wall / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "one 120-neuron antennal-lobe-shaped network (90 PN + 30 LN; "
+                                  "ACh, fast and slow GABA; pulse trains), V every step, "
+                                  "psst_integrate", "rk4_steps": total},
+           "us_per_rk4_step": 1e3 * ms / total}
+    log(f"one AL network: {n * total / wall:.3e} neuron-steps/s, {1e3 * ms / total:.2f} us per step")
+    print(json.dumps(out), flush=True)
+
+
 def bench_adjoint(args, torch, psst, W, dev, stream):
     """Adjoint workload: trials of the 120-neuron network sharing one set of
     conductances; forward with checkpoints every K steps and the V trace,
@@ -371,14 +412,16 @@ def main():
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter files of a "
                          "bench run (same --workload/--chunk/--instances) and of a "
                          "--copy-calibration run into profiles/KERNEL_traffic.txt and exit")
-    ap.add_argument("--workload", choices=("batched", "large", "uncoupled", "sparse", "streamed"),
+    ap.add_argument("--workload", choices=("batched", "large", "uncoupled", "sparse", "streamed",
+                                           "al"),
                     default="batched",
                     help="batched: the 4096-network batch (the default line); large: the "
                          "16384-neuron network x 64 trials on the per-stage MFMA path; "
                          "uncoupled: the batch with every synapse removed (compute only); "
                          "sparse: the batch at connection probability 0.1, sparse storage; "
                          "streamed: the batch with its full V trace (every step) and spikes "
-                         "drained to host memory chunk by chunk")
+                         "drained to host memory chunk by chunk; al: one 120-neuron "
+                         "antennal-lobe network through psst_integrate (latency-bound)")
     ap.add_argument("--method", default="rk4",
                     help="explicit Runge-Kutta method of the batched/uncoupled workloads: "
                          "one of the named tableaux (rk4 = the classical kernels)")
@@ -431,6 +474,9 @@ def main():
         return
     if args.workload == "streamed":
         bench_streamed(args, torch, psst, W, dev, stream)
+        return
+    if args.workload == "al":
+        bench_al(args, torch, psst, W, dev, stream)
         return
 
     # ---------------- workload: batched config -----------------------------
