@@ -4,7 +4,8 @@ of the synaptic conductances (per pathway block, nS) and the intrinsic
 conductances g_Na, g_K, g_L (mS/cm^2).
 
 forward  -> psst_integrate_batch with checkpoints every K steps, V every step
-backward -> psst_adjoint (discrete adjoint of the RK4 map, summed over trials)
+backward -> psst_adjoint (discrete adjoint of the RK4 map, or of the explicit
+            method given as a tableau, summed over trials)
 
 All arithmetic happens in the HIP library; this module only marshals tensors.
 """
@@ -24,8 +25,9 @@ class TraceSimulation:
     replaced by the tensors passed to __call__); i_nA, v0: [B, n] arrays."""
 
     def __init__(self, net, i_nA, v0, dt: float, n_steps: int, K: int = 100,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", tableau=None):
         self.template = net
+        self.tableau = tableau          # explicit method (dict(a, b)); None: classical RK4
         self.dev = torch.device(device)
         self.B = int(i_nA.shape[0])
         self.n = int(net.n)
@@ -63,6 +65,8 @@ class PsstTraceFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, sim: TraceSimulation, g_flat, g_na, g_k, g_l):
         net = psst.network_create(sim.build(g_flat, g_na, g_k, g_l))
+        if sim.tableau is not None:
+            psst.network_set_tableau(net, sim.tableau)
         batch = psst.batch_create([net] * sim.B)
         nt = batch.n_total
         states = torch.zeros(14 * nt, dtype=torch.float32, device=sim.dev)
