@@ -196,12 +196,18 @@ typedef struct {
 } psst_record;
 
 /* Integrate one network (the plain one-network-per-launch form): n_steps
- * RK4 steps of size dt_ms from global step index step0 (time t = step0 *
- * dt), state in/out.  Calling it with (n1, step0) then (n2, step0 + n1)
- * gives bitwise the same state and records as one call with n1 + n2.
- * stim, rec may be NULL.  n_steps >= 0, dt_ms > 0 and finite, step0 >= 0.
- * Errors: INVALID_ARGUMENT, DEVICE, UNSUPPORTED (n beyond the single-network
- * kernel's limit).  Non-finite states are reported by psst_network_poll. */
+ * steps of the network's method (classical RK4 unless
+ * psst_network_set_tableau says otherwise) of size dt_ms from global step
+ * index step0 (time t = step0 * dt), state in/out.  Calling it with
+ * (n1, step0) then (n2, step0 + n1) gives bitwise the same state and records
+ * as one call with n1 + n2.  stim, rec may be NULL.  n_steps >= 0, dt_ms > 0
+ * and finite, step0 >= 0.  A network of at most 1024 neurons runs as one
+ * persistent workgroup (its shape follows the network; the environment
+ * variable PSST_WG_SHAPE="<threads>x<neurons per thread>" overrides it);
+ * larger ones take the per-stage path with one trial.  Errors:
+ * INVALID_ARGUMENT, DEVICE, OUT_OF_MEMORY (first call on the per-stage
+ * path allocates its workspace).  Non-finite states are reported by
+ * psst_network_poll. */
 psst_status psst_integrate(psst_network *net, float *state, const psst_stimulus *stim,
                            float dt_ms, int64_t n_steps, int64_t step0,
                            const psst_record *rec, void *hip_stream);
