@@ -303,9 +303,9 @@ psst_status psst_network_grad_size(const psst_network *net, int64_t *n_entries);
  *     existing count, those beyond spike_cap dropped (counted).
  * rec_stride must divide chunk_steps, and step0 must be a multiple of it.
  * Returns when every record is in host memory (the call is synchronous);
- * states holds the state after the last step.  Not for batches on the
- * per-stage path (UNSUPPORTED).  Errors: INVALID_ARGUMENT, OUT_OF_MEMORY,
- * DEVICE, NONFINITE (checked once at the end). */
+ * states holds the state after the last step.  Batches of a large shared
+ * network (per-stage path) stream the same way.  Errors: INVALID_ARGUMENT,
+ * OUT_OF_MEMORY, DEVICE, NONFINITE (checked once at the end). */
 psst_status psst_integrate_batch_streamed(psst_batch *batch, float *states,
                                           const psst_stimulus *stim, float dt_ms,
                                           int64_t n_steps, int64_t step0, int64_t chunk_steps,

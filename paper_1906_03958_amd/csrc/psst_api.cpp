@@ -961,6 +961,9 @@ psst_status batch_launch_direct(psst_batch *b, float *states, const psst_stimulu
     if (s != PSST_OK) return s;
     if ((s = validate_stim(stim)) != PSST_OK) return s;
     if (n_steps == 0) return PSST_OK;
+    if (b->stage_path)        // the per-stage graph: parameters go through its control block
+        return stage_batch_integrate(b->stage, states, stim, dt, n_steps, step0, rec, nullptr, 0,
+                                     stream);
     for (auto &g : b->groups) {
         WGArgs a = group_args(b, g, states, stim, dt, n_steps, step0, rec, nullptr, 1);
         if ((s = launch_group(g, b->gen, a, (hipStream_t)stream)) != PSST_OK) return s;

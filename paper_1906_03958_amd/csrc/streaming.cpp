@@ -100,7 +100,6 @@ extern "C" psst_status psst_integrate_batch_streamed(psst_batch *b, float *state
 {
     if (!b) return fail(PSST_ERR_INVALID_ARGUMENT, "batch is NULL");
     if (!states) return fail(PSST_ERR_INVALID_ARGUMENT, "states is NULL");
-    if (b->stage_path) return fail(PSST_ERR_UNSUPPORTED, "streaming is for per-instance batches");
     if (n_steps < 0 || step0 < 0) return fail(PSST_ERR_INVALID_ARGUMENT, "n_steps and step0 must be >= 0");
     if (chunk <= 0) return fail(PSST_ERR_INVALID_ARGUMENT, "chunk_steps must be > 0");
     if (host_v && (stride <= 0 || chunk % stride != 0 || step0 % stride != 0))

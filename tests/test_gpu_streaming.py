@@ -68,3 +68,39 @@ def test_streamed_argument_checks():
         with pytest.raises(psst.PsstError) as e:
             psst.integrate_batch_streamed(batch, st, stim, 0.01, 40, step0, chunk, stride, hv)
         assert e.value.status == psst.ERR_INVALID_ARGUMENT
+
+
+def test_streamed_per_stage_path_equals_one_call_bitwise():
+    """A large shared network (2048 neurons x 8 trials, the per-stage MFMA
+    path) streamed in chunks of 64 steps (ragged last chunk) equals one call
+    with device records bit for bit."""
+    net = W.all_pairs_network(45, 0, 1536, 512, g_max=0.1)
+    i_nA, v0 = W.trial_inputs(45, net.n, 8)
+    insts = [W.Instance(net, v0[t], W.Stimulus(i_nA[t])) for t in range(8)]
+    import torch
+    from paper_1906_03958_amd import psst
+    dev = torch.device("cuda:0")
+    h = psst.network_create(net)
+    batch = psst.batch_create([h] * 8)
+    nt = batch.n_total
+    st = torch.zeros(14 * nt, dtype=torch.float32, device=dev)
+    psst.batch_state_init(batch, torch.from_numpy(v0.ravel()).to(dev), st)
+    stim = psst.DeviceStimulus(torch.from_numpy(i_nA.ravel()).to(dev))
+    n, stride, cap, chunk = 300, 4, 8, 64
+    st1 = st.clone()
+    rows = n // stride
+    v = torch.zeros((rows, nt), dtype=torch.float32, device=dev)
+    cnt = torch.zeros(nt, dtype=torch.int32, device=dev)
+    spk = torch.zeros((nt, cap), dtype=torch.float32, device=dev)
+    psst.integrate_batch(batch, st1, stim, 0.01, n, 0,
+                         psst.DeviceRecord(v, stride, rows, cnt, spk, cap))
+    psst.batch_poll(batch)
+    hv = np.zeros((rows, nt), np.float32)
+    hc = np.zeros(nt, np.int32)
+    hs = np.zeros((nt, cap), np.float32)
+    psst.integrate_batch_streamed(batch, st, stim, 0.01, n, 0, chunk, stride, hv, hc, hs, cap)
+    np.testing.assert_array_equal(hv, v.cpu().numpy())
+    np.testing.assert_array_equal(hc, cnt.cpu().numpy())
+    np.testing.assert_array_equal(hs, spk.cpu().numpy())
+    np.testing.assert_array_equal(st.cpu().numpy(), st1.cpu().numpy())
+    assert hc.sum() > 0
