@@ -204,10 +204,9 @@ typedef struct {
  * and finite, step0 >= 0.  A network of at most 1024 neurons runs as one
  * persistent workgroup (its shape follows the network; the environment
  * variable PSST_WG_SHAPE="<threads>x<neurons per thread>" overrides it);
- * larger ones take the per-stage path with one trial.  Errors:
- * INVALID_ARGUMENT, DEVICE, OUT_OF_MEMORY (first call on the per-stage
- * path allocates its workspace).  Non-finite states are reported by
- * psst_network_poll. */
+ * larger ones take the per-stage path with one trial (its workspace is
+ * allocated by psst_network_create).  Errors: INVALID_ARGUMENT, DEVICE.
+ * Non-finite states are reported by psst_network_poll. */
 psst_status psst_integrate(psst_network *net, float *state, const psst_stimulus *stim,
                            float dt_ms, int64_t n_steps, int64_t step0,
                            const psst_record *rec, void *hip_stream);

@@ -363,6 +363,15 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
     NETCHK(hipMalloc(&net->d_flag, sizeof(int32_t)));
     NETCHK(hipMemset(net->d_flag, 0, sizeof(int32_t)));
 #undef NETCHK
+    if (!wg) {
+        // the one-trial stage batch psst_integrate uses: allocated here, so
+        // integrate calls allocate nothing
+        psst_status st = stage_single_prepare(net);
+        if (st != PSST_OK) {
+            net_free(net);
+            return st;
+        }
+    }
     *out = net;
     return PSST_OK;
 }

@@ -22,6 +22,8 @@ struct StageNet {
 psst_status stage_net_create(psst_network *net, const psst_pathway *paths, int32_t np);
 void stage_net_free(StageNet *sn);
 
+// The one-trial stage batch of a large network (for psst_integrate).
+psst_status stage_single_prepare(psst_network *net);
 psst_status stage_integrate_single(psst_network *net, float *state, const psst_stimulus *stim,
                                    float dt, int64_t n_steps, int64_t step0,
                                    const psst_record *rec, void *stream);

@@ -594,18 +594,24 @@ psst_status stage_batch_poll(StageBatch *sb, void *stream)
     return PSST_OK;
 }
 
+psst_status stage_single_prepare(psst_network *net)
+{
+    if (net->single) return PSST_OK;
+    psst_status st = stage_batch_create(net, 1, &net->single);
+    if (st != PSST_OK) return st;
+    net->single->fx.B = 1;
+    // the network's own non-finite flag is the one its poll reads
+    (void)hipFree(net->single->d_flag);
+    net->single->d_flag = nullptr;
+    return PSST_OK;
+}
+
 psst_status stage_integrate_single(psst_network *net, float *state, const psst_stimulus *stim,
                                    float dt, int64_t n_steps, int64_t step0,
                                    const psst_record *rec, void *stream)
 {
-    if (!net->single) {
-        psst_status st = stage_batch_create(net, 1, &net->single);
-        if (st != PSST_OK) return st;
-        net->single->fx.B = 1;
-        // the network's own non-finite flag is the one its poll reads
-        (void)hipFree(net->single->d_flag);
-        net->single->d_flag = nullptr;
-    }
+    psst_status st0 = stage_single_prepare(net);     // made at network creation
+    if (st0 != PSST_OK) return st0;
     StageBatch *sb = net->single;
     const int32_t *saved = sb->d_flag;
     sb->d_flag = net->d_flag;
