@@ -259,7 +259,9 @@ psst_status psst_batch_describe(const psst_batch *batch, char *buf, int32_t buf_
 /* ------------------------------------------------------------------------ */
 
 /* Gradients of a loss of the recorded potentials with respect to the synaptic
- * and intrinsic conductances, by reverse differentiation of the RK4 map.
+ * and intrinsic conductances, by reverse differentiation of the RK4 map (or
+ * of the batch's explicit method, psst_batch_set_tableau).  Networks of at
+ * most 512 neurons on the per-instance path, dense or sparse storage.
  * checkpoints: as written by psst_integrate_batch(..., K) for the same
  * stimulus, dt, n_steps and step0.  dL_dV: device [n_steps x n_total],
  * row k = dL/dV after global step step0 + k + 1.
@@ -270,7 +272,10 @@ psst_status psst_batch_describe(const psst_batch *batch, char *buf, int32_t buf_
  * instance, per-neuron arrays [n_total]); per_instance = 0: all instances
  * must share one network and outputs hold the sum over instances
  * (grad_g [network's blocks], per-neuron arrays [n]).  Sums over time and
- * instances use compensated float32.  Outputs are overwritten.
+ * instances use compensated float32.  Outputs are overwritten.  The
+ * batch's adjoint workspace (per instance K steps of stage records, float64)
+ * is allocated on the first call and grown when a later call needs more;
+ * calls that fit it allocate nothing.
  * Errors: INVALID_ARGUMENT, UNSUPPORTED, DEVICE, OUT_OF_MEMORY. */
 psst_status psst_adjoint(psst_batch *batch, const float *checkpoints, int32_t K,
                          const psst_stimulus *stim, float dt_ms, int64_t n_steps,
