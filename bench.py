@@ -217,6 +217,8 @@ def bench_large(args, torch, psst, W, dev, stream):
                         "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4),
                         "traffic": traffic,
                         "traffic_GBps": round(traffic / stage_s / 1e9, 1) if traffic else None,
+                        "traffic_frac": (round(traffic / stage_s / 1e9 / HBM_PEAK_GBS, 4)
+                                         if traffic else None),
                         "kernel": "stage_kernel<4,2,1,2> (fp32 MFMA GEMM, 8 wavefronts, + fused "
                                   "RK stage)",
                         "avg_launch_ms": round(1e3 * stage_s, 4),
