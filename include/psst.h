@@ -30,6 +30,10 @@
  *     memory, e.g. from torch tensors); the library never frees them.
  *   - create/destroy/poll calls are synchronous; integrate and adjoint calls
  *     are asynchronous on the caller's HIP stream (NULL = default stream).
+ *   - A handle holds per-handle device state (control blocks, graphs,
+ *     workspaces, error flags): calls on one network or batch must be issued
+ *     from one host thread at a time and on one stream, or the caller orders
+ *     them; different handles are independent.
  *   - Units: mV, ms, nS (synaptic g), nA (injected current), uF/cm^2, mS/cm^2
  *     (intrinsic g).  With membrane area A (cm^2), 1 nS = 1e-6/A mS/cm^2 and
  *     1 nA = 1e-3/A uA/cm^2.
