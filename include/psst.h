@@ -30,6 +30,12 @@
  *     memory, e.g. from torch tensors); the library never frees them.
  *   - create/destroy/poll calls are synchronous; integrate and adjoint calls
  *     are asynchronous on the caller's HIP stream (NULL = default stream).
+ *   - Environment variables, for comparisons and tests (defaults are the
+ *     library's own choices): PSST_TUNE=0 and PSST_WG_SHAPE (batch and
+ *     psst_integrate launch shapes, see there), PSST_LDS_G=0 (conductances
+ *     never held in LDS: always streamed), PSST_ADJ_MODE=lacc|mma (how the
+ *     adjoint accumulates dL/dg), PSST_ADJ_BS=64|128|256|512 (adjoint
+ *     workgroup size, when it covers the batch's largest network).
  *   - A handle holds per-handle device state (control blocks, graphs,
  *     workspaces, error flags): calls on one network or batch must be issued
  *     from one host thread at a time and on one stream, or the caller orders
