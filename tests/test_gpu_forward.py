@@ -273,3 +273,32 @@ def test_config3_full_batch_sampled_parity():
                                       o["spike_count"], o["spike_t"], 50.0)
     _say(f"  spikes {total}, count mismatches {bad}, worst dt {worst:.2e} ms")
     assert bad == 0 and worst <= SPIKE_TOL
+
+
+def test_config3_full_horizon_rates():
+    """The batched workload's whole horizon, 500 ms (50,000 steps), for all
+    4096 networks in one batch; the runs are chaotic, so the comparison is the
+    population firing rate (PN and LN pooled over 16 instances stratified by
+    size) against the oracle, within 2 %."""
+    insts = W.config3(4096)
+    n = 50_000
+    _say("config3 full horizon: 4096 networks, 500 ms")
+    g = R.gpu_run(insts, n, rec_stride=0, spike_cap=1)
+    sizes = np.array([i.net.n for i in insts])
+    order = np.argsort(sizes, kind="stable")
+    pick = [int(b) for b in order[np.linspace(0, len(sizes) - 1, 16).astype(int)]]
+    o = R.oracle_run([insts[b] for b in pick], n, rec_stride=0, spike_cap=1)
+    offs = g["offsets"]
+    gp = gl = op = ol = 0.0
+    npn = nln = 0
+    k = 0
+    for b in pick:
+        net = insts[b].net
+        c = g["spike_count"][offs[b]:offs[b + 1]]
+        oc = o["spike_count"][k:k + net.n]
+        gp += c[:net.n_pn].sum(); op += oc[:net.n_pn].sum(); npn += net.n_pn
+        gl += c[net.n_pn:].sum(); ol += oc[net.n_pn:].sum(); nln += net.n - net.n_pn
+        k += net.n
+    for name, a, r, m in (("PN", gp, op, npn), ("LN", gl, ol, nln)):
+        _say(f"  {name}: {a / m / 0.5:.2f} Hz on the GPU, {r / m / 0.5:.2f} Hz in the oracle")
+        assert r > 0 and abs(a - r) <= RATE_TOL * r
