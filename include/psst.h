@@ -235,7 +235,9 @@ psst_status psst_network_poll(psst_network *net, void *hip_stream);
  * array, off_b = sum of the sizes of instances before b.  Creation also tunes
  * the launch shape on the device (timing a few short candidate runs) unless
  * the environment variable PSST_TUNE=0, or PSST_WG_SHAPE="<threads>x<neurons
- * per thread>" names a shape to use.  n in [1, 1 << 20]. */
+ * per thread>" names a shape to use; the result is kept for the process and
+ * reused by later batches of the same shape (instance count, sizes, matrix
+ * volume, storage, method).  n in [1, 1 << 20]. */
 psst_status psst_batch_create(psst_network *const *nets, int32_t n, psst_batch **out);
 psst_status psst_batch_destroy(psst_batch *batch);
 

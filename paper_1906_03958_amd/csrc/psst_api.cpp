@@ -9,7 +9,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/psst.h"
@@ -825,8 +828,28 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     BCHK(hipMalloc(&g.d_order, sizeof(int32_t) * g.order.size()));
     BCHK(hipMemcpy(g.d_order, g.order.data(), sizeof(int32_t) * g.order.size(), hipMemcpyHostToDevice));
     b->groups.push_back(g);
-    // launch-shape tuning on a scratch state
+    // launch-shape tuning on a scratch state, once per batch shape in the
+    // process: batches alike in count, sizes, matrix volume, storage and
+    // method (an autograd loop makes one per forward call) reuse the result
     const char *tenv = std::getenv("PSST_TUNE");
+    int64_t gsum = 0;
+    int nsparse = 0;
+    for (auto *q : b->nets) {
+        gsum += q->g_floats;
+        nsparse += q->sparse ? 1 : 0;
+    }
+    const auto tkey = std::make_tuple(n, b->nt, g.max_n, gsum, nsparse, b->gen, b->groups[0].lds);
+    static std::mutex tune_mu;
+    static std::map<decltype(tkey), std::pair<int, int>> tune_cache;
+    if (!fixed && !(tenv && tenv[0] == '0')) {
+        std::lock_guard<std::mutex> lock(tune_mu);
+        auto it = tune_cache.find(tkey);
+        if (it != tune_cache.end()) {
+            b->groups[0].bs = it->second.first;
+            b->groups[0].npt = it->second.second;
+            fixed = true;
+        }
+    }
     if (!fixed && !(tenv && tenv[0] == '0')) {
         float *scratch = nullptr;
         float *v0 = nullptr;
@@ -848,6 +871,8 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
             batch_free(b);
             return s;
         }
+        std::lock_guard<std::mutex> lock(tune_mu);
+        tune_cache[tkey] = {b->groups[0].bs, b->groups[0].npt};
     }
 #undef BCHK
     char buf[256];
