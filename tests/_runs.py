@@ -7,7 +7,6 @@ import numpy as np
 
 import oracle
 from paper_1906_03958_amd import psst
-from paper_1906_03958_amd import workloads as W
 
 
 def torch_dev():
