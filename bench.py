@@ -641,7 +641,7 @@ def main():
         threads = min(os.cpu_count() or 1, 16)
         t0 = time.perf_counter()
         otab = None if args.method == "rk4" else W.TABLEAUX[args.method]
-        res = oracle.run_many(sub, args.cpu_steps, dt=DT, rec_stride=10, threads=threads,
+        res = oracle.run_many(sub, args.cpu_steps, dt=float(np.float32(DT)), rec_stride=10, threads=threads,
                               tableau=otab)
         ct = time.perf_counter() - t0
         ns = sum(i.net.n for i in sub) * args.cpu_steps

@@ -5,6 +5,8 @@ CPU-baseline leg are the only callers.  The product path (the HIP library and
 its binding) never imports this package, and this package imports nothing from
 the product.  Inputs arrive as plain arrays or duck-typed objects with the
 generator's field names; every float32 input is widened to float64 exactly.
+The step dt is used as given: a caller comparing with a float32 integrator
+passes the float32 value of its step.
 
 Functions follow the paper's statement of the method: the initial value problem
 and the fourth-order Runge-Kutta step ("Brain simulations as computational

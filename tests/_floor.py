@@ -15,7 +15,9 @@ def conditioning_floor(inst, n_steps, dt=0.01):
     max over the run of |V_i(perturbed) - V_i(reference)| when neuron i's own
     inputs (V0_i and its constant current) move up by one float32 ulp.  The
     float32 inputs of the GPU path are exact, but a discrepancy of this size
-    in neuron i is indistinguishable from a one-ulp change of its inputs."""
+    in neuron i is indistinguishable from a one-ulp change of its inputs.
+    The step is taken as the float32 value the library integrates with."""
+    dt = float(np.float32(dt))
     ref = oracle.run(inst, n_steps, dt, rec_stride=1)[0]["v"]
     insts = []
     for i in range(inst.net.n):

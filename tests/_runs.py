@@ -82,8 +82,17 @@ def gpu_run(insts, n_steps, dt=0.01, rec_stride=1, spike_cap=0, batched=True,
     return out
 
 
+# The library takes the step as float32 (dt_ms in the C ABI); the oracle is
+# handed that same value, so both integrate the same discrete map.
+DT = float(np.float32(0.01))
+
+
+def step_f32(dt):
+    return float(np.float32(dt))
+
+
 def oracle_run(insts, n_steps, dt=0.01, rec_stride=1, spike_cap=0, threads=None, tableau=None):
-    res = oracle.run_many(insts, n_steps, dt=dt, rec_stride=rec_stride, spike_cap=spike_cap,
+    res = oracle.run_many(insts, n_steps, dt=step_f32(dt), rec_stride=rec_stride, spike_cap=spike_cap,
                           threads=threads, tableau=tableau)
     v = np.concatenate([r[0]["v"] for r in res], axis=1) if rec_stride else None
     cnt = np.concatenate([r[0]["spike_count"] for r in res])

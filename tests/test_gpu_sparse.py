@@ -131,7 +131,7 @@ def test_sparse_adjoint_equals_dense_bitwise_and_oracle():
     inst = insts[k]
     off = nt - inst.net.n
     on = oracle.OracleNet(inst.net)
-    ref = oracle.adjoint(on, oracle.init_state(on, inst.v0), inst.stim, 0.01, n_steps,
+    ref = oracle.adjoint(on, oracle.init_state(on, inst.v0), inst.stim, R.DT, n_steps,
                          dl[:, off:].astype(np.float64))
     gsz = sum(int(p.g_nS.size) for p in inst.net.pathways)
     got = {"g": s[0][-gsz:], "g_Na": s[1][off:], "g_K": s[2][off:], "g_L": s[3][off:]}

@@ -173,7 +173,7 @@ def test_tableau_adjoint_matches_oracle(name):
     gg = gg.cpu().numpy().reshape(B, gs)
     for t in range(B):
         y0 = oracle.init_state(on, v0[t])
-        ref = oracle.adjoint(on, y0, W.Stimulus(i_nA[t]), 0.01, n_steps,
+        ref = oracle.adjoint(on, y0, W.Stimulus(i_nA[t]), R.DT, n_steps,
                              dl[:, t * ev.n:(t + 1) * ev.n].astype(np.float64), tableau=tab)
         for key, got in (("g", gg[t]), ("g_Na", gna.cpu().numpy()[t * ev.n:(t + 1) * ev.n]),
                          ("g_K", gk.cpu().numpy()[t * ev.n:(t + 1) * ev.n]),
@@ -219,7 +219,7 @@ def test_tableau_adjoint_after_rk4_on_the_same_batch():
     on = oracle.OracleNet(ev)
     for t in range(B):
         y0 = oracle.init_state(on, v0[t])
-        ref = np.asarray(oracle.adjoint(on, y0, W.Stimulus(i_nA[t]), 0.01, n_steps,
+        ref = np.asarray(oracle.adjoint(on, y0, W.Stimulus(i_nA[t]), R.DT, n_steps,
                                         dl[:, t * ev.n:(t + 1) * ev.n].astype(np.float64),
                                         tableau=W.TABLEAUX["heun"])["g"], np.float64)
         nrm = np.linalg.norm(outs["heun"][t] - ref) / np.linalg.norm(ref)
