@@ -51,7 +51,9 @@
  * each state variable is stored as a float32 pair (value, compensation) whose
  * sum is the state after every step, rounded to 48 significant bits.  Large
  * shared networks on the per-stage path (more than 1024 neurons) take the
- * synaptic sums from a float32 matrix-core GEMM instead.
+ * synaptic sums from a float32 matrix-core GEMM instead: float32 activations,
+ * float32 sums over groups of 16 presynaptic columns, the group sums added in
+ * float64.
  */
 #ifndef PSST_H
 #define PSST_H

@@ -4,7 +4,9 @@
 // "Circumventing memory constraints", item 1: the synaptic update as a
 // matrix multiplication):
 //   A[i][b] = sum_k G[i][k] X_q[b][k]      float32 GEMM on the matrix cores,
-//                                          one accumulator set per synapse class
+//                                          one accumulator set per synapse class;
+//                                          each 16-column group's float32 sum is
+//                                          added to float64 totals
 //   f = rhs(Y_q, cg * A, I(g))             float64, fused epilogue
 //   acc += w_q f; Y_{q+1} = y + c_{q+1} dt f; X_{q+1} = x(Y_{q+1})
 // and at q = 3 the combine y <- y + dt/6 acc, spikes and records.  A generic
@@ -19,7 +21,11 @@
 // feeds v_mfma_f32_16x16x4f32.  Within a 16-column group, lane l at sub-step
 // s takes column 4 (l / 16) + s, so each lane reads its four A and four B
 // values with one 16-byte LDS load; the column order of the sum is fixed, so
-// results are deterministic.
+// results are deterministic.  A float32 running sum over all K columns would
+// carry a rounding error growing with K (16384 here); each 16-column group
+// therefore starts from zero on the matrix cores (four chained products of
+// four columns) and its sum is added in float64, so float32 rounding acts on
+// 16-term sums of non-negative products only.
 //
 // Between launches the per-(neuron, trial) stage input Y and accumulator acc
 // live in a float64 workspace; activations X are double-buffered float32.
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
     constexpr int NTH = 64 * WR * WC;           // threads per workgroup
     static_assert(WR * BR * 16 == MT, "tile rows");
     constexpr int TILE_F = 2 * (MT + NTILE) * LDK;
-    constexpr int ACC_F = 3 * MT * (NTILE + 1);
+    constexpr int ACC_F = 2 * 3 * MT * (NTILE + 1);  // float64 totals
     extern __shared__ float smem[];                 // max(TILE_F, ACC_F) floats
     float *sG = smem;                       // [2][MT * LDK]
     float *sX = smem + 2 * MT * LDK;        // [2][NTILE * LDK]
@@ -137,13 +143,15 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
     const float *X = (k_launch & 1) ? fx.X1 : fx.X0;
     float *Xn = (k_launch & 1) ? fx.X0 : fx.X1;
 
-    floatx4 acc[3][BR][BC];
+    double acc[3][BR][BC][4];
 #pragma unroll
     for (int t = 0; t < 3; ++t)
 #pragma unroll
         for (int br = 0; br < BR; ++br)
 #pragma unroll
-            for (int bc = 0; bc < BC; ++bc) acc[t][br][bc] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int bc = 0; bc < BC; ++bc)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[t][br][bc][r] = 0.0;
 
     // tile loaders: a G tile is MT x KT floats = 8 float4 per thread, an X
     // tile NTILE x KT floats = NTILE / 8 float4 per thread; the next tile is
@@ -181,6 +189,11 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
             __builtin_amdgcn_iglp_opt(1);
 #pragma unroll
             for (int kk = 0; kk < KT / 16; ++kk) {
+                floatx4 tacc[BR][BC];
+#pragma unroll
+                for (int br = 0; br < BR; ++br)
+#pragma unroll
+                    for (int bc = 0; bc < BC; ++bc) tacc[br][bc] = floatx4{0.f, 0.f, 0.f, 0.f};
                 floatx4 a[BR], bv[BC];
                 const int kq = kk * 16 + 4 * (lane >> 4);
 #pragma unroll
@@ -199,14 +212,21 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
                     for (int br = 0; br < BR; ++br)
 #pragma unroll
                         for (int bc = 0; bc < BC; ++bc)
-                            acc[blk][br][bc] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                a[br][s], bv[bc][s], acc[blk][br][bc], 0, 0, 0);
+                            tacc[br][bc] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                a[br][s], bv[bc][s], tacc[br][bc], 0, 0, 0);
+#pragma unroll
+                for (int br = 0; br < BR; ++br)
+#pragma unroll
+                    for (int bc = 0; bc < BC; ++bc)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            acc[blk][br][bc][r] += (double)tacc[br][bc][r];
             }
         }
     }
     __syncthreads();
     // accumulators to LDS: lane holds rows 4 (lane / 16) + r, column lane % 16
-    float *sA = smem;                       // [3][MT][NTILE + 1]
+    double *sA = reinterpret_cast<double *>(smem);   // [3][MT][NTILE + 1]
 #pragma unroll
     for (int t = 0; t < 3; ++t)
 #pragma unroll
@@ -503,7 +523,7 @@ static int stage_threads(int ntile) { return ntile == 16 ? 256 : 512; }
 static size_t stage_lds_bytes(int ntile)
 {
     const size_t tile = 2 * (size_t)(MT + ntile) * LDK;
-    const size_t accf = 3 * (size_t)MT * (ntile + 1);
+    const size_t accf = 2 * 3 * (size_t)MT * (ntile + 1);   // float64 totals
     return sizeof(float) * (tile > accf ? tile : accf);
 }
 

@@ -52,6 +52,30 @@ def test_stage_path_2048_neurons_8_trials():
     assert np.abs(y[1:5] - o["state"][1:5]).max() < 1e-5
 
 
+def test_stage_path_50ms_parity_and_spikes():
+    """The literal forward gate on the per-stage path: max |dV| <= 1e-3 mV
+    over 0-50 ms and spike times within 0.05 ms, 2048 neurons, two of eight
+    trials followed by the oracle (float32 matrix-core sums, the path's
+    largest error source, accumulate over 5000 steps)."""
+    net = W.all_pairs_network(40, 0, 1536, 512, g_max=0.1)
+    insts = _trials(net, 40, 8)
+    n = 5000
+    _say("stage path: 2048 neurons x 8 trials, 50 ms")
+    g = _gpu_trials(net, insts, n, rec_stride=1, spike_cap=64)
+    pick = [0, 7]
+    o = R.oracle_run([insts[t] for t in pick], n, rec_stride=1, spike_cap=64, threads=2)
+    for k, t in enumerate(pick):
+        a, b = t * net.n, (t + 1) * net.n
+        oa, ob = k * net.n, (k + 1) * net.n
+        dv = np.abs(g["v"][:, a:b].astype(np.float64) - o["v"][:, oa:ob]).max()
+        bad, worst, total = R.spike_match(g["spike_count"][a:b], g["spike_t"][a:b],
+                                          o["spike_count"][oa:ob], o["spike_t"][oa:ob], 50.0)
+        _say(f"  trial {t}: max|dV| 0-50 ms {dv:.2e} mV, spikes {total}, count mismatches "
+             f"{bad}, worst dt {worst:.2e} ms")
+        assert dv <= 1e-3, (t, dv)
+        assert bad == 0 and worst <= 0.05 and total > 0
+
+
 def test_stage_path_slow_gaba_and_pulses():
     # an AL-shaped network above the per-workgroup limit: 900 PN + 300 LN with
     # cholinergic, fast-GABA and slow-GABA pathways and pulse stimuli
@@ -108,12 +132,12 @@ def test_stage_path_single_network_integrate_and_chunking():
 
 def test_config4_full_size_sampled_trials():
     # the full 16384-neuron network, 64 trials on the GPU; the oracle follows
-    # two of the trials for a few steps
+    # two of the trials for 100 steps (about a minute of oracle time each)
     from paper_1906_03958_amd import psst
     import torch
     net = W.config4_network()
     insts = _trials(net, 4, W.CONFIG4_TRIALS)
-    steps = 3
+    steps = 100
     _say("config4: 16384 neurons x 64 trials,", steps, "steps")
     h = psst.network_create(net)
     g = R.gpu_run(insts, steps, rec_stride=1, nets=[h] * len(insts))
