@@ -247,6 +247,29 @@ def test_compensated_state_against_closed_form(batched):
     assert err_f32 > 1e3 * 1e-7                 # the gate would catch a dropped compensation
 
 
+@pytest.mark.parametrize("batched", [False, True], ids=["plain", "batched"])
+def test_spike_time_on_a_passive_crossing(batched):
+    """Spike detection against a closed form: a passive membrane driven to
+    V_inf > 0 crosses 0 mV once, between V_n = V_inf + R(z)^n (V0 - V_inf)
+    and V_{n+1}; the spike time is (n + (0 - V_n) / (V_{n+1} - V_n)) dt, stored
+    as float32.  A neuron settling below 0 mV records none."""
+    I = np.array([3.0, 1.0])
+    inst = W.uncoupled(I, np.full(2, -65.0), params=dict(g_Na=0.0, g_K=0.0, g_L=0.3))
+    N = 600
+    g = R.gpu_run([inst], N, rec_stride=0, spike_cap=4, batched=batched)
+    p = {k: np.asarray(v, np.float64) for k, v in inst.net.params.items()}
+    ci = 1e-3 / float(np.float32(W.AREA_CM2))
+    dt = R.DT
+    z = -p["g_L"][0] * dt / p["C_m"][0]
+    vinf = p["E_L"][0] + ci * float(np.float32(I[0])) / p["g_L"][0]
+    v = vinf + (1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24) ** np.arange(N + 1) * (-65.0 - vinf)
+    n = int(np.argmax(v >= 0.0)) - 1
+    t = (n + (0.0 - v[n]) / (v[n + 1] - v[n])) * dt
+    _say(f"  spike at {g['spike_t'][0, 0]:.7f} ms, closed form {t:.7f} ms")
+    assert list(g["spike_count"]) == [1, 0]
+    assert abs(float(g["spike_t"][0, 0]) - t) <= 0.5 * np.spacing(np.float32(t)) + 1e-9
+
+
 def test_edge_cases():
     import torch
     from paper_1906_03958_amd import psst

@@ -60,6 +60,28 @@ def test_rk4_amplification_passive_membrane():
     assert abs(R4(-1.5) - 0.2734375) < 1e-16
 
 
+def test_spike_time_on_a_passive_crossing():
+    # A spike is an upward crossing of 0 mV between two steps, timed by linear
+    # interpolation between them.  A passive membrane driven to V_inf > 0
+    # rises monotonically, V_n = V_inf + R(z)^n (V0 - V_inf): exactly one
+    # crossing, at the first n with V_{n+1} >= 0, at time
+    # (n + (0 - V_n) / (V_{n+1} - V_n)) dt.  The second neuron settles below
+    # 0 mV and never spikes.
+    I = np.array([3.0, 1.0])
+    inst = W.uncoupled(I, np.full(2, -65.0), params=dict(g_Na=0.0, g_K=0.0, g_L=0.3))
+    p = {k: np.asarray(v, np.float64) for k, v in inst.net.params.items()}
+    dt, N = 0.01, 600
+    res, _ = oracle.run(inst, N, dt=dt, rec_stride=0, spike_cap=4)
+    z = -p["g_L"][0] * dt / p["C_m"][0]
+    vinf = p["E_L"][0] + CI * float(np.float32(I[0])) / p["g_L"][0]
+    v = vinf + R4(z) ** np.arange(N + 1) * (-65.0 - vinf)
+    n = int(np.argmax(v >= 0.0)) - 1
+    assert v[n] < 0.0 <= v[n + 1] and 200 < n < N - 100
+    t = (n + (0.0 - v[n]) / (v[n + 1] - v[n])) * dt
+    assert list(res["spike_count"]) == [1, 0]
+    assert abs(res["spike_t"][0, 0] - t) < 1e-12
+
+
 def test_rk4_amplification_gate_with_clamped_voltage():
     # g_Na = g_K = 0, I = 0, V0 = E_L: dV/dt = 0 exactly, so each gate obeys
     # x' = alpha - (alpha + beta) x with constant rates.
