@@ -78,17 +78,17 @@ static const int kMaxAdjointNeurons = 512;  // largest network of the adjoint
 static void net_free(psst_network *n)
 {
     if (!n) return;
-    hipFree(n->d_gt);
-    hipFree(n->d_gtb);
-    hipFree(n->d_prm);
-    hipFree(n->d_kin);
-    hipFree(n->d_maskt);
-    hipFree(n->d_desc);
-    hipFree(n->d_order);
-    hipFree(n->d_flag);
-    hipFree(n->d_paths);
-    hipFree(n->d_spcol);
-    hipFree(n->d_spval);
+    (void)hipFree(n->d_gt);
+    (void)hipFree(n->d_gtb);
+    (void)hipFree(n->d_prm);
+    (void)hipFree(n->d_kin);
+    (void)hipFree(n->d_maskt);
+    (void)hipFree(n->d_desc);
+    (void)hipFree(n->d_order);
+    (void)hipFree(n->d_flag);
+    (void)hipFree(n->d_paths);
+    (void)hipFree(n->d_spcol);
+    (void)hipFree(n->d_spval);
     stage_batch_free(n->single);
     stage_net_free(n->stage);
     delete n;
@@ -452,7 +452,7 @@ static size_t max_lds_per_block()
     static size_t cached = 0;
     if (!cached) {
         int dev = 0;
-        hipGetDevice(&dev);
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cached = prop.sharedMemPerBlock;
         if (!cached) cached = 65536;
@@ -626,11 +626,11 @@ extern "C" psst_status psst_network_poll(psst_network *net, void *stream)
 static void batch_free(psst_batch *b)
 {
     if (!b) return;
-    for (auto &g : b->groups) hipFree(g.d_order);
-    hipFree(b->d_desc);
-    hipFree(b->d_flag);
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    for (auto &g : b->groups) (void)hipFree(g.d_order);
+    (void)hipFree(b->d_desc);
+    (void)hipFree(b->d_flag);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     stage_batch_free(b->stage);
     adjoint_free(b->adj);
     stream_bufs_free(b->strm);
@@ -670,6 +670,16 @@ static psst_status launch_group(const Group &g, bool gen, WGArgs &a, hipStream_t
     return PSST_OK;
 }
 
+// Two timing events, destroyed on every return path.
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~EventPair()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 // Time candidate shapes for one group on a scratch state (short run, no
 // stimulus, no recording) and keep the fastest.
 static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream_t s)
@@ -683,9 +693,9 @@ static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream
         cands.push_back({v->bs, v->npt});
     }
     if (cands.size() <= 1) return PSST_OK;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    EventPair ev;
+    HIPCHK(hipEventCreate(&ev.e0));
+    HIPCHK(hipEventCreate(&ev.e1));
     float best = 1e30f;
     int bbs = g.bs, bnpt = g.npt;
     for (auto &c : cands) {
@@ -696,16 +706,14 @@ static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream
         psst_status st = launch_group(t, b->gen, a, s);        // warm-up
         if (st != PSST_OK) return st;
         a.n_steps = 16;
-        HIPCHK(hipEventRecord(e0, s));
+        HIPCHK(hipEventRecord(ev.e0, s));
         if ((st = launch_group(t, b->gen, a, s)) != PSST_OK) return st;
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventRecord(ev.e1, s));
+        HIPCHK(hipEventSynchronize(ev.e1));
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        HIPCHK(hipEventElapsedTime(&ms, ev.e0, ev.e1));
         if (ms < best) { best = ms; bbs = c.first; bnpt = c.second; }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     g.bs = bbs;
     g.npt = bnpt;
     return PSST_OK;
@@ -851,26 +859,35 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
         }
     }
     if (!fixed && !(tenv && tenv[0] == '0')) {
+        // scratch state for the timing runs; every buffer is released on
+        // every path before an error is returned
         float *scratch = nullptr;
         float *v0 = nullptr;
-        BCHK(hipMalloc(&scratch, sizeof(float) * 14 * b->nt));
-        BCHK(hipMalloc(&v0, sizeof(float) * b->nt));
-        std::vector<float> hv(b->nt, -65.f);
-        BCHK(hipMemcpy(v0, hv.data(), sizeof(float) * b->nt, hipMemcpyHostToDevice));
-        hipStream_t st;
-        BCHK(hipStreamCreate(&st));
-        s = launch_init(b->d_desc, n, v0, scratch, b->nt, st);
-        for (auto &g : b->groups)
-            if (s == PSST_OK) s = tune_group(b, g, scratch, st);
-        hipStreamSynchronize(st);
-        hipStreamDestroy(st);
-        hipFree(scratch);
-        hipFree(v0);
-        BCHK(hipMemset(b->d_flag, 0, sizeof(int32_t)));
+        hipStream_t st = nullptr;
+        hipError_t e = hipMalloc(&scratch, sizeof(float) * 14 * b->nt);
+        if (e == hipSuccess) e = hipMalloc(&v0, sizeof(float) * b->nt);
+        if (e == hipSuccess) {
+            std::vector<float> hv(b->nt, -65.f);
+            e = hipMemcpy(v0, hv.data(), sizeof(float) * b->nt, hipMemcpyHostToDevice);
+        }
+        if (e == hipSuccess) e = hipStreamCreate(&st);
+        if (e == hipSuccess) {
+            s = launch_init(b->d_desc, n, v0, scratch, b->nt, st);
+            for (auto &g : b->groups)
+                if (s == PSST_OK) s = tune_group(b, g, scratch, st);
+            e = hipStreamSynchronize(st);
+        }
+        if (st) (void)hipStreamDestroy(st);
+        (void)hipFree(scratch);
+        (void)hipFree(v0);
+        if (e != hipSuccess && s == PSST_OK)
+            s = fail(e == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY : PSST_ERR_DEVICE,
+                     "launch-shape tuning failed: %s", hipGetErrorString(e));
         if (s != PSST_OK) {
             batch_free(b);
             return s;
         }
+        BCHK(hipMemset(b->d_flag, 0, sizeof(int32_t)));
         std::lock_guard<std::mutex> lock(tune_mu);
         tune_cache[tkey] = {b->groups[0].bs, b->groups[0].npt};
     }

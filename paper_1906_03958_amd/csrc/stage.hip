@@ -43,6 +43,16 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int KT = 128;       // presynaptic columns per LDS tile
 constexpr int MT = 64;        // postsynaptic rows per workgroup
 constexpr int LDK = KT + 4;   // LDS row stride in floats
+
+// Dynamic LDS of a stage launch with NTILE trials per workgroup, in floats:
+// the double-buffered G and X tiles during the products, then the float64
+// totals of the three synapse classes for the epilogue (same memory).
+constexpr size_t tile_floats(int ntile) { return 2 * (size_t)(MT + ntile) * LDK; }
+constexpr size_t acc_floats(int ntile) { return 2 * 3 * (size_t)MT * (ntile + 1); }
+constexpr size_t stage_lds_floats(int ntile)
+{
+    return tile_floats(ntile) > acc_floats(ntile) ? tile_floats(ntile) : acc_floats(ntile);
+}
 constexpr int NVS = NVAR;
 
 struct StageFixed {
@@ -127,9 +137,7 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
     constexpr int NTILE = WC * BC * 16;
     constexpr int NTH = 64 * WR * WC;           // threads per workgroup
     static_assert(WR * BR * 16 == MT, "tile rows");
-    constexpr int TILE_F = 2 * (MT + NTILE) * LDK;
-    constexpr int ACC_F = 2 * 3 * MT * (NTILE + 1);  // float64 totals
-    extern __shared__ float smem[];                 // max(TILE_F, ACC_F) floats
+    extern __shared__ float smem[];                 // stage_lds_floats(NTILE) floats
     float *sG = smem;                       // [2][MT * LDK]
     float *sX = smem + 2 * MT * LDK;        // [2][NTILE * LDK]
 
@@ -520,12 +528,7 @@ static const void *stage_fn(int ntile, bool gen)
 
 static int stage_threads(int ntile) { return ntile == 16 ? 256 : 512; }
 
-static size_t stage_lds_bytes(int ntile)
-{
-    const size_t tile = 2 * (size_t)(MT + ntile) * LDK;
-    const size_t accf = 2 * 3 * (size_t)MT * (ntile + 1);   // float64 totals
-    return sizeof(float) * (tile > accf ? tile : accf);
-}
+static size_t stage_lds_bytes(int ntile) { return sizeof(float) * stage_lds_floats(ntile); }
 
 // One step as a graph: its stages (4 for RK4) then the step-counter advance.
 static psst_status build_graph(StageBatch *sb)
