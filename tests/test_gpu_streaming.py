@@ -7,7 +7,6 @@ import numpy as np
 import pytest
 
 from paper_1906_03958_amd import workloads as W
-from tests import _runs as R
 
 pytestmark = pytest.mark.gpu
 
