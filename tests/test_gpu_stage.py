@@ -174,3 +174,27 @@ def test_stage_path_ragged_tiles():
         assert dv <= 1e-3, (t, dv)
         np.testing.assert_array_equal(g["spike_count"][a:a + net.n],
                                       o["spike_count"][k * net.n:(k + 1) * net.n])
+
+
+def test_stage_path_trial_invariance_bitwise():
+    """A trial's trajectory on the per-stage path does not depend on the
+    other trials of its batch: 70 trials (64-trial tiles, the second one
+    ragged) vs ten of them alone (16-trial tiles) vs the same ten in reverse
+    order, bit for bit."""
+    net = W.all_pairs_network(44, 0, 816, 272, g_max=0.1)
+    insts = _trials(net, 44, 70)
+    n = 100
+    a = _gpu_trials(net, insts, n, rec_stride=1, spike_cap=8)
+    sub = list(range(60, 70))
+    b = _gpu_trials(net, [insts[t] for t in sub], n, rec_stride=1, spike_cap=8)
+    c = _gpu_trials(net, [insts[t] for t in sub[::-1]], n, rec_stride=1, spike_cap=8)
+    m = net.n
+    for k, t in enumerate(sub):
+        ka = slice(t * m, (t + 1) * m)
+        kb = slice(k * m, (k + 1) * m)
+        kc = slice((len(sub) - 1 - k) * m, (len(sub) - k) * m)
+        np.testing.assert_array_equal(a["v"][:, ka], b["v"][:, kb])
+        np.testing.assert_array_equal(a["v"][:, ka], c["v"][:, kc])
+        np.testing.assert_array_equal(a["state"][:, :, ka], b["state"][:, :, kb])
+        np.testing.assert_array_equal(a["spike_t"][ka], c["spike_t"][kc])
+    _say("  per-stage path: 10 trials bitwise equal in batches of 70, 10 and 10 reversed")
