@@ -42,6 +42,28 @@ def test_state_init_matches_oracle():
     np.testing.assert_allclose(y, yo, rtol=0, atol=1e-13)
 
 
+def test_steady_state_gates_over_a_voltage_grid():
+    """The rate functions through the initial state x_inf(V0) = a / (a + b)
+    on a dense grid of V0 over [-150, 100] mV plus the removable
+    singularities of a_m (-40 mV) and a_n (-55 mV), exactly and a little off
+    them on both sides of where the kernels switch from the series of
+    u / (1 - e^-u) to the quotient: every gate within 1e-13 of the oracle."""
+    import oracle
+    grid = np.arange(-150.0, 100.0 + 1e-9, 1.25)
+    sing = []
+    for vs in (-40.0, -55.0):
+        for d in (0.0, 1e-6, 1e-3, 0.1, 0.49, 0.5, 0.51, 1.0):
+            sing += [vs - d, vs + d]
+    v0 = np.unique(np.concatenate([grid, sing])).astype(np.float32)
+    inst = W.uncoupled(np.zeros(len(v0)), v0)
+    g = R.gpu_run([inst], 0, rec_stride=0)
+    y = R.state_value(g["state"])
+    yo = oracle.init_state(inst.net, inst.v0)
+    err = np.abs(y[1:4] - yo[1:4]).max()
+    _say(f"  {len(v0)} voltages: max |x_inf gpu - oracle| = {err:.2e}")
+    assert err <= 1e-13
+
+
 def test_config1_parity_50ms_and_spikes_100ms():
     for seed in (0, 1):
         inst = W.config1(seed)
