@@ -393,3 +393,26 @@ def test_config3_full_horizon_rates():
     for name, a, r, m in (("PN", gp, op, npn), ("LN", gl, ol, nln)):
         _say(f"  {name}: {a / m / 0.5:.2f} Hz on the GPU, {r / m / 0.5:.2f} Hz in the oracle")
         assert r > 0 and abs(a - r) <= RATE_TOL * r
+
+
+def test_readme_example_runs():
+    """The README's minimal-use snippet, executed as written, integrates the
+    20-neuron network within the forward gate of the oracle."""
+    import os
+    import oracle
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "README.md")).read()
+    lines = []
+    for line in text.split("## Minimal use from Python", 1)[1].splitlines()[1:]:
+        if line.strip() and not line.startswith("    "):
+            break                                   # end of the indented block
+        lines.append(line[4:])
+    code = "\n".join(lines)
+    assert "integrate_batch" in code
+    ns = {}
+    exec(compile(code, "README.md", "exec"), ns)
+    v = ns["v"].cpu().numpy()
+    ref, _ = oracle.run(ns["inst"], 1000, dt=R.DT)
+    dv = float(np.abs(v - ref["v"]).max())
+    _say(f"  README example: max|dV| vs oracle {dv:.2e} mV")
+    assert dv <= DV_TOL
