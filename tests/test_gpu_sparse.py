@@ -140,3 +140,26 @@ def test_sparse_adjoint_equals_dense_bitwise_and_oracle():
         nrm = np.linalg.norm(v - r) / np.linalg.norm(r)
         _say(f"  {key}: norm rel err {nrm:.2e}")
         assert nrm <= 1e-3, (key, nrm)
+
+
+def test_sparse_at_the_per_instance_limit():
+    """Sparse rows at the largest per-instance network, 1024 neurons
+    (768 PN + 256 LN, p = 0.1): bitwise the dense result (plain and batched)
+    and within the forward gate of the oracle over 3 ms."""
+    from paper_1906_03958_amd import psst
+    net = W.all_pairs_network(45, 0, 768, 256, p=0.1)
+    i_nA, v0 = W.trial_inputs(45, net.n, 1)
+    inst = W.Instance(net, v0[0], W.Stimulus(i_nA[0]))
+    n = 300
+    for batched in (True, False):
+        d = R.gpu_run([inst], n, rec_stride=1, spike_cap=16, batched=batched,
+                      nets=_nets([inst], psst.STORAGE_DENSE))
+        s = R.gpu_run([inst], n, rec_stride=1, spike_cap=16, batched=batched,
+                      nets=_nets([inst], psst.STORAGE_SPARSE))
+        np.testing.assert_array_equal(d["state"], s["state"])
+        np.testing.assert_array_equal(d["v"], s["v"])
+    o = R.oracle_run([inst], n, rec_stride=1, spike_cap=16)
+    dv = float(np.abs(s["v"] - o["v"]).max())
+    _say(f"  sparse 1024 neurons: max|dV| {dv:.2e} mV")
+    assert dv <= DV_TOL
+    np.testing.assert_array_equal(s["spike_count"], o["spike_count"])
