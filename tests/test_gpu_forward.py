@@ -416,3 +416,23 @@ def test_readme_example_runs():
     dv = float(np.abs(v - ref["v"]).max())
     _say(f"  README example: max|dV| vs oracle {dv:.2e} mV")
     assert dv <= DV_TOL
+
+
+def test_batch_reports_a_blow_up():
+    """A batch driven far beyond stability (dt = 5 ms) reports non-finite
+    states through psst_batch_poll, which then clears the flag."""
+    import torch
+    from paper_1906_03958_amd import psst
+    dev = torch.device("cuda:0")
+    insts = [W.config3_instance(b) for b in (1, 2)]
+    nets = [psst.network_create(i.net) for i in insts]
+    batch = psst.batch_create(nets)
+    st = torch.zeros(14 * batch.n_total, dtype=torch.float32, device=dev)
+    psst.batch_state_init(batch, torch.from_numpy(np.concatenate([i.v0 for i in insts])).to(dev),
+                          st)
+    stim = psst.pack_stimulus([i.stim for i in insts], dev)
+    psst.integrate_batch(batch, st, stim, 5.0, 200, 0)
+    with pytest.raises(psst.PsstError) as e:
+        psst.batch_poll(batch)
+    assert e.value.status == psst.ERR_NONFINITE
+    psst.batch_poll(batch)                           # flag was cleared

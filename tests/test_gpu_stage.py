@@ -198,3 +198,24 @@ def test_stage_path_trial_invariance_bitwise():
         np.testing.assert_array_equal(a["state"][:, :, ka], b["state"][:, :, kb])
         np.testing.assert_array_equal(a["spike_t"][ka], c["spike_t"][kc])
     _say("  per-stage path: 10 trials bitwise equal in batches of 70, 10 and 10 reversed")
+
+
+def test_stage_path_reports_a_blow_up():
+    """The per-stage path flags non-finite states too (dt = 5 ms, 1100
+    neurons x 2 trials); the poll clears the flag."""
+    from paper_1906_03958_amd import psst
+    import torch
+    dev = torch.device("cuda:0")
+    net = W.all_pairs_network(46, 0, 825, 275, g_max=0.1)
+    insts = _trials(net, 46, 2)
+    h = psst.network_create(net)
+    batch = psst.batch_create([h, h])
+    st = torch.zeros(14 * batch.n_total, dtype=torch.float32, device=dev)
+    psst.batch_state_init(batch, torch.from_numpy(np.concatenate([i.v0 for i in insts])).to(dev),
+                          st)
+    stim = psst.pack_stimulus([i.stim for i in insts], dev)
+    psst.integrate_batch(batch, st, stim, 5.0, 50, 0)
+    with pytest.raises(psst.PsstError) as e:
+        psst.batch_poll(batch)
+    assert e.value.status == psst.ERR_NONFINITE
+    psst.batch_poll(batch)
