@@ -219,3 +219,18 @@ def test_stage_path_reports_a_blow_up():
         psst.batch_poll(batch)
     assert e.value.status == psst.ERR_NONFINITE
     psst.batch_poll(batch)
+
+
+def test_stage_path_strided_records_across_chunks():
+    """Records every 7th step on the per-stage path, the run split at step 10
+    (not a multiple of the stride): the rows are exactly the stride-1 run's
+    rows at steps 7, 14, ..., 35, and the state is the same bit for bit."""
+    net = W.all_pairs_network(47, 0, 780, 260, g_max=0.1)
+    insts = _trials(net, 47, 3)
+    from paper_1906_03958_amd import psst
+    h = psst.network_create(net)
+    a = R.gpu_run(insts, 35, rec_stride=1, nets=[h] * 3)
+    b = R.gpu_run(insts, 35, rec_stride=7, nets=[h] * 3, chunks=[10, 25])
+    assert b["v"].shape[0] == 5
+    np.testing.assert_array_equal(b["v"], a["v"][6::7])
+    np.testing.assert_array_equal(b["state"], a["state"])
