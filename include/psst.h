@@ -207,8 +207,10 @@ typedef struct {
     int32_t spike_cap;
 } psst_record;
 
-/* Integrate one network (the plain one-network-per-launch form): n_steps
- * steps of the network's method (classical RK4 unless
+/* Integrate one network (the plain one-network-per-launch form; the RK4 step
+ * of "Brain simulations as computational graphs" iterated as a scan over the
+ * time grid, long runs resumed batch by batch per "Circumventing memory
+ * constraints", item 2): n_steps steps of the network's method (classical RK4 unless
  * psst_network_set_tableau says otherwise) of size dt_ms from global step
  * index step0 (time t = step0 * dt), state in/out.  Calling it with
  * (n1, step0) then (n2, step0 + n1) gives bitwise the same state and records
@@ -231,8 +233,11 @@ psst_status psst_network_poll(psst_network *net, void *hip_stream);
 /* Batches: many independent instances in one launch                         */
 /* ------------------------------------------------------------------------ */
 
-/* Batch of n instances; nets[b] may repeat (trials of one network share its
- * device conductances).  The batch keeps references: the networks must
+/* Batch of n instances, integrated side by side like the independent ODEs of
+ * the paper's Fig. 2b runtime comparison ("Motivation"), with the per-neuron
+ * equations vectorised across all of them ("Brain simulations as
+ * computational graphs", vectorisation paragraph); nets[b] may repeat
+ * (trials of one network share its device conductances).  The batch keeps references: the networks must
  * outlive it.  Instance b owns neurons [off_b, off_b + n_b) of every packed
  * array, off_b = sum of the sizes of instances before b.  Creation also tunes
  * the launch shape on the device (timing a few short candidate runs) unless
@@ -252,8 +257,9 @@ psst_status psst_batch_layout(const psst_batch *batch, int64_t *n_total, int64_t
 psst_status psst_batch_state_init(const psst_batch *batch, const float *v0, float *states,
                                   void *hip_stream);
 
-/* Integrate every instance of the batch by n_steps (same semantics as
- * psst_integrate per instance; instance results are bitwise independent of
+/* Integrate every instance of the batch by n_steps (the RK4 scan of "Brain
+ * simulations as computational graphs" for all instances in one launch; same
+ * semantics as psst_integrate per instance; instance results are bitwise independent of
  * the batch's order and composition).  states, stim, rec are packed over
  * n_total neurons.  checkpoints: NULL, or device [n_steps / K + 1 x n_words]
  * float32 receiving the state before global steps step0 + c K (c = 0, 1,
@@ -267,6 +273,19 @@ psst_status psst_batch_poll(psst_batch *batch, void *hip_stream);
 
 /* Text description of the tuned launch shape (for logs and benchmarks). */
 psst_status psst_batch_describe(const psst_batch *batch, char *buf, int32_t buf_len);
+
+/* Conductance bytes a forward launch of the batch reads, by the library's
+ * own placement of the matrices (for roofline accounting; "Circumventing
+ * memory constraints", item 1: the synaptic update is a product with the
+ * conductance matrices, so these bytes are its operand traffic):
+ * resident_bytes are read once per launch (the leading columns of every
+ * conductance chunk kept in LDS for the whole launch, or an instance's whole
+ * sparse rows), streamed_bytes once per stage evaluation (the rest; on the
+ * per-stage path of a large shared network, its whole padded matrix).  Trials
+ * that share one network count once per workgroup that reads it.  Either
+ * pointer may be NULL.  Synchronous, no device call. */
+psst_status psst_batch_conductance_bytes(const psst_batch *batch, int64_t *resident_bytes,
+                                         int64_t *streamed_bytes);
 
 /* ------------------------------------------------------------------------ */
 /* Discrete adjoint                                                          */

@@ -28,6 +28,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "psst_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# A separately built copy of the same source (the sanitizer test builds one
+# with address and undefined-behaviour checks) is loaded instead when named
+# here; it is used as is, never rebuilt.
+_LIB_OVERRIDE = os.environ.get("PSST_ORACLE_LIB")
 
 NVAR = 7
 VAR_NAMES = ("V", "m", "h", "n", "s", "r", "G")
@@ -67,9 +71,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = C.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+            L = C.CDLL(_LIB)
         dp, ip32, ip64 = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
         L.or_exprel.restype = C.c_double
         L.or_exprel.argtypes = [C.c_double]

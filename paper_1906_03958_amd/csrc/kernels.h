@@ -67,6 +67,20 @@ const void *init_kernel();
 // Column chunk width of the synaptic sums (fixed summation structure).
 constexpr int kChunkWidth = 64;
 
+// Leading columns of every conductance chunk that a workgroup keeps in LDS
+// for a whole launch: what its dynamic LDS (lds_bytes) leaves beside the two
+// float64 activation vectors and the nch float64 partial-sum rows of ld
+// entries, in whole columns of every chunk, at most the chunk width (all
+// columns when the instance has no dense chunks).  The kernels' set-up and
+// the host's byte accounting both use it.
+__host__ __device__ inline int resident_columns(int64_t lds_bytes, int ld, int nch)
+{
+    const int64_t room = lds_bytes - (int64_t)sizeof(double) * (2 + nch) * ld;
+    const int64_t per_col = (int64_t)sizeof(float) * nch * ld;
+    const int64_t R = per_col == 0 ? kChunkWidth : (room > 0 ? room / per_col : 0);
+    return (int)(R < kChunkWidth ? R : kChunkWidth);
+}
+
 // Column chunks of an instance: cholinergic, fast-GABA and slow-GABA columns.
 inline int n_chunks(int n, int n_pn, bool gabab)
 {

@@ -926,6 +926,48 @@ extern "C" psst_status psst_batch_describe(const psst_batch *b, char *buf, int32
     return PSST_OK;
 }
 
+extern "C" psst_status psst_batch_conductance_bytes(const psst_batch *b, int64_t *resident,
+                                                    int64_t *streamed)
+{
+    if (!b) return fail(PSST_ERR_INVALID_ARGUMENT, "batch is NULL");
+    int64_t res = 0, str = 0;
+    if (b->stage_path) {
+        str = stage_batch_matrix_bytes(b->stage);
+    } else {
+        for (const Group &g : b->groups) {
+            for (int32_t k : g.order) {
+                const psst_network *q = b->nets[k];
+                if (q->desc.flags & DESC_NOSYN) continue;
+                if (q->sparse) {
+                    // ELL rows (column index and value, 8 bytes per entry) go to
+                    // LDS for the launch when they fit beside the two
+                    // activation vectors
+                    const int64_t ents = (int64_t)(q->desc.sp_kf + q->desc.sp_kb) * q->ld;
+                    const int64_t room = (int64_t)g.lds - (int64_t)sizeof(double) * 2 * q->ld;
+                    (8 * ents <= room ? res : str) += 8 * ents;
+                    continue;
+                }
+                // chunk widths: cholinergic columns, fast-GABA columns, slow
+                // matrix, each cut at kChunkWidth; the first R columns of
+                // every chunk stay in LDS
+                const int R = resident_columns((int64_t)g.lds, q->ld, q->nch);
+                const int n_ln = q->n - q->n_pn;
+                const int spans[3] = {q->n_pn, n_ln, q->gabab ? n_ln : 0};
+                for (int t = 0; t < 3; ++t)
+                    for (int j0 = 0; j0 < spans[t]; j0 += kChunkWidth) {
+                        const int w = std::min(kChunkWidth, spans[t] - j0);
+                        const int r = std::min(w, R);
+                        res += (int64_t)sizeof(float) * q->ld * r;
+                        str += (int64_t)sizeof(float) * q->ld * (w - r);
+                    }
+            }
+        }
+    }
+    if (resident) *resident = res;
+    if (streamed) *streamed = str;
+    return PSST_OK;
+}
+
 extern "C" psst_status psst_batch_state_init(const psst_batch *b, const float *v0, float *states,
                                              void *stream)
 {

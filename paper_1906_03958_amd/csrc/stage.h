@@ -34,6 +34,8 @@ psst_status stage_batch_integrate(StageBatch *sb, float *states, const psst_stim
                                   float dt, int64_t n_steps, int64_t step0,
                                   const psst_record *rec, float *ckpt, int32_t K, void *stream);
 psst_status stage_batch_poll(StageBatch *sb, void *stream);
+// Bytes of the padded conductance matrix one stage launch reads.
+int64_t stage_batch_matrix_bytes(const StageBatch *sb);
 // Switch between classical RK4 (gen = false) and a generic explicit method;
 // the step graph is rebuilt on the next call.
 void stage_batch_set_method(StageBatch *sb, bool gen, const psst::Tab &tab);

@@ -517,6 +517,14 @@ void stage_batch_free(StageBatch *sb)
 
 const char *stage_batch_describe(const StageBatch *sb) { return sb ? sb->desc.c_str() : ""; }
 
+// Each workgroup column (one tile of trials) reads the whole padded matrix
+// once per stage launch.
+int64_t stage_batch_matrix_bytes(const StageBatch *sb)
+{
+    const StageNet *sn = sb->net->stage;
+    return (int64_t)sizeof(float) * sn->Mp * sn->Kp * (sb->Bp / sb->ntile);
+}
+
 static const void *stage_fn(int ntile, bool gen)
 {
     if (gen)

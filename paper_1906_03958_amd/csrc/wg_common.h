@@ -520,8 +520,6 @@ __device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int6
     w.gt = d.gt;
     w.gtb = d.gtb;
     const int64_t room = lds_bytes - (int64_t)sizeof(double) * (2 + w.nch) * d.ld;
-    const int64_t per_col = (int64_t)sizeof(float) * w.nch * d.ld;
-    int64_t R = per_col == 0 ? CW : (room > 0 ? room / per_col : 0);
     // sparse rows: the whole ELL (columns then values) into LDS when it fits
     w.sp_lds = false;
     if (w.sparse) {
@@ -538,7 +536,7 @@ __device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int6
             w.sp_lds = true;
         }
     }
-    w.R = (int)(R < CW ? R : CW);
+    w.R = resident_columns(lds_bytes, d.ld, w.nch);
     const int tid = threadIdx.x;
     if (w.R > 0) {
         const int q = d.ld >> 2;

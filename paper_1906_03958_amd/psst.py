@@ -34,7 +34,7 @@ EXPORTS = (
     "psst_batch_state_init", "psst_integrate_batch", "psst_batch_poll",
     "psst_batch_describe", "psst_adjoint", "psst_network_grad_size",
     "psst_network_set_tableau", "psst_batch_set_tableau", "psst_network_create_storage",
-    "psst_integrate_batch_streamed",
+    "psst_integrate_batch_streamed", "psst_batch_conductance_bytes",
 )
 STORAGE_AUTO, STORAGE_DENSE, STORAGE_SPARSE = 0, 1, 2
 
@@ -134,6 +134,7 @@ def lib():
             "psst_network_create_storage": (i32, [C.POINTER(NeuronParams), i32, C.POINTER(Pathway),
                                                   i32, C.POINTER(Kinetics), i32, C.POINTER(vp)]),
             "psst_batch_set_tableau": (i32, [vp, C.POINTER(Tableau)]),
+            "psst_batch_conductance_bytes": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -405,6 +406,14 @@ def batch_describe(batch: Batch) -> str:
     buf = C.create_string_buffer(4096)
     _check(lib().psst_batch_describe(batch.handle, buf, 4096))
     return buf.value.decode()
+
+
+def batch_conductance_bytes(batch: Batch):
+    """(resident, streamed): conductance bytes a forward launch reads once per
+    launch and once per stage evaluation."""
+    r, s = C.c_int64(), C.c_int64()
+    _check(lib().psst_batch_conductance_bytes(batch.handle, C.byref(r), C.byref(s)))
+    return int(r.value), int(s.value)
 
 
 def adjoint(batch: Batch, checkpoints, K: int, stim: Optional[DeviceStimulus], dt_ms: float,

@@ -174,6 +174,9 @@ def test_null_handles_rejected():
     assert L.psst_batch_create(arr, 0, C.byref(h)) == psst.ERR_INVALID_ARGUMENT
     nw, nv = C.c_int64(), C.c_int32()
     assert L.psst_state_layout(None, C.byref(nw), C.byref(nv)) == psst.ERR_INVALID_ARGUMENT
+    r, s = C.c_int64(), C.c_int64()
+    assert L.psst_batch_conductance_bytes(None, C.byref(r), C.byref(s)) == \
+        psst.ERR_INVALID_ARGUMENT
 
 
 def test_missing_library_fails_loudly(monkeypatch):

@@ -14,6 +14,8 @@ import pytest
 import oracle
 from paper_1906_03958_amd import workloads as W
 from tests._floor import conditioning_floor
+from tests._pins import (RELEASE_VK, clamped_release_network, gate_closed_form,
+                          release_points, slow_gaba_half_closed_form)
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -141,6 +143,48 @@ def test_rk4_amplification_synaptic_gate_and_single_synapse_current():
     expect = -0.375 * y[4, 0] * (-20.0 - k[0, 2]) * CG / 1.0
     assert abs((f_with[0, 1] - f_without[0, 1]) - expect) < 1e-13
     assert f_with[0, 0] == f_without[0, 0]      # presynaptic cell unaffected
+
+
+# --------------------------------------------------------------------------
+# Transmitter release T(V) = 1 / (1 + exp(-(V - V_p) / K_p)), pinned by the
+# logistic's special values rather than by its formula: T(V_p) = 1/2 exactly,
+# T(V_p + K_p ln 3) = 3/4 and T(V_p - K_p ln 3) = 1/4.  A presynaptic cell
+# clamped at such a V (passive, V0 = E_L, no input) releases at that constant
+# T, so its gate obeys the linear ODE s' = a T (1 - s) - b s and one RK4 step
+# maps s - s_inf by R(z), z = -(a T + b) dt.  A sign slip, swapped V_p and
+# K_p, or a misplaced K_p each move T away from these values.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("syn_type", [W.ACH, W.GABA_A])
+def test_release_sigmoid_special_values(syn_type):
+    for v, T, dT in release_points(syn_type):
+        inst, k = clamped_release_network(v, syn_type)
+        a, b = k[0], k[1]
+        dt = 1.5 / (a * T + b)          # z = -1.5 at the exact T
+        on = oracle.OracleNet(inst.net)
+        y = oracle.init_state(on, inst.v0)
+        traj = []
+        for _ in range(6):
+            oracle.integrate(on, y, inst.stim, dt, 1)
+            traj.append(y[4, 0])
+        assert y[0, 0] == float(np.float32(v))      # the clamp holds
+        expect = gate_closed_form(a, b, T, dt, 6)
+        # the gate's sensitivity to T is below 2 here (s_inf' = a b / (a T +
+        # b)^2 < 0.04, and R(z)^n moves by at most n |R'(z)| a dt dT); the
+        # rounding of the clamp voltage is the only source of dT
+        np.testing.assert_allclose(traj, expect, rtol=0, atol=1e-13 + 4.0 * dT)
+        assert dT < 2e-7
+
+
+def test_release_sigmoid_slow_gaba_at_half():
+    # Slow GABA: the LN clamped at its own V_p releases at T_B = 1/2 exactly.
+    inst, k = clamped_release_network(RELEASE_VK[W.GABA_B][0], W.GABA_B)
+    on = oracle.OracleNet(inst.net)
+    y = oracle.init_state(on, inst.v0)
+    expect = slow_gaba_half_closed_form(k, 2.0, 4)
+    for s in range(4):
+        oracle.integrate(on, y, inst.stim, 2.0, 1)
+        np.testing.assert_allclose(y[5:7, 0], expect[s], rtol=1e-13, atol=1e-15)
 
 
 def test_slow_gaba_linear_kinetics_and_current():
