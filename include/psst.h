@@ -316,6 +316,29 @@ psst_status psst_adjoint(psst_batch *batch, const float *checkpoints, int32_t K,
                          float *grad_gK, float *grad_gL, int32_t per_instance,
                          void *hip_stream);
 
+/* psst_adjoint for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results (bit for bit), but the stage
+ * records, gradient accumulators and per-instance gradient offsets live in a
+ * 64 MiB device array of the library (one per device, reserved when the
+ * library's code loads on that device and held until the process ends)
+ * instead of the batch's workspace.  The call allocates nothing, copies
+ * nothing from the host and does not synchronize; it enqueues its kernels on
+ * the stream.  It needs 8 * 60 * ld * K bytes of stage records per instance
+ * (ld = the largest network's neuron count rounded up to 4), the largest
+ * over the batch's networks of 8 * (n + n_LN + 3) * ld bytes of accumulators
+ * per instance, and 8 bytes per instance, each part rounded up to 256 bytes: a request above 64 MiB is refused with
+ * PSST_ERR_INVALID_ARGUMENT before any device call (use a smaller K, fewer
+ * instances, or psst_adjoint).  Every call on a device shares that device's
+ * array and leaves its contents behind: calls that overlap on one device
+ * (different streams, or host threads) race and must be ordered by the
+ * caller.  Errors: INVALID_ARGUMENT, UNSUPPORTED, DEVICE. */
+psst_status psst_adjoint_noalloc(psst_batch *batch, const float *checkpoints, int32_t K,
+                                 const psst_stimulus *stim, float dt_ms, int64_t n_steps,
+                                 int64_t step0, const float *dL_dV, float *grad_g,
+                                 float *grad_gNa, float *grad_gK, float *grad_gL,
+                                 int32_t per_instance, void *hip_stream);
+
 /* Number of float32 gradient entries one copy of the network's pathway blocks
  * occupies in grad_g. */
 psst_status psst_network_grad_size(const psst_network *net, int64_t *n_entries);

@@ -26,6 +26,7 @@
 // (general tableau) runs the same scheme with its own a and b.
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "runtime.h"
 #include "wg_common.h"
@@ -47,7 +48,6 @@ struct AdjArgs {
     int64_t ws_stride;
     float *gacc;                // per-instance compensated pairs, gacc_stride floats each
     int64_t gacc_stride;
-    int32_t ld_max;
     int64_t lds_bytes;
     int32_t *flag;
     Tab tab;                    // method of the generic-step variants
@@ -747,14 +747,55 @@ static const void *adj_fn(int bs, bool gen)
     return nullptr;
 }
 
-psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
-                        int64_t nt, const std::vector<int64_t> &offsets, AdjWork **work,
-                        const float *ckpt, int32_t K, const psst_stimulus *stim, float dt,
-                        int64_t n_steps, int64_t step0, const float *dLdV, float *grad_g,
-                        float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
-                        size_t lds_max, bool gen, const Tab &tab, void *stream)
+// Exclusive prefix sum of the instances' gradient-block sizes: goff[b] =
+// offset of instance b's blocks in a per-instance grad_g (one workgroup).
+__global__ __launch_bounds__(256) void grad_offsets_kernel(const InstDesc *desc, int32_t n,
+                                                           int64_t *goff)
 {
-    const int32_t n = (int32_t)nets.size();
+    __shared__ int64_t part[256];
+    const int t = threadIdx.x;
+    const int per = (n + 255) / 256;
+    const int b0 = min(n, t * per), b1 = min(n, b0 + per);
+    int64_t s = 0;
+    for (int b = b0; b < b1; ++b) s += desc[b].grad_entries;
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t run = 0;
+        for (int k = 0; k < 256; ++k) {
+            const int64_t v = part[k];
+            part[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int64_t run = part[t];
+    for (int b = b0; b < b1; ++b) {
+        goff[b] = run;
+        run += desc[b].grad_entries;
+    }
+}
+
+// Zero fill (the accumulators of a call with no steps).
+__global__ __launch_bounds__(256) void fill_zero_kernel(float *p, int64_t count)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0.f;
+}
+
+// Launch shape, LDS and workspace strides of one adjoint call.
+struct AdjPlan {
+    int bs = 0;
+    size_t lds = 0;
+    int64_t wstride = 0;     // doubles of stage records per instance
+    int64_t gstride = 0;     // floats of gradient accumulators per instance
+    const void *fn = nullptr;
+};
+
+static psst_status adjoint_plan(const std::vector<psst_network *> &nets, int32_t K,
+                                size_t lds_max, bool gen, AdjPlan *p)
+{
     int max_n = 0, max_ld = 0;
     int64_t gstride = 0;
     for (auto *q : nets) {
@@ -772,13 +813,6 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
         if (adj_fn(v, gen) && v >= max_n) bs = v;
     }
     if (4 * bs < max_ld) return fail(PSST_ERR_UNSUPPORTED, "no adjoint launch shape for n=%d", max_n);
-    if (!*work) *work = new AdjWork();
-    AdjWork *W = *work;
-    const int64_t wstride = ws_doubles(max_ld, K);
-    psst_status s = ensure((void **)&W->ws, &W->ws_bytes, sizeof(double) * wstride * n);
-    if (s != PSST_OK) return s;
-    if ((s = ensure((void **)&W->gacc, &W->gacc_bytes, sizeof(float) * gstride * n)) != PSST_OK)
-        return s;
     // LDS: q and product vectors, the forward view, and G when it fits
     size_t need = 0;
     for (auto *q : nets) {
@@ -786,9 +820,27 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
         need = std::max(need, base);
     }
     if (need > lds_max) return fail(PSST_ERR_UNSUPPORTED, "adjoint LDS buffers exceed the LDS");
-    const size_t lds = lds_max;     // the rest holds conductance columns
-    const void *fn = adj_fn(bs, gen);
-    if (lds > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    p->bs = bs;
+    p->lds = lds_max;     // the rest holds conductance columns
+    p->wstride = ws_doubles(max_ld, K);
+    p->gstride = gstride;
+    p->fn = adj_fn(bs, gen);
+    return PSST_OK;
+}
+
+// The adjoint kernel (or, without steps, zeroed accumulators) and the
+// finalize kernel, all on stream, with the given workspace, accumulators and
+// per-instance gradient offsets (device).
+static psst_status adjoint_launch(const AdjPlan &P, int32_t n, const InstDesc *d_desc, int64_t nt,
+                                  double *ws, float *gacc, const int64_t *goff,
+                                  const float *ckpt, int32_t K, const psst_stimulus *stim,
+                                  float dt, int64_t n_steps, int64_t step0, const float *dLdV,
+                                  float *grad_g, float *gna, float *gk, float *gl,
+                                  int32_t per_instance, int32_t *flag, const Tab &tab,
+                                  hipStream_t st)
+{
+    if (P.lds > 65536)
+        HIPCHK(hipFuncSetAttribute(P.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds));
     AdjArgs a{};
     a.desc = d_desc;
     a.ckpt = ckpt;
@@ -805,34 +857,32 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
     a.n_steps = n_steps;
     a.step0 = step0;
     a.dLdV = dLdV;
-    a.ws = W->ws;
-    a.ws_stride = wstride;
-    a.gacc = W->gacc;
-    a.gacc_stride = gstride;
-    a.ld_max = max_ld;
-    a.lds_bytes = (int64_t)lds;
+    a.ws = ws;
+    a.ws_stride = P.wstride;
+    a.gacc = gacc;
+    a.gacc_stride = P.gstride;
+    a.lds_bytes = (int64_t)P.lds;
     a.flag = flag;
     a.tab = tab;
     // PSST_ADJ_MODE=lacc keeps dL/dg in the per-step LDS accumulator even when
     // the matrix-core contraction is possible (comparison runs)
     if (const char *e = std::getenv("PSST_ADJ_MODE"))
         a.mode = std::strcmp(e, "lacc") == 0 ? 1 : (std::strcmp(e, "mma") == 0 ? 2 : 0);
-    hipStream_t st = (hipStream_t)stream;
-    void *args[] = {&a};
-    if (n_steps > 0) HIPCHK(hipLaunchKernel(fn, dim3(n), dim3(bs), args, lds, st));
-    else HIPCHK(hipMemsetAsync(W->gacc, 0, sizeof(float) * gstride * n, st));
-    // grad_g offsets per instance (per-instance mode)
-    std::vector<int64_t> goff(n, 0);
-    for (int32_t k = 1; k < n; ++k) goff[k] = goff[k - 1] + nets[k - 1]->grad_entries;
-    if (!W->goff) HIPCHK(hipMalloc(&W->goff, sizeof(int64_t) * n));
-    HIPCHK(hipMemcpyAsync(W->goff, goff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));     // goff host copy goes out of scope
+    if (n_steps > 0) {
+        void *args[] = {&a};
+        HIPCHK(hipLaunchKernel(P.fn, dim3(n), dim3(P.bs), args, P.lds, st));
+    } else {
+        const int64_t cnt = P.gstride * n;
+        const unsigned blocks = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
+        fill_zero_kernel<<<dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st>>>(gacc, cnt);
+        HIPCHK(hipGetLastError());
+    }
     FinArgs f{};
     f.desc = d_desc;
     f.n_inst = n;
-    f.gacc = W->gacc;
-    f.gacc_stride = gstride;
-    f.goff = W->goff;
+    f.gacc = gacc;
+    f.gacc_stride = P.gstride;
+    f.goff = goff;
     f.grad_g = grad_g;
     f.gna = gna;
     f.gk = gk;
@@ -841,8 +891,104 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
     void *fargs[] = {&f};
     HIPCHK(hipLaunchKernel((const void *)adjoint_finalize, dim3(per_instance ? n : 1), dim3(256),
                            fargs, 0, st));
-    (void)offsets;
     return PSST_OK;
+}
+
+psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
+                        int64_t nt, const std::vector<int64_t> &offsets, AdjWork **work,
+                        const float *ckpt, int32_t K, const psst_stimulus *stim, float dt,
+                        int64_t n_steps, int64_t step0, const float *dLdV, float *grad_g,
+                        float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
+                        size_t lds_max, bool gen, const Tab &tab, void *stream)
+{
+    const int32_t n = (int32_t)nets.size();
+    AdjPlan P;
+    psst_status s = adjoint_plan(nets, K, lds_max, gen, &P);
+    if (s != PSST_OK) return s;
+    if (!*work) *work = new AdjWork();
+    AdjWork *W = *work;
+    if ((s = ensure((void **)&W->ws, &W->ws_bytes, sizeof(double) * P.wstride * n)) != PSST_OK)
+        return s;
+    if ((s = ensure((void **)&W->gacc, &W->gacc_bytes, sizeof(float) * P.gstride * n)) != PSST_OK)
+        return s;
+    if (!W->goff) HIPCHK(hipMalloc(&W->goff, sizeof(int64_t) * n));
+    hipStream_t st = (hipStream_t)stream;
+    grad_offsets_kernel<<<dim3(1), dim3(256), 0, st>>>(d_desc, n, W->goff);
+    HIPCHK(hipGetLastError());
+    (void)offsets;
+    return adjoint_launch(P, n, d_desc, nt, W->ws, W->gacc, W->goff, ckpt, K, stim, dt, n_steps,
+                          step0, dLdV, grad_g, gna, gk, gl, per_instance, flag, tab, st);
+}
+
+// ---------------------------------------------------------------------------
+// The adjoint without allocation (psst_adjoint_noalloc): the stage records,
+// gradient accumulators and gradient offsets live in one file-scope device
+// array of kAdjScratchBytes, one copy per device, shared by every call on
+// that device (the last call's contents stay; calls that overlap on one
+// device race).  Its device address is looked up once per device with the
+// device current and kept; kernels are handed that address, never the
+// array's host-side name.
+// ---------------------------------------------------------------------------
+
+static constexpr int64_t kAdjScratchBytes = 64LL << 20;
+static __device__ __align__(256) unsigned char scratch[kAdjScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+static psst_status scratch_on_device(void **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(PSST_ERR_UNSUPPORTED, "device %d beyond the %d devices of the scratch table",
+                    dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(PSST_ERR_DEVICE, "no device address for the adjoint scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PSST_OK;
+}
+
+static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+psst_status adjoint_run_noalloc(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
+                                int64_t nt, const float *ckpt, int32_t K,
+                                const psst_stimulus *stim, float dt, int64_t n_steps,
+                                int64_t step0, const float *dLdV, float *grad_g, float *gna,
+                                float *gk, float *gl, int32_t per_instance, int32_t *flag,
+                                size_t lds_max, bool gen, const Tab &tab, void *stream)
+{
+    const int32_t n = (int32_t)nets.size();
+    AdjPlan P;
+    psst_status s = adjoint_plan(nets, K, lds_max, gen, &P);
+    if (s != PSST_OK) return s;
+    const int64_t ws_b = align256((int64_t)sizeof(double) * P.wstride * n);
+    const int64_t ga_b = align256((int64_t)sizeof(float) * P.gstride * n);
+    const int64_t go_b = align256((int64_t)sizeof(int64_t) * n);
+    if (ws_b + ga_b + go_b > kAdjScratchBytes)
+        return fail(PSST_ERR_INVALID_ARGUMENT,
+                    "psst_adjoint_noalloc needs %lld bytes of scratch (stage records %lld, "
+                    "accumulators %lld, offsets %lld) for %d instances at K=%d; its maximum is "
+                    "%lld: use a smaller K or fewer instances, or psst_adjoint",
+                    (long long)(ws_b + ga_b + go_b), (long long)ws_b, (long long)ga_b,
+                    (long long)go_b, n, K, (long long)kAdjScratchBytes);
+    void *base = nullptr;
+    if ((s = scratch_on_device(&base)) != PSST_OK) return s;
+    unsigned char *b8 = static_cast<unsigned char *>(base);
+    double *ws = reinterpret_cast<double *>(b8);
+    float *gacc = reinterpret_cast<float *>(b8 + ws_b);
+    int64_t *goff = reinterpret_cast<int64_t *>(b8 + ws_b + ga_b);
+    hipStream_t st = (hipStream_t)stream;
+    grad_offsets_kernel<<<dim3(1), dim3(256), 0, st>>>(d_desc, n, goff);
+    HIPCHK(hipGetLastError());
+    return adjoint_launch(P, n, d_desc, nt, ws, gacc, goff, ckpt, K, stim, dt, n_steps, step0,
+                          dLdV, grad_g, gna, gk, gl, per_instance, flag, tab, st);
 }
 
 void adjoint_free(AdjWork *w)

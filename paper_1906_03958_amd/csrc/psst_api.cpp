@@ -1093,6 +1093,28 @@ extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
                        max_lds_per_block(), b->gen, b->tab, stream);
 }
 
+extern "C" psst_status psst_adjoint_noalloc(psst_batch *b, const float *ckpt, int32_t K,
+                                            const psst_stimulus *stim, float dt,
+                                            int64_t n_steps, int64_t step0, const float *dLdV,
+                                            float *grad_g, float *grad_gNa, float *grad_gK,
+                                            float *grad_gL, int32_t per_instance, void *stream)
+{
+    if (!b) return fail(PSST_ERR_INVALID_ARGUMENT, "batch is NULL");
+    if (!ckpt || !dLdV || !grad_g || !grad_gNa || !grad_gK || !grad_gL)
+        return fail(PSST_ERR_INVALID_ARGUMENT, "NULL buffer");
+    if (K <= 0) return fail(PSST_ERR_INVALID_ARGUMENT, "K must be > 0");
+    psst_status s = validate_common(dt, n_steps, step0, nullptr);
+    if (s != PSST_OK) return s;
+    if ((s = validate_stim(stim)) != PSST_OK) return s;
+    if (!per_instance && !b->shared)
+        return fail(PSST_ERR_INVALID_ARGUMENT, "summed gradients need every instance to share one network");
+    if (b->stage_path)
+        return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available on the per-stage path");
+    return adjoint_run_noalloc(b->nets, b->d_desc, b->nt, ckpt, K, stim, dt, n_steps, step0, dLdV,
+                               grad_g, grad_gNa, grad_gK, grad_gL, per_instance, b->d_flag,
+                               max_lds_per_block(), b->gen, b->tab, stream);
+}
+
 // ---------------------------------------------------------------------------
 // explicit Runge-Kutta tableaux
 // ---------------------------------------------------------------------------

@@ -117,3 +117,11 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
                         float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
                         size_t lds_max, bool gen, const psst::Tab &tab, void *stream);
 void adjoint_free(AdjWork *w);
+// The same with the workspace in the library's per-device scratch array
+// (no allocation); sizes beyond its capacity are refused.
+psst_status adjoint_run_noalloc(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
+                                int64_t nt, const float *ckpt, int32_t K,
+                                const psst_stimulus *stim, float dt, int64_t n_steps,
+                                int64_t step0, const float *dLdV, float *grad_g, float *gna,
+                                float *gk, float *gl, int32_t per_instance, int32_t *flag,
+                                size_t lds_max, bool gen, const psst::Tab &tab, void *stream);

@@ -34,7 +34,7 @@ EXPORTS = (
     "psst_batch_state_init", "psst_integrate_batch", "psst_batch_poll",
     "psst_batch_describe", "psst_adjoint", "psst_network_grad_size",
     "psst_network_set_tableau", "psst_batch_set_tableau", "psst_network_create_storage",
-    "psst_integrate_batch_streamed", "psst_batch_conductance_bytes",
+    "psst_integrate_batch_streamed", "psst_batch_conductance_bytes", "psst_adjoint_noalloc",
 )
 STORAGE_AUTO, STORAGE_DENSE, STORAGE_SPARSE = 0, 1, 2
 
@@ -135,6 +135,8 @@ def lib():
                                                   i32, C.POINTER(Kinetics), i32, C.POINTER(vp)]),
             "psst_batch_set_tableau": (i32, [vp, C.POINTER(Tableau)]),
             "psst_batch_conductance_bytes": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
+            "psst_adjoint_noalloc": (i32, [vp, vp, i32, C.POINTER(Stimulus), f32, i64, i64, vp,
+                                           vp, vp, vp, vp, i32, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -425,6 +427,19 @@ def adjoint(batch: Batch, checkpoints, K: int, stim: Optional[DeviceStimulus], d
                               int(step0), _ptr(dL_dV), _ptr(grad_g), _ptr(grad_gNa),
                               _ptr(grad_gK), _ptr(grad_gL), int(bool(per_instance)),
                               _stream(stream)))
+
+
+def adjoint_noalloc(batch: Batch, checkpoints, K: int, stim: Optional[DeviceStimulus],
+                    dt_ms: float, n_steps: int, step0: int, dL_dV, grad_g, grad_gNa, grad_gK,
+                    grad_gL, per_instance: bool, stream=None):
+    """psst_adjoint_noalloc: psst_adjoint with the library's fixed scratch array
+    instead of an allocated workspace."""
+    s = None if stim is None else stim.c()
+    _check(lib().psst_adjoint_noalloc(batch.handle, _ptr(checkpoints), int(K),
+                                      None if s is None else C.byref(s), float(dt_ms),
+                                      int(n_steps), int(step0), _ptr(dL_dV), _ptr(grad_g),
+                                      _ptr(grad_gNa), _ptr(grad_gK), _ptr(grad_gL),
+                                      int(bool(per_instance)), _stream(stream)))
 
 
 # ---------------------------------------------------------------------------
