@@ -33,7 +33,10 @@
  *   - Environment variables, for comparisons and tests (defaults are the
  *     library's own choices): PSST_TUNE=0 and PSST_WG_SHAPE (batch and
  *     psst_integrate launch shapes, see there), PSST_LDS_G=0 (conductances
- *     never held in LDS: always streamed), PSST_ADJ_MODE=lacc|mma (how the
+ *     never held in LDS: always streamed), PSST_LG=0 (small dense networks
+ *     -- at most 128 neurons and 4 column chunks of 64 -- take the
+ *     LDS-resident kernels instead of the one holding their conductances in
+ *     registers; both give the same bits), PSST_ADJ_MODE=lacc|mma (how the
  *     adjoint accumulates dL/dg), PSST_ADJ_BS=64|128|256|512 (adjoint
  *     workgroup size, when it covers the batch's largest network).
  *   - A handle holds per-handle device state (control blocks, graphs,
@@ -279,8 +282,9 @@ psst_status psst_batch_describe(const psst_batch *batch, char *buf, int32_t buf_
  * memory constraints", item 1: the synaptic update is a product with the
  * conductance matrices, so these bytes are its operand traffic):
  * resident_bytes are read once per launch (the leading columns of every
- * conductance chunk kept in LDS for the whole launch, or an instance's whole
- * sparse rows), streamed_bytes once per stage evaluation (the rest; on the
+ * conductance chunk kept in LDS for the whole launch, an instance's whole
+ * sparse rows, or a small network's whole matrices held in registers),
+ * streamed_bytes once per stage evaluation (the rest; on the
  * per-stage path of a large shared network, its whole padded matrix).  Trials
  * that share one network count once per workgroup that reads it.  Either
  * pointer may be NULL.  Synchronous, no device call. */

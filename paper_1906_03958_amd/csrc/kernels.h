@@ -52,11 +52,13 @@ struct WGArgs {
 
 typedef void (*wg_kernel_t)(WGArgs);
 
-// Kernel variant: threads per workgroup, neurons per thread, and whether it
-// runs the generic tableau step (else classical RK4).
+// Kernel variant: threads per workgroup, neurons per thread, whether it
+// runs the generic tableau step (else classical RK4), and whether it is the
+// lane-group kernel (every instance of its launches must be eligible).
 struct WGVariant {
     int bs, npt;
     bool gen;
+    bool lg;
     const void *fn;
 };
 
@@ -82,7 +84,7 @@ __host__ __device__ inline int resident_columns(int64_t lds_bytes, int ld, int n
 }
 
 // Column chunks of an instance: cholinergic, fast-GABA and slow-GABA columns.
-inline int n_chunks(int n, int n_pn, bool gabab)
+__host__ __device__ inline int n_chunks(int n, int n_pn, bool gabab)
 {
     const int na = (n_pn + kChunkWidth - 1) / kChunkWidth;
     const int ng = (n - n_pn + kChunkWidth - 1) / kChunkWidth;
@@ -96,6 +98,24 @@ inline size_t wg_lds_bytes(bool glds, int ld, int n_chunks, int64_t g_floats)
 {
     return sizeof(double) * (2 + (size_t)n_chunks) * (size_t)ld +
            sizeof(float) * (glds ? (size_t)g_floats : 0);
+}
+
+// Lane-group kernel (256 threads): networks of at most kLGRows neurons with
+// dense storage and at most 4 column chunks keep every conductance in
+// registers, two (chunk, row) pairs of 64 columns per lane; the LDS holds
+// only the activations, in one slot of kLGSlot doubles per chunk (64 used;
+// the 2 extra stagger the slots' LDS banks), two sets alternating by stage.
+constexpr int kLGRows = 128;
+constexpr int kLGSlot = 66;
+constexpr int kLGThreads = 256;
+constexpr int64_t kLGLdsBytes = (int64_t)sizeof(double) * 2 * 4 * kLGSlot;
+
+// Whether an instance can take the lane-group kernel (flags as in InstDesc).
+__host__ __device__ inline bool lg_eligible(int n, int n_pn, int flags)
+{
+    if (flags & (DESC_NOSYN | DESC_SPARSE)) return false;
+    if (n > kLGRows) return false;
+    return n_chunks(n, n_pn, (flags & DESC_GABAB) != 0) <= 4;
 }
 
 struct InitArgs {

@@ -440,11 +440,25 @@ extern "C" psst_status psst_state_init(const psst_network *net, const float *v0,
 // the per-instance persistent kernel: variant choice and launch
 // ---------------------------------------------------------------------------
 
-static const WGVariant *find_variant(int bs, int npt, bool gen)
+static const WGVariant *find_variant(int bs, int npt, bool gen, bool lg = false)
 {
     for (const WGVariant *v = wg_variants(); v->fn; ++v)
-        if (v->bs == bs && v->npt == npt && v->gen == gen) return v;
+        if (v->bs == bs && v->npt == npt && v->gen == gen && v->lg == lg) return v;
     return nullptr;
+}
+
+// The lane-group kernel (conductances in registers) takes the instances it
+// can unless the environment variable PSST_LG=0 turns it off (comparisons:
+// both mappings give the same bits).
+static bool lg_enabled()
+{
+    const char *e = std::getenv("PSST_LG");
+    return !(e && e[0] == '0');
+}
+
+static bool net_lg(const psst_network *q)
+{
+    return lg_enabled() && lg_eligible(q->n, q->n_pn, q->desc.flags);
 }
 
 static size_t max_lds_per_block()
@@ -547,11 +561,17 @@ extern "C" psst_status psst_integrate(psst_network *net, float *state, const pss
     if (n_steps == 0) return PSST_OK;
     int bs, npt;
     default_shape(net->n, &bs, &npt);
+    // small dense networks: the lane-group kernel (unless a shape is forced)
+    const bool lg = net_lg(net) && !std::getenv("PSST_WG_SHAPE");
+    if (lg) {
+        bs = kLGThreads;
+        npt = 1;
+    }
     // a network whose whole conductance matrix stays in LDS sums one (chunk,
     // row) pair per thread: enough threads for every pair in one pass (up to
     // 512) shorten the stage (measured: 120 neurons, 512 threads 12.0 us per
     // step against 14.0 with 256; 60 neurons, 128 threads 8.9 against 10.1)
-    if (!net->sparse && net->nch > 0 && net->n <= 512 &&
+    if (!lg && !net->sparse && net->nch > 0 && net->n <= 512 &&
         sizeof(double) * (2 + (size_t)net->nch) * net->ld +
                 sizeof(float) * (size_t)net->nch * kChunkWidth * net->ld <= max_lds_per_block()) {
         const int pairs = net->nch * net->n;
@@ -573,11 +593,13 @@ extern "C" psst_status psst_integrate(psst_network *net, float *state, const pss
         }
     }
     // the whole LDS: whatever the activation and partial buffers leave holds
-    // the leading columns of every conductance chunk (all of G when it fits)
+    // the leading columns of every conductance chunk (all of G when it fits);
+    // the lane-group kernel needs only its activation slots
     const char *env = std::getenv("PSST_LDS_G");
-    const size_t lds = (env && env[0] == '0') ? wg_lds_bytes(false, net->ld, net->nch, 0)
-                                              : max_lds_per_block();
-    const WGVariant *v = find_variant(bs, npt, net->gen);
+    const size_t lds = lg ? (size_t)kLGLdsBytes
+                          : (env && env[0] == '0') ? wg_lds_bytes(false, net->ld, net->nch, 0)
+                                                   : max_lds_per_block();
+    const WGVariant *v = find_variant(bs, npt, net->gen, lg);
     if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant for n=%d", net->n);
     if ((s = set_lds_attr(v->fn, lds)) != PSST_OK) return s;
     WGArgs a{};
@@ -661,7 +683,7 @@ static WGArgs group_args(psst_batch *b, const Group &g, float *states, const pss
 
 static psst_status launch_group(const Group &g, bool gen, WGArgs &a, hipStream_t s)
 {
-    const WGVariant *v = find_variant(g.bs, g.npt, gen);
+    const WGVariant *v = find_variant(g.bs, g.npt, gen, g.lg);
     if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant bs=%d npt=%d", g.bs, g.npt);
     psst_status st = set_lds_attr(v->fn, g.lds);
     if (st != PSST_OK) return st;
@@ -684,6 +706,7 @@ struct EventPair {
 // stimulus, no recording) and keep the fastest.
 static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream_t s)
 {
+    if (g.lg) return PSST_OK;          // one shape
     std::vector<std::pair<int, int>> cands;
     for (const WGVariant *v = wg_variants(); v->fn; ++v) {
         if (v->gen != b->gen) continue;
@@ -794,10 +817,13 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
         return PSST_OK;
     }
 
-    // One launch, workgroups in largest-first (LPT) order of cost ~ n^2; the
-    // LDS request is the full per-workgroup LDS: each instance keeps the
-    // leading columns of every conductance chunk there (all of G when it
-    // fits) and streams the rest from L2/MALL/HBM.
+    // Launch groups, workgroups in largest-first (LPT) order of cost ~ n^2:
+    // small dense networks the lane-group kernel takes (conductances in
+    // registers) form one group, the rest another whose LDS request is the
+    // full per-workgroup LDS: each instance keeps the leading columns of every
+    // conductance chunk there (all of G when it fits) and streams the rest
+    // from L2/MALL/HBM.  Each group is one launch (a node of the batch's
+    // graph).
     std::vector<int32_t> idx(n);
     for (int32_t k = 0; k < n; ++k) idx[k] = k;
     std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
@@ -806,25 +832,33 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     const size_t lmax = max_lds_per_block();
     const char *env = std::getenv("PSST_LDS_G");
     const bool allow_lds = !(env && env[0] == '0');
-    Group g;
+    const char *shp = std::getenv("PSST_WG_SHAPE");
+    Group g, gl;
+    gl.lg = true;
     size_t need = 0;
+    bool any_syn = false;
     for (int32_t k : idx) {
         const psst_network *q = nets[k];
-        g.order.push_back(k);
-        g.max_n = std::max(g.max_n, q->n);
-        g.max_ld = std::max(g.max_ld, q->ld);
-        need = std::max(need, wg_lds_bytes(false, q->ld, q->nch, 0));
+        Group &t = (!shp && net_lg(q)) ? gl : g;
+        t.order.push_back(k);
+        t.max_n = std::max(t.max_n, q->n);
+        t.max_ld = std::max(t.max_ld, q->ld);
+        if (&t == &g) {
+            need = std::max(need, wg_lds_bytes(false, q->ld, q->nch, 0));
+            // networks without synapses need no LDS beyond the small buffers,
+            // so several workgroups share a CU
+            any_syn |= q->desc.n_paths > 0;
+        }
     }
-    // networks without synapses need no LDS beyond the small buffers, so
-    // several workgroups share a CU
-    bool any_syn = false;
-    for (int32_t k : idx) any_syn |= nets[k]->desc.n_paths > 0;
     g.lds = (allow_lds && any_syn) ? lmax : need;
     default_shape(g.max_n, &g.bs, &g.npt);
+    gl.bs = kLGThreads;
+    gl.npt = 1;
+    gl.lds = (size_t)kLGLdsBytes;
     // PSST_WG_SHAPE="<threads>x<neurons per thread>" fixes the launch shape
     // (and skips tuning) when that variant can take every instance.
-    bool fixed = false;
-    if (const char *shp = std::getenv("PSST_WG_SHAPE")) {
+    bool fixed = g.order.empty();
+    if (shp) {
         int bs = 0, npt = 0;
         if (std::sscanf(shp, "%dx%d", &bs, &npt) == 2 && find_variant(bs, npt, b->gen) &&
             bs * npt >= g.max_n && 4 * bs >= g.max_ld) {
@@ -833,9 +867,15 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
             fixed = true;
         }
     }
-    BCHK(hipMalloc(&g.d_order, sizeof(int32_t) * g.order.size()));
-    BCHK(hipMemcpy(g.d_order, g.order.data(), sizeof(int32_t) * g.order.size(), hipMemcpyHostToDevice));
-    b->groups.push_back(g);
+    for (Group *t : {&g, &gl}) {
+        if (t->order.empty()) continue;
+        BCHK(hipMalloc(&t->d_order, sizeof(int32_t) * t->order.size()));
+        BCHK(hipMemcpy(t->d_order, t->order.data(), sizeof(int32_t) * t->order.size(),
+                       hipMemcpyHostToDevice));
+        b->groups.push_back(*t);
+        t->d_order = nullptr;           // owned by the batch's copy now
+    }
+    Group &gt = b->groups[0];           // the tuned group (the classic kernels) when present
     // launch-shape tuning on a scratch state, once per batch shape in the
     // process: batches alike in count, sizes, matrix volume, storage and
     // method (an autograd loop makes one per forward call) reuse the result
@@ -846,15 +886,15 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
         gsum += q->g_floats;
         nsparse += q->sparse ? 1 : 0;
     }
-    const auto tkey = std::make_tuple(n, b->nt, g.max_n, gsum, nsparse, b->gen, b->groups[0].lds);
+    const auto tkey = std::make_tuple(n, b->nt, g.max_n, gsum, nsparse, b->gen, gt.lds);
     static std::mutex tune_mu;
     static std::map<decltype(tkey), std::pair<int, int>> tune_cache;
     if (!fixed && !(tenv && tenv[0] == '0')) {
         std::lock_guard<std::mutex> lock(tune_mu);
         auto it = tune_cache.find(tkey);
         if (it != tune_cache.end()) {
-            b->groups[0].bs = it->second.first;
-            b->groups[0].npt = it->second.second;
+            gt.bs = it->second.first;
+            gt.npt = it->second.second;
             fixed = true;
         }
     }
@@ -873,8 +913,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
         if (e == hipSuccess) e = hipStreamCreate(&st);
         if (e == hipSuccess) {
             s = launch_init(b->d_desc, n, v0, scratch, b->nt, st);
-            for (auto &g : b->groups)
-                if (s == PSST_OK) s = tune_group(b, g, scratch, st);
+            if (s == PSST_OK) s = tune_group(b, gt, scratch, st);
             e = hipStreamSynchronize(st);
         }
         if (st) (void)hipStreamDestroy(st);
@@ -889,13 +928,13 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
         }
         BCHK(hipMemset(b->d_flag, 0, sizeof(int32_t)));
         std::lock_guard<std::mutex> lock(tune_mu);
-        tune_cache[tkey] = {b->groups[0].bs, b->groups[0].npt};
+        tune_cache[tkey] = {gt.bs, gt.npt};
     }
 #undef BCHK
     char buf[256];
     for (auto &g : b->groups) {
-        snprintf(buf, sizeof buf, "[%zu inst, n<=%d, %d thr x %d neurons, lds %zu B] ",
-                 g.order.size(), g.max_n, g.bs, g.npt, g.lds);
+        snprintf(buf, sizeof buf, "[%zu inst, n<=%d, %s%d thr x %d neurons, lds %zu B] ",
+                 g.order.size(), g.max_n, g.lg ? "lane-group, " : "", g.bs, g.npt, g.lds);
         b->describe += buf;
     }
     *out = b;
@@ -938,6 +977,12 @@ extern "C" psst_status psst_batch_conductance_bytes(const psst_batch *b, int64_t
             for (int32_t k : g.order) {
                 const psst_network *q = b->nets[k];
                 if (q->desc.flags & DESC_NOSYN) continue;
+                if (g.lg) {
+                    // the lane-group kernel holds every conductance in registers
+                    res += (int64_t)sizeof(float) * q->ld *
+                           (q->n + (q->gabab ? q->n - q->n_pn : 0));
+                    continue;
+                }
                 if (q->sparse) {
                     // ELL rows (column index and value, 8 bytes per entry) go to
                     // LDS for the launch when they fit beside the two
@@ -986,7 +1031,7 @@ static psst_status submit_graph(psst_batch *b, std::vector<WGArgs> &args, hipStr
         b->node_args = args;
         for (size_t k = 0; k < G; ++k) {
             const Group &g = b->groups[k];
-            const WGVariant *v = find_variant(g.bs, g.npt, b->gen);
+            const WGVariant *v = find_variant(g.bs, g.npt, b->gen, g.lg);
             if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant");
             psst_status st = set_lds_attr(v->fn, g.lds);
             if (st != PSST_OK) return st;
@@ -1006,7 +1051,7 @@ static psst_status submit_graph(psst_batch *b, std::vector<WGArgs> &args, hipStr
             if (std::memcmp(&b->node_args[k], &args[k], sizeof(WGArgs)) == 0) continue;
             b->node_args[k] = args[k];
             const Group &g = b->groups[k];
-            const WGVariant *v = find_variant(g.bs, g.npt, b->gen);
+            const WGVariant *v = find_variant(g.bs, g.npt, b->gen, g.lg);
             void *kp[] = {&b->node_args[k]};
             hipKernelNodeParams p{};
             p.func = const_cast<void *>(v->fn);

@@ -30,19 +30,18 @@
 
 namespace psst {
 
-template <int BS, int NPT, bool GEN>
-__global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
+// The integration loop of one instance for every step of the call: state
+// in registers, stimulus at each step's start (zero-order hold), spikes and
+// records after each step, checkpoints before each K-th step, state stored at
+// the end.  Slot k of the calling thread is neuron nid(k); own(k) says
+// whether this thread carries that neuron (loads, stores, records); step(Iu,
+// y) advances every slot by one step and is called by every thread.
+template <int NPT, typename Nid, typename Own, typename Step>
+__device__ __forceinline__ void integrate_loop(const WGArgs &a, const InstDesc &d, Nid &&nid,
+                                               Own &&own_of, Step &&step)
 {
-    extern __shared__ double lds_d[];
-    const int32_t b = a.order[blockIdx.x];
-    const InstDesc d = a.desc[b];
-    const WGSyn w = wg_setup<BS>(d, lds_d, a.lds_bytes);
-    const int tid = threadIdx.x;
     const int n = d.n, ld = d.ld;
-    const Kin K = load_kin(d.kin);
-    const double dt = a.dt;
     const int64_t NT = a.nt;
-
     bool own[NPT];
     double y[NPT][NVAR];
     float pr[NPT][NPRM];
@@ -51,9 +50,9 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
     int32_t nspk[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int i = tid + k * BS;
-        own[k] = i < n;
-        const int ic = own[k] ? i : 0;
+        const int i = nid(k);
+        own[k] = own_of(k);
+        const int ic = (own[k] && i < n) ? i : 0;
         const int64_t gi = d.off + ic;
 #pragma unroll
         for (int v = 0; v < NVAR; ++v)
@@ -80,7 +79,7 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 if (!own[k]) continue;
-                const int64_t gi = d.off + tid + k * BS;
+                const int64_t gi = d.off + nid(k);
 #pragma unroll
                 for (int v = 0; v < NVAR; ++v) {
                     float hi, lo;
@@ -98,16 +97,13 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
             Iu[k] = d.ci * stim_nA(a.stim, Ic[k], p0[k], p1[k], g);
             vold[k] = y[k][YV];
         }
-        if constexpr (GEN)
-            rk_step_wg_tab<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr, a.tab);
-        else
-            rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr);
+        step(pr, Iu, y);
         // spikes, records
         const bool do_rec = (g + 1 == next_rec);
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             if (!own[k]) continue;
-            const int64_t gi = d.off + tid + k * BS;
+            const int64_t gi = d.off + nid(k);
             double chk = 0.0;
 #pragma unroll
             for (int v = 0; v < NVAR; ++v) chk += y[k][v];
@@ -116,7 +112,7 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
             if (a.rec.spike_count && vold[k] < 0.0 && vnew >= 0.0) {
                 if (nspk[k] < a.rec.spike_cap)
                     a.rec.spike_t[gi * a.rec.spike_cap + nspk[k]] =
-                        (float)(((double)g + (0.0 - vold[k]) / (vnew - vold[k])) * dt);
+                        (float)(((double)g + (0.0 - vold[k]) / (vnew - vold[k])) * a.dt);
                 nspk[k]++;
             }
             if (do_rec && rec_row < a.rec.capacity)
@@ -130,7 +126,7 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         if (!own[k]) continue;
-        const int64_t gi = d.off + tid + k * BS;
+        const int64_t gi = d.off + nid(k);
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
             float hi, lo;
@@ -141,6 +137,150 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
         if (a.rec.spike_count) a.rec.spike_count[gi] = nspk[k];
     }
     if (bad) atomicOr(a.flag, 1);
+}
+
+// Lane-group mapping (small dense networks, kLGThreads = 256 threads, one
+// wavefront per SIMD so that a lane has room for its conductances): lane
+// 16 c + r of wavefront w takes the pairs (chunk c, row i_k = 64 k + 16 w +
+// r), k = 0, 1, and keeps their 64 conductances each in registers for the
+// whole launch (zeros past the chunk's last column); lane 16 k + r (k = 0, 1)
+// owns neuron i_k.  Per stage the owners write their activations into the
+// chunk slots of one of two LDS slot sets (alternating by stage, so a
+// wavefront that runs ahead writes the other set), one barrier, each lane
+// sums its pairs in column order -- the fma sequence of every other mapping,
+// the zero columns adding exact zeros -- and each owner gathers its row's
+// chunk partials from the four lanes r, 16 + r, 32 + r, 48 + r by shuffles
+// and adds them in chunk order, per synapse class.
+template <bool GEN>
+__device__ __forceinline__ void lg_integrate(const WGArgs &a, const InstDesc &d, double *lds)
+{
+    constexpr int RPL = kLGRows / (kLGThreads / 4);     // pairs (rows) per lane
+    static_assert(RPL == 2, "row blocks 0 and 1 are owned by lane groups 0 and 1");
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int cl = lane >> 4, r = lane & 15;
+    const int row0 = (tid >> 6) * 16 + r;
+    const int n = d.n, n_pn = d.n_pn, ld = d.ld;
+    const bool gabab = (d.flags & DESC_GABAB) != 0;
+    const Chunks ch = chunks_of(n, n_pn, gabab);
+    const int nch = ch.na + ch.ng + ch.nb;
+    const Kin K = load_kin(d.kin);
+    int mat = 0, j0 = 0, j1 = 0;
+    if (cl < nch) chunk_range(ch, n, n_pn, cl, mat, j0, j1);
+    const int wc = j1 - j0;               // columns of this lane's chunk (0: no chunk)
+    float g[RPL][CW];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        const int i = row0 + 64 * k;
+        const bool pair = wc > 0 && i < n;
+        // every address is inside the matrix (row j0 + min(u, wc - 1), or
+        // entry 0 for a lane without a pair); the value is kept only for the
+        // chunk's own columns
+        const float *M = (mat ? d.gtb : d.gt) + (pair ? i : 0);
+#pragma unroll
+        for (int u = 0; u < CW; ++u) {
+            const int64_t jj = pair ? (int64_t)(j0 + min(u, wc - 1)) * ld : 0;
+            const float v = M[jj];
+            g[k][u] = (pair && u < wc) ? v : 0.f;
+        }
+    }
+    const int me = row0 + 64 * (cl & 1);  // the neuron this lane owns when cl < 2
+    const bool owner = cl < 2 && me < n;
+    // both slot sets start at zero: columns past a chunk's end stay 0
+    for (int e = tid; e < 2 * 4 * kLGSlot; e += kLGThreads) lds[e] = 0.0;
+    __syncthreads();
+    int parity = 0;
+    auto syn = [&](const double (&Y)[1][NVAR], double (&sa)[1], double (&sg)[1],
+                   double (&sb)[1]) {
+        double *S = lds + parity * 4 * kLGSlot;
+        parity ^= 1;
+        if (owner) {
+            const bool ln = me >= n_pn;
+            const int c = ln ? ch.na + (me - n_pn) / CW : me / CW;
+            const int u = ln ? (me - n_pn) % CW : me % CW;
+            S[c * kLGSlot + u] = Y[0][YS];
+            if (gabab && ln)
+                S[(ch.na + ch.ng + (me - n_pn) / CW) * kLGSlot + u] = gabab_act(Y[0][YG], K);
+        }
+        __syncthreads();
+        double p[RPL];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) p[k] = 0.0;
+        if (wc > 0) {
+            lds_double *X = (lds_double *)(S + cl * kLGSlot);
+#pragma unroll
+            for (int u0 = 0; u0 < CW; u0 += 8) {
+                if (u0 < wc) {
+                    double xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) xv[u] = X[u0 + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+#pragma unroll
+                        for (int k = 0; k < RPL; ++k) p[k] = fma((double)g[k][u0 + u], xv[u], p[k]);
+                }
+            }
+        }
+        double pc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double a0 = __shfl(p[0], 16 * c + r), a1 = __shfl(p[1], 16 * c + r);
+            pc[c] = (cl & 1) ? a1 : a0;
+        }
+        double ta = 0.0, tg = 0.0, tb = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c < ch.na) ta += pc[c];
+            else if (c < ch.na + ch.ng) tg += pc[c];
+            else if (c < nch) tb += pc[c];
+        }
+        sa[0] = ta;
+        sg[0] = tg;
+        sb[0] = tb;
+    };
+    const Slots sl{n, n_pn, gabab};
+    auto nid = [&](int) { return me; };
+    auto own = [&](int) { return owner; };
+    const double dt = a.dt;
+    integrate_loop<1>(a, d, nid, own,
+                      [&](const float (&pr)[1][NPRM], const double (&Iu)[1], double (&y)[1][NVAR]) {
+                          if constexpr (GEN)
+                              rk_step_core_tab<1>(sl, syn, nid, own, K, d.cg, pr, Iu, dt, y,
+                                                  nullptr, a.tab);
+                          else
+                              rk4_step_core<1>(sl, syn, nid, own, K, d.cg, pr, Iu, dt, y, nullptr);
+                      });
+}
+
+template <int BS, int NPT, bool GEN>
+__global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
+{
+    extern __shared__ double lds_d[];
+    const int32_t b = a.order[blockIdx.x];
+    const InstDesc d = a.desc[b];
+    const WGSyn w = wg_setup<BS>(d, lds_d, a.lds_bytes);
+    const int tid = threadIdx.x;
+    const Kin K = load_kin(d.kin);
+    const double dt = a.dt;
+    integrate_loop<NPT>(
+        a, d, [&](int k) { return tid + k * BS; }, [&](int k) { return tid + k * BS < d.n; },
+        [&](const float (&pr)[NPT][NPRM], const double (&Iu)[NPT], double (&y)[NPT][NVAR]) {
+            if constexpr (GEN)
+                rk_step_wg_tab<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr, a.tab);
+            else
+                rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr);
+        });
+}
+
+// The lane-group mapping as a kernel of its own (its registers hold the
+// conductances; the other mappings' register budget stays unchanged): every
+// instance of the launch must be eligible.
+template <bool GEN>
+__global__ __launch_bounds__(kLGThreads) void rk4_lg_kernel(WGArgs a)
+{
+    extern __shared__ double lds_d[];
+    const int32_t b = a.order[blockIdx.x];
+    const InstDesc d = a.desc[b];
+    lg_integrate<GEN>(a, d, lds_d);
 }
 
 // Initial state: V = v0, gates at steady state, synaptic variables 0.
@@ -163,13 +303,15 @@ __global__ __launch_bounds__(256) void init_state_kernel(InitArgs a)
     }
 }
 
-#define WGV(BS, NPT) {BS, NPT, false, (const void *)rk4_wg_kernel<BS, NPT, false>}
-#define WGG(BS, NPT) {BS, NPT, true, (const void *)rk4_wg_kernel<BS, NPT, true>}
+#define WGV(BS, NPT) {BS, NPT, false, false, (const void *)rk4_wg_kernel<BS, NPT, false>}
+#define WGG(BS, NPT) {BS, NPT, true, false, (const void *)rk4_wg_kernel<BS, NPT, true>}
 
 static const WGVariant kVariants[] = {
     WGV(64, 1), WGV(128, 1), WGV(128, 2), WGV(256, 1), WGV(256, 2), WGV(256, 4), WGV(512, 1),
     WGG(64, 1), WGG(128, 1), WGG(128, 2), WGG(256, 1), WGG(256, 2), WGG(256, 4), WGG(512, 1),
-    {0, 0, false, nullptr},
+    {kLGThreads, 1, false, true, (const void *)rk4_lg_kernel<false>},
+    {kLGThreads, 1, true, true, (const void *)rk4_lg_kernel<true>},
+    {0, 0, false, false, nullptr},
 };
 
 const WGVariant *wg_variants() { return kVariants; }

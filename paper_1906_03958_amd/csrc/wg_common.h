@@ -365,15 +365,25 @@ struct StageStash {
     int ld;
 };
 
+// The calling thread's neuron slots for one step: slot k holds neuron
+// idx(k) of the instance (a neuron when below n); live(k) false skips the
+// slot's per-neuron work (uniform over the workgroup for the per-instance
+// mappings, per lane for the lane-group one).  syn(Y, sa, sg, sb) forms the
+// synaptic sums of every slot from the stage inputs; every thread calls it.
+struct Slots {
+    int n, n_pn;
+    bool gabab;
+};
+
 // One RK4 step of the calling thread's neurons, y updated in place and
 // rounded to its stored float32 pair.  Iu: injected current (uA/cm^2).
-template <int BS, int NPT>
-__device__ __forceinline__ void rk4_step_wg(const WGSyn &w, const Kin &K, double cgf,
-                                            const float (&pr)[NPT][NPRM], const double (&Iu)[NPT],
-                                            double dt, double (&y)[NPT][NVAR],
-                                            const StageStash *stash)
+template <int NPT, typename Syn, typename Idx, typename Live>
+__device__ __forceinline__ void rk4_step_core(const Slots &sl, Syn &&syn, Idx &&idx, Live &&live,
+                                              const Kin &K, double cgf,
+                                              const float (&pr)[NPT][NPRM],
+                                              const double (&Iu)[NPT], double dt,
+                                              double (&y)[NPT][NVAR], const StageStash *stash)
 {
-    const int tid = threadIdx.x;
     double acc[NPT][NVAR];
     double Y[NPT][NVAR];
 #pragma unroll
@@ -386,12 +396,12 @@ __device__ __forceinline__ void rk4_step_wg(const WGSyn &w, const Kin &K, double
 #pragma unroll 1
     for (int q = 0; q < 4; ++q) {
         double sa[NPT], sg[NPT], sb[NPT];
-        syn_sums<BS, NPT>(w, K, Y, sa, sg, sb);
+        syn(Y, sa, sg, sb);
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            if (k * BS >= w.n) continue;
-            const int i = tid + k * BS;
-            if (stash && i < w.n) {
+            if (!live(k)) continue;
+            const int i = idx(k);
+            if (stash && i < sl.n) {
 #pragma unroll
                 for (int v = 0; v < NVAR; ++v) stash->sY[(q * NVAR + v) * stash->ld + i] = Y[k][v];
                 stash->sS[(q * 3 + 0) * stash->ld + i] = sa[k];
@@ -400,7 +410,7 @@ __device__ __forceinline__ void rk4_step_wg(const WGSyn &w, const Kin &K, double
             }
             double f[NVAR];
             hh_rhs(Y[k], prm_of(pr[k]), K, cgf * sa[k], cgf * sg[k], cgf * sb[k], Iu[k],
-                   i >= w.n_pn, w.gabab, f);
+                   i >= sl.n_pn, sl.gabab, f);
             const double wq = (q == 0 || q == 3) ? 1.0 : 2.0;
             const double c = (q == 2) ? dt : 0.5 * dt;
 #pragma unroll
@@ -412,7 +422,7 @@ __device__ __forceinline__ void rk4_step_wg(const WGSyn &w, const Kin &K, double
     }
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        if (tid + k * BS >= w.n) continue;
+        if (idx(k) >= sl.n || !live(k)) continue;
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
             float hi, lo;
@@ -427,14 +437,14 @@ __device__ __forceinline__ void rk4_step_wg(const WGSyn &w, const Kin &K, double
 // stored float32 pair.  The stage loop is unrolled so the earlier k stay in
 // registers; T.s is the same for the whole workgroup, so the barriers inside
 // the synaptic sums are reached by every thread.
-template <int BS, int NPT>
-__device__ __forceinline__ void rk_step_wg_tab(const WGSyn &w, const Kin &K, double cgf,
-                                               const float (&pr)[NPT][NPRM],
-                                               const double (&Iu)[NPT], double dt,
-                                               double (&y)[NPT][NVAR], const StageStash *stash,
-                                               const Tab &T)
+template <int NPT, typename Syn, typename Idx, typename Live>
+__device__ __forceinline__ void rk_step_core_tab(const Slots &sl, Syn &&syn, Idx &&idx,
+                                                 Live &&live, const Kin &K, double cgf,
+                                                 const float (&pr)[NPT][NPRM],
+                                                 const double (&Iu)[NPT], double dt,
+                                                 double (&y)[NPT][NVAR], const StageStash *stash,
+                                                 const Tab &T)
 {
-    const int tid = threadIdx.x;
     double inc[NPT][NVAR];
     double kq[3][NPT][NVAR];
     double Y[NPT][NVAR];
@@ -460,12 +470,12 @@ __device__ __forceinline__ void rk_step_wg_tab(const WGSyn &w, const Kin &K, dou
                 }
         }
         double sa[NPT], sg[NPT], sb[NPT];
-        syn_sums<BS, NPT>(w, K, Y, sa, sg, sb);
+        syn(Y, sa, sg, sb);
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            if (k * BS >= w.n) continue;
-            const int i = tid + k * BS;
-            if (stash && i < w.n) {
+            if (!live(k)) continue;
+            const int i = idx(k);
+            if (stash && i < sl.n) {
 #pragma unroll
                 for (int v = 0; v < NVAR; ++v) stash->sY[(q * NVAR + v) * stash->ld + i] = Y[k][v];
                 stash->sS[(q * 3 + 0) * stash->ld + i] = sa[k];
@@ -474,7 +484,7 @@ __device__ __forceinline__ void rk_step_wg_tab(const WGSyn &w, const Kin &K, dou
             }
             double f[NVAR];
             hh_rhs(Y[k], prm_of(pr[k]), K, cgf * sa[k], cgf * sg[k], cgf * sb[k], Iu[k],
-                   i >= w.n_pn, w.gabab, f);
+                   i >= sl.n_pn, sl.gabab, f);
 #pragma unroll
             for (int v = 0; v < NVAR; ++v) {
                 inc[k][v] += T.b[q] * f[v];
@@ -484,13 +494,45 @@ __device__ __forceinline__ void rk_step_wg_tab(const WGSyn &w, const Kin &K, dou
     }
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        if (tid + k * BS >= w.n) continue;
+        if (idx(k) >= sl.n || !live(k)) continue;
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
             float hi, lo;
             y[k][v] = split_store(y[k][v] + dt * inc[k][v], hi, lo);
         }
     }
+}
+
+// The per-instance mappings: slot k of thread tid is neuron tid + k BS.
+template <int BS, int NPT>
+__device__ __forceinline__ void rk4_step_wg(const WGSyn &w, const Kin &K, double cgf,
+                                            const float (&pr)[NPT][NPRM], const double (&Iu)[NPT],
+                                            double dt, double (&y)[NPT][NVAR],
+                                            const StageStash *stash)
+{
+    const int tid = threadIdx.x;
+    rk4_step_core<NPT>(
+        Slots{w.n, w.n_pn, w.gabab},
+        [&](const double (&Y)[NPT][NVAR], double (&sa)[NPT], double (&sg)[NPT],
+            double (&sb)[NPT]) { syn_sums<BS, NPT>(w, K, Y, sa, sg, sb); },
+        [&](int k) { return tid + k * BS; }, [&](int k) { return k * BS < w.n; }, K, cgf, pr,
+        Iu, dt, y, stash);
+}
+
+template <int BS, int NPT>
+__device__ __forceinline__ void rk_step_wg_tab(const WGSyn &w, const Kin &K, double cgf,
+                                               const float (&pr)[NPT][NPRM],
+                                               const double (&Iu)[NPT], double dt,
+                                               double (&y)[NPT][NVAR], const StageStash *stash,
+                                               const Tab &T)
+{
+    const int tid = threadIdx.x;
+    rk_step_core_tab<NPT>(
+        Slots{w.n, w.n_pn, w.gabab},
+        [&](const double (&Y)[NPT][NVAR], double (&sa)[NPT], double (&sg)[NPT],
+            double (&sb)[NPT]) { syn_sums<BS, NPT>(w, K, Y, sa, sg, sb); },
+        [&](int k) { return tid + k * BS; }, [&](int k) { return k * BS < w.n; }, K, cgf, pr,
+        Iu, dt, y, stash, T);
 }
 
 // Set up the workgroup's view of instance d: LDS carve-up and the resident
