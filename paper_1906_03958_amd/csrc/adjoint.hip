@@ -51,7 +51,11 @@ struct AdjArgs {
     int64_t lds_bytes;
     int32_t *flag;
     Tab tab;                    // method of the generic-step variants
-    int32_t mode;               // 0 choose, 1 no matrix-core contraction, 2 prefer it
+    int32_t mode;               // 0 default, 1 per-step LDS accumulation of dL/dg
+    double *adj_state;          // per instance [NVAR][ld]: lam between segment launches
+    int64_t adj_stride;
+    int64_t seg;                // the segment this launch handles
+    int32_t first;              // 1: the first launch of the call (the last segment)
 };
 
 // workspace layout of one instance (doubles), ld = padded neuron count
@@ -280,8 +284,52 @@ __device__ __forceinline__ double row_dot_quad(F *row, const double *q, int n, i
     return p + __shfl_xor(p, 2);
 }
 
+// How one instance's reverse sweep uses the LDS: lacc -- the step's stage
+// records and the dL/dg accumulator as float32 (value, compensation) planes in
+// LDS, updated every step (only when asked for, PSST_ADJ_MODE=lacc, and when
+// it fits); otherwise the records go to the workspace for the segment's
+// contraction kernel.  staged -- one step's stage data (40 doubles per
+// neuron) staged through LDS: when the whole conductance matrix still fits
+// beside it, or, when the matrix does not fit anyway, when the staging takes
+// at most half of the LDS.
+struct AdjModes {
+    bool lacc, staged;
+    int rows;                   // presynaptic rows of the conductance matrices
+};
+
+__device__ inline AdjModes adj_modes(const InstDesc &d, int64_t lds_bytes, int mode)
+{
+    const int n = d.n, ld = d.ld, n_ln = d.n - d.n_pn;
+    const bool gb_net = (d.flags & DESC_GABAB) != 0;
+    AdjModes m;
+    m.rows = (d.flags & DESC_NOSYN) ? 0 : n + (gb_net ? n_ln : 0);
+    const Chunks ch0 = chunks_of(n, d.n_pn, gb_net);
+    const int nch = ch0.na + ch0.ng + ch0.nb;
+    const int64_t fwd_min = (int64_t)sizeof(double) * (2 + nch) * ld;
+    const int64_t lacc_bytes = (int64_t)sizeof(double) * (5 + 20) * ld +
+                               (int64_t)sizeof(float) * 2 * m.rows * ld;
+    const int64_t res_bytes = (int64_t)sizeof(float) * nch * CW * ld;
+    const int64_t base5 = (int64_t)sizeof(double) * 5 * ld;
+    const int64_t stage_b = (int64_t)sizeof(double) * 40 * ld;
+    m.lacc = mode == 1 && m.rows > 0 && lacc_bytes + fwd_min <= lds_bytes;
+    const bool res_fits = base5 + fwd_min + res_bytes <= lds_bytes;
+    m.staged = !m.lacc && (res_fits ? base5 + stage_b + fwd_min + res_bytes <= lds_bytes
+                                    : 2 * (base5 + stage_b) <= lds_bytes);
+    return m;
+}
+
+// The reverse sweep over one segment (a.seg) of every instance, one
+// workgroup per instance: the stage inputs and synaptic sums of the
+// segment's steps are in the workspace (written by the forward kernels'
+// recomputation); lam and the per-neuron gradient partials carry over from
+// the previous launch through adj_state.  Per step, stages last to first:
+// the elementwise VJP, the presynaptic term sum_i g_ij q(i) (four lanes per
+// presynaptic row, each summing one residue class of i in index order), and
+// lam <- lam + sum_q u_q + dL/dV.  The q and x vectors of every (step, stage)
+// go to the workspace for the contraction kernel (or, lacc, into the LDS
+// accumulator).
 template <int BS, bool GEN>
-__global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
+__global__ __launch_bounds__(BS) void adjoint_reverse_kernel(AdjArgs a)
 {
     constexpr int NPT = 1;
     extern __shared__ double lds_d[];
@@ -289,40 +337,24 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
     const InstDesc d = a.desc[b];
     const int n = d.n, n_pn = d.n_pn, ld = d.ld, n_ln = d.n - d.n_pn;
     const int tid = threadIdx.x;
-    // LDS: q vectors [3][ld] and transposed products [2][ld]; then, when
-    // they fit, the step's four stage records [4][5][ld] and the gradient
-    // accumulator as float32 (value, compensation) planes [2][rows][ld], or
-    // else a staging area for one step's stage data [40][ld]; then the
-    // forward view with as many conductance columns as remain.
-    const bool gb_net = (d.flags & DESC_GABAB) != 0;
-    // presynaptic rows of the conductance matrices (none without synapses)
-    const int rows = (d.flags & DESC_NOSYN) ? 0 : n + (gb_net ? n_ln : 0);
-    const Chunks ch0 = chunks_of(n, n_pn, gb_net);
-    const int64_t fwd_min = (int64_t)sizeof(double) * (2 + ch0.na + ch0.ng + ch0.nb) * ld;
+    // LDS: q vectors [3][ld] and transposed products [2][ld]; then, lacc, the
+    // step's four stage records [4][5][ld] and the gradient accumulator
+    // [2][rows][ld] float32, or a staging area for one step's stage data
+    // [40][ld]; then the conductance view with as many columns as remain.
+    const AdjModes md = adj_modes(d, a.lds_bytes, a.mode);
+    const bool lacc = md.lacc, staged = md.staged;
+    const int rows = md.rows;
     const int64_t lacc_bytes = (int64_t)sizeof(double) * (5 + 20) * ld +
                                (int64_t)sizeof(float) * 2 * rows * ld;
-    // mma: every conductance column in LDS for the recomputation and the
-    // transposed products, dL/dg contracted once per segment on the matrix
-    // cores; chosen when the whole matrix fits beside the q/product vectors
-    const int64_t res_bytes =
-        (int64_t)sizeof(float) * (ch0.na + ch0.ng + ch0.nb) * CW * ld;
-    const int64_t base5 = (int64_t)sizeof(double) * 5 * ld;
-    const bool mma = a.mode != 1 && rows > 0 && base5 + fwd_min + res_bytes <= a.lds_bytes;
-    const bool lacc = !mma && lacc_bytes + fwd_min <= a.lds_bytes;
     double *qb = lds_d;
     double *tb = lds_d + 3 * ld;
     double *recs = lds_d + 5 * ld;                         // lacc: [4][5][ld]
     float *gls = reinterpret_cast<float *>(lds_d + 25 * ld);  // lacc: [2][rows][ld]
-    // staging of one step's stage data (40 doubles per neuron) when it takes
-    // at most half of the LDS: one global round trip per reverse step
     const int64_t stage_d = 40LL * ld;
-    const bool staged =
-        mma ? base5 + (int64_t)sizeof(double) * stage_d + fwd_min + res_bytes <= a.lds_bytes
-            : !lacc && (int64_t)sizeof(double) * (5 * ld + stage_d) * 2 <= a.lds_bytes;
     double *stg = lds_d + 5 * ld;
     const int64_t used_b = lacc ? lacc_bytes
                                 : (int64_t)sizeof(double) * (5 * ld + (staged ? stage_d : 0));
-    WGSyn w = wg_setup<BS>(d, lds_d + used_b / sizeof(double), a.lds_bytes - used_b);
+    const WGSyn w = wg_setup<BS>(d, lds_d + used_b / sizeof(double), a.lds_bytes - used_b);
     const bool gabab = w.gabab;
     const Kin K = load_kin(d.kin);
     const double dt = a.dt;
@@ -332,13 +364,19 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
     float *gacc = a.gacc + (int64_t)b * a.gacc_stride;
     const int64_t sec_f = (int64_t)n * ld, sec_b = (int64_t)n_ln * ld, sec_p = 3LL * ld;
     const int64_t half = sec_f + sec_b + sec_p;     // value plane size
-    for (int64_t e = tid; e < 2 * half; e += BS) gacc[e] = 0.f;
-
+    double *ast = a.adj_state + (int64_t)b * a.adj_stride;
+    if (a.first)
+        for (int64_t e = tid; e < 2 * half; e += BS) gacc[e] = 0.f;
     for (int e = tid; e < 3 * ld; e += BS) qb[e] = 0.0;   // padding entries stay 0
     if (lacc) {
         for (int e = tid; e < 20 * ld; e += BS) recs[e] = 0.0;
-        for (int e = tid; e < 2 * rows * ld; e += BS) gls[e] = 0.f;
+        // the accumulator continues from the previous launch's
+        for (int64_t e = tid; e < (int64_t)rows * ld; e += BS) {
+            gls[e] = a.first ? 0.f : gacc[e];
+            gls[(int64_t)rows * ld + e] = a.first ? 0.f : gacc[half + e];
+        }
     }
+    __syncthreads();
     const int i = tid;                               // the thread's neuron (NPT = 1)
     const bool own = i < n;
     const int ic = own ? i : 0;
@@ -348,318 +386,232 @@ __global__ __launch_bounds__(BS) void adjoint_wg_kernel(AdjArgs a)
 #pragma unroll
     for (int p = 0; p < NPRM; ++p) pr[0][p] = d.prm[p * ld + ic];
     const Prm P = prm_of(pr[0]);
-    const double Ic = a.stim.i_const ? (double)a.stim.i_const[gi] : 0.0;
-    const int32_t p0 = a.stim.pulse_ptr ? a.stim.pulse_ptr[gi] : 0;
-    const int32_t p1 = a.stim.pulse_ptr ? a.stim.pulse_ptr[gi + 1] : 0;
 
     double lam[NVAR];
-#pragma unroll
-    for (int v = 0; v < NVAR; ++v) lam[v] = 0.0;
     double pg[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) lam[v] = (a.first || !own) ? 0.0 : ast[(int64_t)v * ld + i];
     const double bq[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     const double cq[4] = {0.0, 0.5, 0.5, 1.0};
 
-    const int64_t nseg = (a.n_steps + KK - 1) / KK;
-    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-        const int64_t s0 = seg * KK;
-        const int L = (int)((a.n_steps - s0) < KK ? (a.n_steps - s0) : KK);
-        // ---- forward recompute of the segment from its checkpoint
-        double y[NPT][NVAR];
-        const float *cp = a.ckpt + seg * (14 * NT);
+    const int64_t seg = a.seg;
+    const int64_t s0 = seg * KK;
+    const int L = (int)((a.n_steps - s0) < KK ? (a.n_steps - s0) : KK);
+    // ---- reverse steps
+    for (int s = L - 1; s >= 0; --s) {
+        const int64_t ls = s0 + s;                 // local step index
+        if (own) lam[YV] += (double)a.dLdV[ls * NT + gi];
+        const double *sYs = W.sY + (int64_t)s * 4 * NVAR * ld;
+        const double *sSs = W.sS + (int64_t)s * 12 * ld;
+        if (staged) {
+            // each thread moves its own neuron's 40 values (the same
+            // thread reads them back, so no barrier is needed)
+            if (own) {
+                double tmp[40];
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v)
-            y[0][v] = (double)cp[(2 * v) * NT + gi] + (double)cp[(2 * v + 1) * NT + gi];
-        for (int s = 0; s < L; ++s) {
-            StageStash stash;      // this step's stage inputs and sums
-            stash.sY = W.sY + (int64_t)s * 4 * NVAR * ld;
-            stash.sS = W.sS + (int64_t)s * 12 * ld;
-            stash.ld = ld;
-            double Iu[NPT] = {d.ci * stim_nA(a.stim, Ic, p0, p1, a.step0 + s0 + s)};
-            if constexpr (GEN)
-                rk_step_wg_tab<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, &stash, a.tab);
-            else
-                rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, &stash);
-        }
-        // ---- reverse steps
-        for (int s = L - 1; s >= 0; --s) {
-            const int64_t ls = s0 + s;                 // local step index
-            if (own) lam[YV] += (double)a.dLdV[ls * NT + gi];
-            const double *sYs = W.sY + (int64_t)s * 4 * NVAR * ld;
-            const double *sSs = W.sS + (int64_t)s * 12 * ld;
-            if (staged) {
-                // each thread moves its own neuron's 40 values (the same
-                // thread reads them back, so no barrier is needed)
-                if (own) {
-                    double tmp[40];
+                for (int e = 0; e < 28; ++e) tmp[e] = sYs[(int64_t)e * ld + i];
 #pragma unroll
-                    for (int e = 0; e < 28; ++e) tmp[e] = sYs[(int64_t)e * ld + i];
+                for (int e = 0; e < 12; ++e) tmp[28 + e] = sSs[(int64_t)e * ld + i];
 #pragma unroll
-                    for (int e = 0; e < 12; ++e) tmp[28 + e] = sSs[(int64_t)e * ld + i];
-#pragma unroll
-                    for (int e = 0; e < 40; ++e) stg[(int64_t)e * ld + i] = tmp[e];
-                }
-                sYs = stg;
-                sSs = stg + 28 * ld;
+                for (int e = 0; e < 40; ++e) stg[(int64_t)e * ld + i] = tmp[e];
             }
-            double un[NVAR], usum[NVAR];
-            double uh[GEN ? 4 : 1][NVAR];      // generic method: u of the later stages
-            constexpr int kStageUnroll = GEN ? 4 : 1;
+            sYs = stg;
+            sSs = stg + 28 * ld;
+        }
+        double un[NVAR], usum[NVAR];
+        double uh[GEN ? 4 : 1][NVAR];      // generic method: u of the later stages
+        constexpr int kStageUnroll = GEN ? 4 : 1;
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+            un[v] = 0.0;
+            usum[v] = 0.0;
+        }
+        // classical RK4: kbar_q = dt b_q lam + dt c_{q+1} u_{q+1}; a generic
+        // tableau: kbar_q = dt b_q lam + dt sum_{r>q} a_rq u_r (stages last
+        // to first, unrolled so the u_r stay in registers)
+#pragma unroll kStageUnroll
+        for (int q = 3; q >= 0; --q) {
+            if (GEN && q >= a.tab.s) {
+                // a stage the method lacks: its records enter the segment
+                // contraction as zeros (the workspace keeps older contents)
+                if (!lacc && own) {
+                    const int64_t rz = (ls - s0) * 4 + q;
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) W.Qs[(rz * 3 + t) * ld + i] = 0.0;
+                    W.Xs[(rz * 2 + 0) * ld + i] = 0.0;
+                    if (gabab && is_ln) W.Xs[(rz * 2 + 1) * ld + (i - n_pn)] = 0.0;
+                }
+                continue;
+            }
+            double Yq[NVAR], kb[NVAR], u[NVAR], qq[3], dg[3];
 #pragma unroll
             for (int v = 0; v < NVAR; ++v) {
-                un[v] = 0.0;
-                usum[v] = 0.0;
-            }
-            // classical RK4: kbar_q = dt b_q lam + dt c_{q+1} u_{q+1}; a generic
-            // tableau: kbar_q = dt b_q lam + dt sum_{r>q} a_rq u_r (stages last
-            // to first, unrolled so the u_r stay in registers)
-#pragma unroll kStageUnroll
-            for (int q = 3; q >= 0; --q) {
-                if (GEN && q >= a.tab.s) {
-                    // a stage the method lacks: its records enter the segment
-                    // contraction as zeros (the workspace keeps older contents)
-                    if (!lacc && own) {
-                        const int64_t rz = (ls - s0) * 4 + q;
+                Yq[v] = own ? sYs[(q * NVAR + v) * ld + i] : 0.0;
+                if constexpr (GEN) {
+                    double t = dt * a.tab.b[q] * lam[v];
 #pragma unroll
-                        for (int t = 0; t < 3; ++t) W.Qs[(rz * 3 + t) * ld + i] = 0.0;
-                        W.Xs[(rz * 2 + 0) * ld + i] = 0.0;
-                        if (gabab && is_ln) W.Xs[(rz * 2 + 1) * ld + (i - n_pn)] = 0.0;
-                    }
-                    continue;
-                }
-                double Yq[NVAR], kb[NVAR], u[NVAR], qq[3], dg[3];
-#pragma unroll
-                for (int v = 0; v < NVAR; ++v) {
-                    Yq[v] = own ? sYs[(q * NVAR + v) * ld + i] : 0.0;
-                    if constexpr (GEN) {
-                        double t = dt * a.tab.b[q] * lam[v];
-#pragma unroll
-                        for (int r = q + 1; r < 4; ++r)
-                            if (r < a.tab.s) t += dt * a.tab.a[r][q] * uh[r][v];
-                        kb[v] = t;
-                    } else {
-                        kb[v] = dt * bq[q] * lam[v] + (q < 3 ? dt * cq[q + 1] * un[v] : 0.0);
-                    }
-                }
-                if (!own) Yq[YM] = Yq[YH] = Yq[YN] = 0.5;   // keep idle lanes finite
-                const double sa = own ? sSs[(q * 3 + 0) * ld + i] : 0.0;
-                const double sg = own ? sSs[(q * 3 + 1) * ld + i] : 0.0;
-                const double sbv = own ? sSs[(q * 3 + 2) * ld + i] : 0.0;
-                hh_vjp(Yq, P, K, d.cg, d.cg * sa, d.cg * sg, d.cg * sbv, kb, is_ln, gabab, u, qq,
-                       dg);
-                const int64_t rec = ls - s0;           // stage record within the segment
-                double *qv0 = lacc ? recs + q * 5 * ld : qb;  // this stage's q vectors
-                if (own) {
-                    pg[0] += dg[0];
-                    pg[1] += dg[1];
-                    pg[2] += dg[2];
-#pragma unroll
-                    for (int t = 0; t < 3; ++t) qv0[t * ld + i] = qq[t];
-                    if (lacc) {
-                        recs[(q * 5 + 3) * ld + i] = Yq[YS];
-                        if (gabab && is_ln) recs[(q * 5 + 4) * ld + (i - n_pn)] = gabab_act(Yq[YG], K);
-                    } else {
-#pragma unroll
-                        for (int t = 0; t < 3; ++t) W.Qs[((rec * 4 + q) * 3 + t) * ld + i] = qq[t];
-                        W.Xs[((rec * 4 + q) * 2 + 0) * ld + i] = Yq[YS];
-                        if (gabab && is_ln)
-                            W.Xs[((rec * 4 + q) * 2 + 1) * ld + (i - n_pn)] = gabab_act(Yq[YG], K);
-                    }
-                }
-                __syncthreads();
-                // presynaptic terms: t_j = sum_i g_ij q_type(j)(i), four lanes per
-                // presynaptic row j (row j of the transposed matrix is contiguous)
-                for (int r0 = 0; r0 < rows; r0 += BS / 4) {
-                    const int r = r0 + (tid >> 2);
-                    const bool on = r < rows;
-                    const int rr = on ? r : 0;
-                    const bool slow = rr >= n;
-                    const int jr = slow ? rr - n : rr;
-                    const double *qv = qv0 + (slow ? 2 : (jr < n_pn ? 0 : 1)) * ld;
-                    double acc;
-                    // rows of the transposed matrix: from LDS when the dense
-                    // layout is resident there, else from global memory (also
-                    // for sparse storage, whose LDS holds the forward's rows)
-                    if (w.R >= CW && !w.sparse)
-                        acc = row_dot_quad((lds_float *)lds_row(w, slow ? 1 : 0, jr), qv, n,
-                                           tid & 3, on);
-                    else
-                        acc = row_dot_quad((global_float *)((slow ? d.gtb : d.gt) + (int64_t)jr * ld),
-                                           qv, n, tid & 3, on);
-                    if (on && (tid & 3) == 0) tb[(slow ? ld : 0) + jr] = acc;
-                }
-                __syncthreads();
-                if (own && rows > 0) {
-                    u[YS] += tb[i];
-                    if (gabab && is_ln) u[YG] += tb[ld + (i - n_pn)] * gabab_act_d(Yq[YG], K);
-                }
-#pragma unroll
-                for (int v = 0; v < NVAR; ++v) {
-                    un[v] = u[v];
-                    if constexpr (GEN) uh[q][v] = u[v];
-                    usum[v] += u[v];
+                    for (int r = q + 1; r < 4; ++r)
+                        if (r < a.tab.s) t += dt * a.tab.a[r][q] * uh[r][v];
+                    kb[v] = t;
+                } else {
+                    kb[v] = dt * bq[q] * lam[v] + (q < 3 ? dt * cq[q + 1] * un[v] : 0.0);
                 }
             }
+            if (!own) Yq[YM] = Yq[YH] = Yq[YN] = 0.5;   // keep idle lanes finite
+            const double sa = own ? sSs[(q * 3 + 0) * ld + i] : 0.0;
+            const double sg = own ? sSs[(q * 3 + 1) * ld + i] : 0.0;
+            const double sbv = own ? sSs[(q * 3 + 2) * ld + i] : 0.0;
+            hh_vjp(Yq, P, K, d.cg, d.cg * sa, d.cg * sg, d.cg * sbv, kb, is_ln, gabab, u, qq,
+                   dg);
+            const int64_t rec = ls - s0;           // stage record within the segment
+            double *qv0 = lacc ? recs + q * 5 * ld : qb;  // this stage's q vectors
+            if (own) {
+                pg[0] += dg[0];
+                pg[1] += dg[1];
+                pg[2] += dg[2];
 #pragma unroll
-            for (int v = 0; v < NVAR; ++v) lam[v] += usum[v];
-            if (lacc) {
-                // dL/dg_ij += sum over this step's stages of q(i) x_j: float64
-                // sum of the four products, then one compensated add per entry
-                __syncthreads();
-                const int q4 = ld >> 2;
-                const int RG = BS / q4;
-                const int i4 = tid % q4, rg = tid / q4;
-                if (rg < RG) {
-                    int cur_t = -1;
-                    double qv[4][4];
-                    for (int r = rg; r < rows; r += RG) {
-                        const bool slow = r >= n;
-                        const int j = slow ? r - n : r;
-                        const int t = slow ? 2 : (j < n_pn ? 0 : 1);
-                        if (t != cur_t) {
-                            cur_t = t;
+                for (int t = 0; t < 3; ++t) qv0[t * ld + i] = qq[t];
+                if (lacc) {
+                    recs[(q * 5 + 3) * ld + i] = Yq[YS];
+                    if (gabab && is_ln) recs[(q * 5 + 4) * ld + (i - n_pn)] = gabab_act(Yq[YG], K);
+                } else {
 #pragma unroll
-                            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                                for (int c = 0; c < 4; ++c) qv[q][c] = recs[(q * 5 + t) * ld + 4 * i4 + c];
-                        }
-                        double v[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const double x = recs[(q * 5 + (slow ? 4 : 3)) * ld + j];
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) v[c] = fma(qv[q][c], x, v[c]);
-                        }
-                        float *hp = gls + (int64_t)r * ld + 4 * i4;
-                        float *lp = gls + (int64_t)(rows + r) * ld + 4 * i4;
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            float h, l;
-                            split_store((double)hp[c] + (double)lp[c] + v[c], h, l);
-                            hp[c] = h;
-                            lp[c] = l;
-                        }
-                    }
+                    for (int t = 0; t < 3; ++t) W.Qs[((rec * 4 + q) * 3 + t) * ld + i] = qq[t];
+                    W.Xs[((rec * 4 + q) * 2 + 0) * ld + i] = Yq[YS];
+                    if (gabab && is_ln)
+                        W.Xs[((rec * 4 + q) * 2 + 1) * ld + (i - n_pn)] = gabab_act(Yq[YG], K);
                 }
-                __syncthreads();
+            }
+            __syncthreads();
+            // presynaptic terms: t_j = sum_i g_ij q_type(j)(i), four lanes per
+            // presynaptic row j (row j of the transposed matrix is contiguous)
+            for (int r0 = 0; r0 < rows; r0 += BS / 4) {
+                const int r = r0 + (tid >> 2);
+                const bool on = r < rows;
+                const int rr = on ? r : 0;
+                const bool slow = rr >= n;
+                const int jr = slow ? rr - n : rr;
+                const double *qv = qv0 + (slow ? 2 : (jr < n_pn ? 0 : 1)) * ld;
+                double acc;
+                // rows of the transposed matrix: from LDS when the dense
+                // layout is resident there, else from global memory (also
+                // for sparse storage, whose LDS holds the forward's rows)
+                if (w.R >= CW && !w.sparse)
+                    acc = row_dot_quad((lds_float *)lds_row(w, slow ? 1 : 0, jr), qv, n,
+                                       tid & 3, on);
+                else
+                    acc = row_dot_quad((global_float *)((slow ? d.gtb : d.gt) + (int64_t)jr * ld),
+                                       qv, n, tid & 3, on);
+                if (on && (tid & 3) == 0) tb[(slow ? ld : 0) + jr] = acc;
+            }
+            __syncthreads();
+            if (own && rows > 0) {
+                u[YS] += tb[i];
+                if (gabab && is_ln) u[YG] += tb[ld + (i - n_pn)] * gabab_act_d(Yq[YG], K);
+            }
+#pragma unroll
+            for (int v = 0; v < NVAR; ++v) {
+                un[v] = u[v];
+                if constexpr (GEN) uh[q][v] = u[v];
+                usum[v] += u[v];
             }
         }
-        __syncthreads();
-        // ---- dL/dg over the segment: sum over its 4L stage records of q(i) x_j,
-        // in record order for every entry.  With the staging area available
-        // the records go through LDS eight at a time and each thread keeps
-        // IPT row quads of accumulators per pass.
-        {
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) lam[v] += usum[v];
+        if (lacc) {
+            // dL/dg_ij += sum over this step's stages of q(i) x_j: float64
+            // sum of the four products, then one compensated add per entry
+            __syncthreads();
             const int q4 = ld >> 2;
-            const int T = 4 * L;
-            const int items = (lacc || mma) ? 0 : rows * q4;
-            if (mma) {
-                contract_mma<BS>(W, T, n, n_pn, n_ln, gabab, ld, lds_d + 5 * ld,
-                                 a.lds_bytes / (int64_t)sizeof(double) - 5LL * ld, gacc, half,
-                                 sec_f);
-            } else if (staged) {
-                constexpr int IPT = 8, TT = 8;
-                for (int base = 0; base < items; base += BS * IPT) {
-                    double acc[IPT][4];
-#pragma unroll
-                    for (int k = 0; k < IPT; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.0;
-                    for (int t0 = 0; t0 < T; t0 += TT) {
-                        const int tn = min(TT, T - t0);
-                        __syncthreads();
-                        for (int idx = tid; idx < ld; idx += BS) {
-                            for (int rec = 0; rec < tn; ++rec) {
-                                const double *qs = W.Qs + (int64_t)(t0 + rec) * 3 * ld + idx;
-                                const double *xsr = W.Xs + (int64_t)(t0 + rec) * 2 * ld + idx;
-                                double *dst = stg + rec * 5 * ld + idx;
-                                dst[0] = qs[0];
-                                dst[ld] = qs[ld];
-                                dst[2 * ld] = qs[2 * ld];
-                                dst[3 * ld] = xsr[0];
-                                dst[4 * ld] = xsr[ld];
-                            }
-                        }
-                        __syncthreads();
-#pragma unroll
-                        for (int k = 0; k < IPT; ++k) {
-                            const int item = base + tid + k * BS;
-                            if (item >= items) continue;
-                            const int r = item / q4, i4 = item % q4;
-                            const bool slow = r >= n;
-                            const int j = slow ? r - n : r;
-                            const int t = slow ? 2 : (j < n_pn ? 0 : 1);
-                            const int xs = slow ? 1 : 0;
-                            for (int tt = 0; tt < tn; ++tt) {
-                                const double xv = stg[(tt * 5 + 3 + xs) * ld + j];
-                                const double *qr = stg + (tt * 5 + t) * ld + 4 * i4;
-                                acc[k][0] = fma(qr[0], xv, acc[k][0]);
-                                acc[k][1] = fma(qr[1], xv, acc[k][1]);
-                                acc[k][2] = fma(qr[2], xv, acc[k][2]);
-                                acc[k][3] = fma(qr[3], xv, acc[k][3]);
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int k = 0; k < IPT; ++k) {
-                        const int item = base + tid + k * BS;
-                        if (item >= items) continue;
-                        const int r = item / q4, i4 = item % q4;
-                        const bool slow = r >= n;
-                        const int j = slow ? r - n : r;
-                        const int64_t e = (slow ? sec_f : 0) + (int64_t)j * ld + 4 * i4;
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) comp_add(gacc + e + c, gacc + half + e + c, acc[k][c]);
-                    }
-                }
-            } else {
-                for (int64_t p = tid; p < items; p += BS) {
-                    const int r = (int)(p / q4), i4 = (int)(p % q4);
+            const int RG = BS / q4;
+            const int i4 = tid % q4, rg = tid / q4;
+            if (rg < RG) {
+                int cur_t = -1;
+                double qv[4][4];
+                for (int r = rg; r < rows; r += RG) {
                     const bool slow = r >= n;
                     const int j = slow ? r - n : r;
                     const int t = slow ? 2 : (j < n_pn ? 0 : 1);
-                    const int xs = slow ? 1 : 0;
-                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                    for (int tt = 0; tt < T; ++tt) {
-                        const double xv = W.Xs[((int64_t)tt * 2 + xs) * ld + j];
-                        const double *qr = W.Qs + ((int64_t)tt * 3 + t) * ld + 4 * i4;
-                        a0 = fma(qr[0], xv, a0);
-                        a1 = fma(qr[1], xv, a1);
-                        a2 = fma(qr[2], xv, a2);
-                        a3 = fma(qr[3], xv, a3);
-                    }
-                    const int64_t e = (slow ? sec_f : 0) + (int64_t)j * ld + 4 * i4;
-                    comp_add(gacc + e + 0, gacc + half + e + 0, a0);
-                    comp_add(gacc + e + 1, gacc + half + e + 1, a1);
-                    comp_add(gacc + e + 2, gacc + half + e + 2, a2);
-                    comp_add(gacc + e + 3, gacc + half + e + 3, a3);
-                }
-            }
-            if (own) {
+                    if (t != cur_t) {
+                        cur_t = t;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const int64_t e = sec_f + sec_b + (int64_t)k * ld + i;
-                    comp_add(gacc + e, gacc + half + e, pg[k]);
-                    pg[k] = 0.0;
+                        for (int q = 0; q < 4; ++q)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) qv[q][c] = recs[(q * 5 + t) * ld + 4 * i4 + c];
+                    }
+                    double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double x = recs[(q * 5 + (slow ? 4 : 3)) * ld + j];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) v[c] = fma(qv[q][c], x, v[c]);
+                    }
+                    float *hp = gls + (int64_t)r * ld + 4 * i4;
+                    float *lp = gls + (int64_t)(rows + r) * ld + 4 * i4;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        float h, l;
+                        split_store((double)hp[c] + (double)lp[c] + v[c], h, l);
+                        hp[c] = h;
+                        lp[c] = l;
+                    }
                 }
             }
-        }
-        __syncthreads();
-        // the contraction used the conductances' LDS: copy them back for the
-        // next segment's recomputation
-        if (mma && seg > 0) {
-            w = wg_setup<BS>(d, lds_d + used_b / sizeof(double), a.lds_bytes - used_b);
             __syncthreads();
         }
     }
+    // the per-neuron gradients of the segment into their accumulators
+    if (own) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t e = sec_f + sec_b + (int64_t)k * ld + i;
+            comp_add(gacc + e, gacc + half + e, pg[k]);
+        }
+    }
     if (lacc) {
+        __syncthreads();
         // value plane -> gacc[0 .. rows*ld), compensation plane -> gacc[half ..]
         for (int64_t e = tid; e < (int64_t)rows * ld; e += BS) {
             gacc[e] = gls[e];
             gacc[half + e] = gls[(int64_t)rows * ld + e];
         }
     }
-    double chk = 0.0;
+    if (own) {
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) chk += lam[v];
-    if (own && !finite_d(chk)) atomicOr(a.flag, 1);
+        for (int v = 0; v < NVAR; ++v) ast[(int64_t)v * ld + i] = lam[v];
+    }
+    if (seg == 0) {
+        double chk = 0.0;
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) chk += lam[v];
+        if (own && !finite_d(chk)) atomicOr(a.flag, 1);
+    }
+}
+
+// dL/dg over one segment (a.seg) of every instance: for each synapse class
+// the product X^T Q over the segment's 4L stage records on the float64
+// matrix cores, added to the compensated accumulators (instances whose
+// reverse sweep accumulated in LDS, and networks without synapses, have
+// nothing to add).
+template <int BS>
+__global__ __launch_bounds__(BS) void adjoint_contract_kernel(AdjArgs a)
+{
+    extern __shared__ double lds_d[];
+    const int b = blockIdx.x;
+    const InstDesc d = a.desc[b];
+    const AdjModes md = adj_modes(d, a.lds_bytes, a.mode);
+    if (md.lacc || md.rows == 0) return;
+    const int n = d.n, n_pn = d.n_pn, ld = d.ld, n_ln = d.n - d.n_pn;
+    const bool gabab = (d.flags & DESC_GABAB) != 0;
+    const int KK = a.K;
+    const WsLayout W = ws_layout(a.ws + (int64_t)b * a.ws_stride, ld, KK);
+    float *gacc = a.gacc + (int64_t)b * a.gacc_stride;
+    const int64_t sec_f = (int64_t)n * ld, sec_b = (int64_t)n_ln * ld;
+    const int64_t half = sec_f + sec_b + 3LL * ld;
+    const int64_t s0 = a.seg * KK;
+    const int L = (int)((a.n_steps - s0) < KK ? (a.n_steps - s0) : KK);
+    contract_mma<BS>(W, 4 * L, n, n_pn, n_ln, gabab, ld, lds_d,
+                     a.lds_bytes / (int64_t)sizeof(double), gacc, half, sec_f);
 }
 
 // Scatter the accumulators into the caller's layout: per instance (grid.x =
@@ -723,6 +675,8 @@ struct AdjWork {
     float *gacc = nullptr;
     size_t gacc_bytes = 0;
     int64_t *goff = nullptr;
+    double *astate = nullptr;
+    size_t astate_bytes = 0;
 };
 
 static psst_status ensure(void **p, size_t *have, size_t need)
@@ -739,10 +693,21 @@ static psst_status ensure(void **p, size_t *have, size_t need)
 static const void *adj_fn(int bs, bool gen)
 {
     switch (bs) {
-    case 64: return gen ? (const void *)adjoint_wg_kernel<64, true> : (const void *)adjoint_wg_kernel<64, false>;
-    case 128: return gen ? (const void *)adjoint_wg_kernel<128, true> : (const void *)adjoint_wg_kernel<128, false>;
-    case 256: return gen ? (const void *)adjoint_wg_kernel<256, true> : (const void *)adjoint_wg_kernel<256, false>;
-    case 512: return gen ? (const void *)adjoint_wg_kernel<512, true> : (const void *)adjoint_wg_kernel<512, false>;
+    case 64: return gen ? (const void *)adjoint_reverse_kernel<64, true> : (const void *)adjoint_reverse_kernel<64, false>;
+    case 128: return gen ? (const void *)adjoint_reverse_kernel<128, true> : (const void *)adjoint_reverse_kernel<128, false>;
+    case 256: return gen ? (const void *)adjoint_reverse_kernel<256, true> : (const void *)adjoint_reverse_kernel<256, false>;
+    case 512: return gen ? (const void *)adjoint_reverse_kernel<512, true> : (const void *)adjoint_reverse_kernel<512, false>;
+    }
+    return nullptr;
+}
+
+static const void *contract_fn(int bs)
+{
+    switch (bs) {
+    case 64: return (const void *)adjoint_contract_kernel<64>;
+    case 128: return (const void *)adjoint_contract_kernel<128>;
+    case 256: return (const void *)adjoint_contract_kernel<256>;
+    case 512: return (const void *)adjoint_contract_kernel<512>;
     }
     return nullptr;
 }
@@ -790,7 +755,9 @@ struct AdjPlan {
     size_t lds = 0;
     int64_t wstride = 0;     // doubles of stage records per instance
     int64_t gstride = 0;     // floats of gradient accumulators per instance
+    int64_t astride = 0;     // doubles of carried adjoint state per instance
     const void *fn = nullptr;
+    const void *fn_con = nullptr;
 };
 
 static psst_status adjoint_plan(const std::vector<psst_network *> &nets, int32_t K,
@@ -824,23 +791,31 @@ static psst_status adjoint_plan(const std::vector<psst_network *> &nets, int32_t
     p->lds = lds_max;     // the rest holds conductance columns
     p->wstride = ws_doubles(max_ld, K);
     p->gstride = gstride;
+    p->astride = (int64_t)NVAR * max_ld;
     p->fn = adj_fn(bs, gen);
+    p->fn_con = contract_fn(bs);
     return PSST_OK;
 }
 
-// The adjoint kernel (or, without steps, zeroed accumulators) and the
-// finalize kernel, all on stream, with the given workspace, accumulators and
-// per-instance gradient offsets (device).
+// The adjoint of one call, all on stream: per segment, last to first, the
+// forward kernels' recomputation of the segment (stage records into ws),
+// the reverse sweep over it and the contraction of its records into the
+// accumulators; then the finalize kernel.  Without steps the accumulators
+// are zeroed.  ws, gacc, goff (per-instance gradient offsets) and astate
+// (carried lam) are device buffers sized by the plan.
 static psst_status adjoint_launch(const AdjPlan &P, int32_t n, const InstDesc *d_desc, int64_t nt,
-                                  double *ws, float *gacc, const int64_t *goff,
-                                  const float *ckpt, int32_t K, const psst_stimulus *stim,
-                                  float dt, int64_t n_steps, int64_t step0, const float *dLdV,
-                                  float *grad_g, float *gna, float *gk, float *gl,
-                                  int32_t per_instance, int32_t *flag, const Tab &tab,
-                                  hipStream_t st)
+                                  double *ws, float *gacc, const int64_t *goff, double *astate,
+                                  const RecomputeFn &recompute, const float *ckpt, int32_t K,
+                                  const psst_stimulus *stim, float dt, int64_t n_steps,
+                                  int64_t step0, const float *dLdV, float *grad_g, float *gna,
+                                  float *gk, float *gl, int32_t per_instance, int32_t *flag,
+                                  const Tab &tab, hipStream_t st)
 {
-    if (P.lds > 65536)
+    if (P.lds > 65536) {
         HIPCHK(hipFuncSetAttribute(P.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds));
+        HIPCHK(hipFuncSetAttribute(P.fn_con, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)P.lds));
+    }
     AdjArgs a{};
     a.desc = d_desc;
     a.ckpt = ckpt;
@@ -864,13 +839,24 @@ static psst_status adjoint_launch(const AdjPlan &P, int32_t n, const InstDesc *d
     a.lds_bytes = (int64_t)P.lds;
     a.flag = flag;
     a.tab = tab;
-    // PSST_ADJ_MODE=lacc keeps dL/dg in the per-step LDS accumulator even when
-    // the matrix-core contraction is possible (comparison runs)
-    if (const char *e = std::getenv("PSST_ADJ_MODE"))
-        a.mode = std::strcmp(e, "lacc") == 0 ? 1 : (std::strcmp(e, "mma") == 0 ? 2 : 0);
+    a.adj_state = astate;
+    a.adj_stride = P.astride;
+    // PSST_ADJ_MODE=lacc keeps dL/dg in the per-step LDS accumulator where it
+    // fits (comparison runs)
+    if (const char *e = std::getenv("PSST_ADJ_MODE")) a.mode = std::strcmp(e, "lacc") == 0 ? 1 : 0;
     if (n_steps > 0) {
-        void *args[] = {&a};
-        HIPCHK(hipLaunchKernel(P.fn, dim3(n), dim3(P.bs), args, P.lds, st));
+        const int64_t nseg = (n_steps + K - 1) / K;
+        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+            const int64_t s0 = seg * K;
+            const int64_t L = std::min<int64_t>(K, n_steps - s0);
+            psst_status s = recompute(ckpt + seg * 14 * nt, step0 + s0, L, ws, P.wstride, K, st);
+            if (s != PSST_OK) return s;
+            a.seg = seg;
+            a.first = seg == nseg - 1;
+            void *args[] = {&a};
+            HIPCHK(hipLaunchKernel(P.fn, dim3(n), dim3(P.bs), args, P.lds, st));
+            HIPCHK(hipLaunchKernel(P.fn_con, dim3(n), dim3(P.bs), args, P.lds, st));
+        }
     } else {
         const int64_t cnt = P.gstride * n;
         const unsigned blocks = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
@@ -895,7 +881,7 @@ static psst_status adjoint_launch(const AdjPlan &P, int32_t n, const InstDesc *d
 }
 
 psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
-                        int64_t nt, const std::vector<int64_t> &offsets, AdjWork **work,
+                        int64_t nt, AdjWork **work, const RecomputeFn &recompute,
                         const float *ckpt, int32_t K, const psst_stimulus *stim, float dt,
                         int64_t n_steps, int64_t step0, const float *dLdV, float *grad_g,
                         float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
@@ -911,13 +897,16 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
         return s;
     if ((s = ensure((void **)&W->gacc, &W->gacc_bytes, sizeof(float) * P.gstride * n)) != PSST_OK)
         return s;
+    if ((s = ensure((void **)&W->astate, &W->astate_bytes, sizeof(double) * P.astride * n)) !=
+        PSST_OK)
+        return s;
     if (!W->goff) HIPCHK(hipMalloc(&W->goff, sizeof(int64_t) * n));
     hipStream_t st = (hipStream_t)stream;
     grad_offsets_kernel<<<dim3(1), dim3(256), 0, st>>>(d_desc, n, W->goff);
     HIPCHK(hipGetLastError());
-    (void)offsets;
-    return adjoint_launch(P, n, d_desc, nt, W->ws, W->gacc, W->goff, ckpt, K, stim, dt, n_steps,
-                          step0, dLdV, grad_g, gna, gk, gl, per_instance, flag, tab, st);
+    return adjoint_launch(P, n, d_desc, nt, W->ws, W->gacc, W->goff, W->astate, recompute, ckpt,
+                          K, stim, dt, n_steps, step0, dLdV, grad_g, gna, gk, gl, per_instance,
+                          flag, tab, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -958,8 +947,8 @@ static psst_status scratch_on_device(void **out)
 static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
 psst_status adjoint_run_noalloc(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
-                                int64_t nt, const float *ckpt, int32_t K,
-                                const psst_stimulus *stim, float dt, int64_t n_steps,
+                                int64_t nt, const RecomputeFn &recompute, const float *ckpt,
+                                int32_t K, const psst_stimulus *stim, float dt, int64_t n_steps,
                                 int64_t step0, const float *dLdV, float *grad_g, float *gna,
                                 float *gk, float *gl, int32_t per_instance, int32_t *flag,
                                 size_t lds_max, bool gen, const Tab &tab, void *stream)
@@ -970,25 +959,28 @@ psst_status adjoint_run_noalloc(const std::vector<psst_network *> &nets, const I
     if (s != PSST_OK) return s;
     const int64_t ws_b = align256((int64_t)sizeof(double) * P.wstride * n);
     const int64_t ga_b = align256((int64_t)sizeof(float) * P.gstride * n);
+    const int64_t as_b = align256((int64_t)sizeof(double) * P.astride * n);
     const int64_t go_b = align256((int64_t)sizeof(int64_t) * n);
-    if (ws_b + ga_b + go_b > kAdjScratchBytes)
+    if (ws_b + ga_b + as_b + go_b > kAdjScratchBytes)
         return fail(PSST_ERR_INVALID_ARGUMENT,
                     "psst_adjoint_noalloc needs %lld bytes of scratch (stage records %lld, "
-                    "accumulators %lld, offsets %lld) for %d instances at K=%d; its maximum is "
-                    "%lld: use a smaller K or fewer instances, or psst_adjoint",
-                    (long long)(ws_b + ga_b + go_b), (long long)ws_b, (long long)ga_b,
-                    (long long)go_b, n, K, (long long)kAdjScratchBytes);
+                    "accumulators %lld, carried state %lld, offsets %lld) for %d instances at "
+                    "K=%d; its maximum is %lld: use a smaller K or fewer instances, or "
+                    "psst_adjoint",
+                    (long long)(ws_b + ga_b + as_b + go_b), (long long)ws_b, (long long)ga_b,
+                    (long long)as_b, (long long)go_b, n, K, (long long)kAdjScratchBytes);
     void *base = nullptr;
     if ((s = scratch_on_device(&base)) != PSST_OK) return s;
     unsigned char *b8 = static_cast<unsigned char *>(base);
     double *ws = reinterpret_cast<double *>(b8);
     float *gacc = reinterpret_cast<float *>(b8 + ws_b);
-    int64_t *goff = reinterpret_cast<int64_t *>(b8 + ws_b + ga_b);
+    double *astate = reinterpret_cast<double *>(b8 + ws_b + ga_b);
+    int64_t *goff = reinterpret_cast<int64_t *>(b8 + ws_b + ga_b + as_b);
     hipStream_t st = (hipStream_t)stream;
     grad_offsets_kernel<<<dim3(1), dim3(256), 0, st>>>(d_desc, n, goff);
     HIPCHK(hipGetLastError());
-    return adjoint_launch(P, n, d_desc, nt, ws, gacc, goff, ckpt, K, stim, dt, n_steps, step0,
-                          dLdV, grad_g, gna, gk, gl, per_instance, flag, tab, st);
+    return adjoint_launch(P, n, d_desc, nt, ws, gacc, goff, astate, recompute, ckpt, K, stim, dt,
+                          n_steps, step0, dLdV, grad_g, gna, gk, gl, per_instance, flag, tab, st);
 }
 
 void adjoint_free(AdjWork *w)
@@ -997,5 +989,6 @@ void adjoint_free(AdjWork *w)
     (void)hipFree(w->ws);
     (void)hipFree(w->gacc);
     (void)hipFree(w->goff);
+    (void)hipFree(w->astate);
     delete w;
 }

@@ -153,6 +153,20 @@ __device__ inline double release(double V, double vp, double kp)
     return 1.0 / (1.0 + exp(-(V - vp) / kp));
 }
 
+// Release of a neuron's own transmitter (cholinergic for PN, fast GABA for
+// LN rows) and, for LN rows with slow GABA, the slow-GABA release: one
+// release evaluation each, the second reusing the first when the two share
+// V_p and K_p (the same function of the same arguments, so the same value).
+__device__ inline void releases(double V, const Kin &K, bool is_ln, bool slow, double &T,
+                                double &TB)
+{
+    const double vp = is_ln ? K.vp_ga : K.vp_ach;
+    const double kp = is_ln ? K.kp_ga : K.kp_ach;
+    T = release(V, vp, kp);
+    TB = T;
+    if (slow && !(K.vp_gb == vp && K.kp_gb == kp)) TB = release(V, K.vp_gb, K.kp_gb);
+}
+
 __device__ inline double ipow(double x, int n)
 {
     double p = 1.0;
@@ -192,10 +206,10 @@ __device__ inline void hh_rhs(const double Y[NVAR], const Prm &P, const Kin &K,
     f[YN] = r.an * (1.0 - n) - r.bn * n;
     const double a = is_ln ? K.a_ga : K.a_ach;
     const double b = is_ln ? K.b_ga : K.b_ach;
-    const double T = is_ln ? release(V, K.vp_ga, K.kp_ga) : release(V, K.vp_ach, K.kp_ach);
+    double T, TB;
+    releases(V, K, is_ln, is_ln && gabab, T, TB);
     f[YS] = a * T * (1.0 - s) - b * s;
     if (is_ln && gabab) {
-        const double TB = release(V, K.vp_gb, K.kp_gb);
         f[YR] = K.r1 * TB * (1.0 - Y[YR]) - K.r2 * Y[YR];
         f[YG] = K.r3 * Y[YR] - K.r4 * Y[YG];
     } else {
@@ -235,11 +249,11 @@ __device__ inline void hh_vjp(const double Y[NVAR], const Prm &P, const Kin &K, 
     const double al = is_ln ? K.a_ga : K.a_ach;
     const double be = is_ln ? K.b_ga : K.b_ach;
     const double kp = is_ln ? K.kp_ga : K.kp_ach;
-    const double T = is_ln ? release(V, K.vp_ga, K.kp_ga) : release(V, K.vp_ach, K.kp_ach);
+    double T, TB;
+    releases(V, K, is_ln, is_ln && gabab, T, TB);
     uV += w[YS] * al * (T * (1.0 - T) / kp) * (1.0 - s);
     u[YS] = -w[YS] * (al * T + be);
     if (is_ln && gabab) {
-        const double TB = release(V, K.vp_gb, K.kp_gb);
         const double rr = Y[YR];
         uV += w[YR] * K.r1 * (TB * (1.0 - TB) / K.kp_gb) * (1.0 - rr);
         u[YR] = -w[YR] * (K.r1 * TB + K.r2) + w[YG] * K.r3;

@@ -48,6 +48,17 @@ struct WGArgs {
                                 // conductances fit keep them in LDS
     int32_t *flag;              // set to 1 when a state turns non-finite
     Tab tab;                    // method of the generic-step variants
+    // recomputation for the adjoint: the initial state comes from state_in
+    // (when not null) and is not stored back when store_state is 0; each
+    // step's stage inputs and synaptic sums go to stash (when not null):
+    // instance b's block at stash + b * stash_stride, laid out as the
+    // adjoint's workspace (stage inputs [stash_K][4][NVAR][ld], then sums
+    // [stash_K][4][3][ld], ld the instance's padded size)
+    const float *state_in;
+    int32_t store_state;
+    double *stash;
+    int64_t stash_stride;
+    int32_t stash_K;
 };
 
 typedef void (*wg_kernel_t)(WGArgs);
@@ -102,10 +113,12 @@ inline size_t wg_lds_bytes(bool glds, int ld, int n_chunks, int64_t g_floats)
 
 // Lane-group kernel (256 threads): networks of at most kLGRows neurons with
 // dense storage and at most 4 column chunks keep every conductance in
-// registers, two (chunk, row) pairs of 64 columns per lane; the LDS holds
-// only the activations, in one slot of kLGSlot doubles per chunk (64 used;
-// the 2 extra stagger the slots' LDS banks), two sets alternating by stage.
+// registers, two (chunk, row) pairs of 64 columns per lane (the variant's
+// "neurons per thread" field holds that count); the LDS holds only the
+// activations, in one slot of kLGSlot doubles per chunk (64 used; the 2 extra
+// stagger the slots' LDS banks), two sets alternating by stage.
 constexpr int kLGRows = 128;
+constexpr int kLGPairs = 2;
 constexpr int kLGSlot = 66;
 constexpr int kLGThreads = 256;
 constexpr int64_t kLGLdsBytes = (int64_t)sizeof(double) * 2 * 4 * kLGSlot;

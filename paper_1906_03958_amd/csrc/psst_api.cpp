@@ -565,7 +565,7 @@ extern "C" psst_status psst_integrate(psst_network *net, float *state, const pss
     const bool lg = net_lg(net) && !std::getenv("PSST_WG_SHAPE");
     if (lg) {
         bs = kLGThreads;
-        npt = 1;
+        npt = kLGPairs;
     }
     // a network whose whole conductance matrix stays in LDS sums one (chunk,
     // row) pair per thread: enough threads for every pair in one pass (up to
@@ -617,6 +617,7 @@ extern "C" psst_status psst_integrate(psst_network *net, float *state, const pss
     a.lds_bytes = (int64_t)lds;
     a.flag = net->d_flag;
     a.tab = net->tab;
+    a.store_state = 1;
     void *args[] = {&a};
     HIPCHK(hipLaunchKernel(v->fn, dim3(1), dim3(bs), args, lds, (hipStream_t)stream));
     return PSST_OK;
@@ -678,6 +679,7 @@ static WGArgs group_args(psst_batch *b, const Group &g, float *states, const pss
     a.lds_bytes = (int64_t)g.lds;
     a.flag = b->d_flag;
     a.tab = b->tab;
+    a.store_state = 1;
     return a;
 }
 
@@ -853,7 +855,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     g.lds = (allow_lds && any_syn) ? lmax : need;
     default_shape(g.max_n, &g.bs, &g.npt);
     gl.bs = kLGThreads;
-    gl.npt = 1;
+    gl.npt = kLGPairs;
     gl.lds = (size_t)kLGLdsBytes;
     // PSST_WG_SHAPE="<threads>x<neurons per thread>" fixes the launch shape
     // (and skips tuning) when that variant can take every instance.
@@ -1116,6 +1118,27 @@ extern "C" psst_status psst_batch_poll(psst_batch *b, void *stream)
     return poll_flag(b->d_flag, stream);
 }
 
+// The forward kernels of a batch as the adjoint's recomputation: each launch
+// group over n_steps steps from the checkpoint row, nothing stored back,
+// stage records to the stash.
+static RecomputeFn batch_recompute(psst_batch *b, const psst_stimulus *stim, float dt)
+{
+    return [b, stim, dt](const float *ckpt_row, int64_t step0, int64_t n_steps, double *stash,
+                         int64_t stash_stride, int32_t K, hipStream_t s) -> psst_status {
+        for (const Group &g : b->groups) {
+            WGArgs a = group_args(b, g, nullptr, stim, dt, n_steps, step0, nullptr, nullptr, 1);
+            a.state_in = ckpt_row;
+            a.store_state = 0;
+            a.stash = stash;
+            a.stash_stride = stash_stride;
+            a.stash_K = K;
+            psst_status st = launch_group(g, b->gen, a, s);
+            if (st != PSST_OK) return st;
+        }
+        return PSST_OK;
+    };
+}
+
 extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
                                     const psst_stimulus *stim, float dt, int64_t n_steps,
                                     int64_t step0, const float *dLdV, float *grad_g,
@@ -1133,7 +1156,8 @@ extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
         return fail(PSST_ERR_INVALID_ARGUMENT, "summed gradients need every instance to share one network");
     if (b->stage_path)
         return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available on the per-stage path");
-    return adjoint_run(b->nets, b->d_desc, b->nt, b->offsets, &b->adj, ckpt, K, stim, dt, n_steps,
+    return adjoint_run(b->nets, b->d_desc, b->nt, &b->adj, batch_recompute(b, stim, dt), ckpt, K,
+                       stim, dt, n_steps,
                        step0, dLdV, grad_g, grad_gNa, grad_gK, grad_gL, per_instance, b->d_flag,
                        max_lds_per_block(), b->gen, b->tab, stream);
 }
@@ -1155,7 +1179,8 @@ extern "C" psst_status psst_adjoint_noalloc(psst_batch *b, const float *ckpt, in
         return fail(PSST_ERR_INVALID_ARGUMENT, "summed gradients need every instance to share one network");
     if (b->stage_path)
         return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available on the per-stage path");
-    return adjoint_run_noalloc(b->nets, b->d_desc, b->nt, ckpt, K, stim, dt, n_steps, step0, dLdV,
+    return adjoint_run_noalloc(b->nets, b->d_desc, b->nt, batch_recompute(b, stim, dt), ckpt, K,
+                               stim, dt, n_steps, step0, dLdV,
                                grad_g, grad_gNa, grad_gK, grad_gL, per_instance, b->d_flag,
                                max_lds_per_block(), b->gen, b->tab, stream);
 }

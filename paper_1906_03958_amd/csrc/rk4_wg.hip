@@ -42,21 +42,25 @@ __device__ __forceinline__ void integrate_loop(const WGArgs &a, const InstDesc &
 {
     const int n = d.n, ld = d.ld;
     const int64_t NT = a.nt;
+    const float *sin = a.state_in ? a.state_in : a.state;
     bool own[NPT];
     double y[NPT][NVAR];
     float pr[NPT][NPRM];
     double Ic[NPT];       // constant injected current, nA
     int32_t p0[NPT], p1[NPT];
     int32_t nspk[NPT];
+    StimCache sc[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
+        sc[k].I = 0.0;
+        sc[k].next = -1;
         const int i = nid(k);
         own[k] = own_of(k);
         const int ic = (own[k] && i < n) ? i : 0;
         const int64_t gi = d.off + ic;
 #pragma unroll
         for (int v = 0; v < NVAR; ++v)
-            y[k][v] = (double)a.state[(2 * v) * NT + gi] + (double)a.state[(2 * v + 1) * NT + gi];
+            y[k][v] = (double)sin[(2 * v) * NT + gi] + (double)sin[(2 * v + 1) * NT + gi];
 #pragma unroll
         for (int p = 0; p < NPRM; ++p) pr[k][p] = d.prm[p * ld + ic];
         Ic[k] = a.stim.i_const ? (double)a.stim.i_const[gi] : 0.0;
@@ -94,10 +98,17 @@ __device__ __forceinline__ void integrate_loop(const WGArgs &a, const InstDesc &
         double Iu[NPT], vold[NPT];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            Iu[k] = d.ci * stim_nA(a.stim, Ic[k], p0[k], p1[k], g);
+            Iu[k] = d.ci * stim_nA_cached(a.stim, Ic[k], p0[k], p1[k], g, sc[k]);
             vold[k] = y[k][YV];
         }
-        step(pr, Iu, y);
+        StageStash stash;
+        if (a.stash) {
+            double *base = a.stash + (int64_t)a.order[blockIdx.x] * a.stash_stride;
+            stash.sY = base + st * 4 * NVAR * ld;
+            stash.sS = base + (int64_t)a.stash_K * 4 * NVAR * ld + st * 12 * ld;
+            stash.ld = ld;
+        }
+        step(pr, Iu, y, a.stash ? &stash : nullptr);
         // spikes, records
         const bool do_rec = (g + 1 == next_rec);
 #pragma unroll
@@ -127,37 +138,55 @@ __device__ __forceinline__ void integrate_loop(const WGArgs &a, const InstDesc &
     for (int k = 0; k < NPT; ++k) {
         if (!own[k]) continue;
         const int64_t gi = d.off + nid(k);
+        if (a.store_state) {
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
-            float hi, lo;
-            split_store(y[k][v], hi, lo);
-            a.state[(2 * v) * NT + gi] = hi;
-            a.state[(2 * v + 1) * NT + gi] = lo;
+            for (int v = 0; v < NVAR; ++v) {
+                float hi, lo;
+                split_store(y[k][v], hi, lo);
+                a.state[(2 * v) * NT + gi] = hi;
+                a.state[(2 * v + 1) * NT + gi] = lo;
+            }
         }
         if (a.rec.spike_count) a.rec.spike_count[gi] = nspk[k];
     }
     if (bad) atomicOr(a.flag, 1);
 }
 
+// A double moved between the lanes of each quad (four consecutive lanes):
+// lane q of the quad receives the value of lane (q + D) mod 4 (DPP quad
+// permutation, no LDS traffic).
+template <int D>
+__device__ __forceinline__ double quad_rotate(double v)
+{
+    constexpr int ctrl = ((0 + D) & 3) | (((1 + D) & 3) << 2) | (((2 + D) & 3) << 4) |
+                         (((3 + D) & 3) << 6);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), ctrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Lane-group mapping (small dense networks, kLGThreads = 256 threads, one
 // wavefront per SIMD so that a lane has room for its conductances): lane
-// 16 c + r of wavefront w takes the pairs (chunk c, row i_k = 64 k + 16 w +
-// r), k = 0, 1, and keeps their 64 conductances each in registers for the
-// whole launch (zeros past the chunk's last column); lane 16 k + r (k = 0, 1)
-// owns neuron i_k.  Per stage the owners write their activations into the
-// chunk slots of one of two LDS slot sets (alternating by stage, so a
-// wavefront that runs ahead writes the other set), one barrier, each lane
+// 4 r + c of wavefront w takes the pairs (chunk c, row i_k = 64 k + 16 w +
+// r), k < RPL row blocks, and keeps their 64 conductances each in registers
+// for the whole launch (zeros past the chunk's last column); lane 4 r + k
+// owns neuron i_k (k < RPL).  Per stage the owners write their activations
+// into the chunk slots of one of two LDS slot sets (alternating by stage, so
+// a wavefront that runs ahead writes the other set), one barrier, each lane
 // sums its pairs in column order -- the fma sequence of every other mapping,
-// the zero columns adding exact zeros -- and each owner gathers its row's
-// chunk partials from the four lanes r, 16 + r, 32 + r, 48 + r by shuffles
-// and adds them in chunk order, per synapse class.
-template <bool GEN>
+// the zero columns adding exact zeros -- and each owner collects its row's
+// partials from the other lanes of its quad (three quad permutations: at
+// distance d the source lane offers the partial of row block (c' - d) mod 4)
+// and adds them in chunk order, per synapse class.  An LN owner of a network
+// with slow GABA forms the next stage's slow activation as soon as the stage
+// update has its input, beside the rest of the right-hand side.
+template <bool GEN, int RPL>
 __device__ __forceinline__ void lg_integrate(const WGArgs &a, const InstDesc &d, double *lds)
 {
-    constexpr int RPL = kLGRows / (kLGThreads / 4);     // pairs (rows) per lane
-    static_assert(RPL == 2, "row blocks 0 and 1 are owned by lane groups 0 and 1");
+    static_assert(RPL >= 1 && RPL <= 4, "row blocks are owned by quad lanes 0 .. RPL-1");
     const int tid = threadIdx.x, lane = tid & 63;
-    const int cl = lane >> 4, r = lane & 15;
+    const int cl = lane & 3, r = lane >> 2;
     const int row0 = (tid >> 6) * 16 + r;
     const int n = d.n, n_pn = d.n_pn, ld = d.ld;
     const bool gabab = (d.flags & DESC_GABAB) != 0;
@@ -183,8 +212,11 @@ __device__ __forceinline__ void lg_integrate(const WGArgs &a, const InstDesc &d,
             g[k][u] = (pair && u < wc) ? v : 0.f;
         }
     }
-    const int me = row0 + 64 * (cl & 1);  // the neuron this lane owns when cl < 2
-    const bool owner = cl < 2 && me < n;
+    const int me = row0 + 64 * cl;        // the neuron this lane owns when cl < RPL
+    const bool owner = cl < RPL && me < n;
+    const bool slow_owner = owner && gabab && me >= n_pn;
+    double xb_next = 0.0;                 // slow activation of the next stage input
+    bool xb_ready = false;
     // both slot sets start at zero: columns past a chunk's end stay 0
     for (int e = tid; e < 2 * 4 * kLGSlot; e += kLGThreads) lds[e] = 0.0;
     __syncthreads();
@@ -198,9 +230,11 @@ __device__ __forceinline__ void lg_integrate(const WGArgs &a, const InstDesc &d,
             const int c = ln ? ch.na + (me - n_pn) / CW : me / CW;
             const int u = ln ? (me - n_pn) % CW : me % CW;
             S[c * kLGSlot + u] = Y[0][YS];
-            if (gabab && ln)
-                S[(ch.na + ch.ng + (me - n_pn) / CW) * kLGSlot + u] = gabab_act(Y[0][YG], K);
+            if (slow_owner)
+                S[(ch.na + ch.ng + (me - n_pn) / CW) * kLGSlot + u] =
+                    xb_ready ? xb_next : gabab_act(Y[0][YG], K);
         }
+        xb_ready = false;
         __syncthreads();
         double p[RPL];
 #pragma unroll
@@ -220,34 +254,54 @@ __device__ __forceinline__ void lg_integrate(const WGArgs &a, const InstDesc &d,
                 }
             }
         }
-        double pc[4];
+        // pd[dd] = partial of chunk (cl + dd) mod 4 for this lane's row block cl:
+        // the quad lane dd places further offers its partial of row block
+        // (its c - dd) mod 4
+        double offer[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double a0 = __shfl(p[0], 16 * c + r), a1 = __shfl(p[1], 16 * c + r);
-            pc[c] = (cl & 1) ? a1 : a0;
+        for (int dd = 0; dd < 4; ++dd) {
+            const int kk = (cl - dd) & 3;
+            double o = 0.0;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) o = kk == k ? p[k] : o;
+            offer[dd] = o;
         }
+        const double pd[4] = {offer[0], quad_rotate<1>(offer[1]), quad_rotate<2>(offer[2]),
+                              quad_rotate<3>(offer[3])};
         double ta = 0.0, tg = 0.0, tb = 0.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            if (c < ch.na) ta += pc[c];
-            else if (c < ch.na + ch.ng) tg += pc[c];
-            else if (c < nch) tb += pc[c];
+            const int dd = (c - cl) & 3;
+            double v = pd[0];
+#pragma unroll
+            for (int e = 1; e < 4; ++e) v = dd == e ? pd[e] : v;
+            if (c < ch.na) ta += v;
+            else if (c < ch.na + ch.ng) tg += v;
+            else if (c < nch) tb += v;
         }
         sa[0] = ta;
         sg[0] = tg;
         sb[0] = tb;
+    };
+    auto post = [&](int, const double (&Yn)[NVAR]) {
+        if (slow_owner) {
+            xb_next = gabab_act(Yn[YG], K);
+            xb_ready = true;
+        }
     };
     const Slots sl{n, n_pn, gabab};
     auto nid = [&](int) { return me; };
     auto own = [&](int) { return owner; };
     const double dt = a.dt;
     integrate_loop<1>(a, d, nid, own,
-                      [&](const float (&pr)[1][NPRM], const double (&Iu)[1], double (&y)[1][NVAR]) {
+                      [&](const float (&pr)[1][NPRM], const double (&Iu)[1], double (&y)[1][NVAR],
+                          const StageStash *stash) {
                           if constexpr (GEN)
                               rk_step_core_tab<1>(sl, syn, nid, own, K, d.cg, pr, Iu, dt, y,
-                                                  nullptr, a.tab);
+                                                  stash, a.tab, post);
                           else
-                              rk4_step_core<1>(sl, syn, nid, own, K, d.cg, pr, Iu, dt, y, nullptr);
+                              rk4_step_core<1>(sl, syn, nid, own, K, d.cg, pr, Iu, dt, y, stash,
+                                               post);
                       });
 }
 
@@ -263,24 +317,25 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
     const double dt = a.dt;
     integrate_loop<NPT>(
         a, d, [&](int k) { return tid + k * BS; }, [&](int k) { return tid + k * BS < d.n; },
-        [&](const float (&pr)[NPT][NPRM], const double (&Iu)[NPT], double (&y)[NPT][NVAR]) {
+        [&](const float (&pr)[NPT][NPRM], const double (&Iu)[NPT], double (&y)[NPT][NVAR],
+            const StageStash *stash) {
             if constexpr (GEN)
-                rk_step_wg_tab<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr, a.tab);
+                rk_step_wg_tab<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, stash, a.tab);
             else
-                rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, nullptr);
+                rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, stash);
         });
 }
 
 // The lane-group mapping as a kernel of its own (its registers hold the
 // conductances; the other mappings' register budget stays unchanged): every
 // instance of the launch must be eligible.
-template <bool GEN>
+template <bool GEN, int RPL>
 __global__ __launch_bounds__(kLGThreads) void rk4_lg_kernel(WGArgs a)
 {
     extern __shared__ double lds_d[];
     const int32_t b = a.order[blockIdx.x];
     const InstDesc d = a.desc[b];
-    lg_integrate<GEN>(a, d, lds_d);
+    lg_integrate<GEN, RPL>(a, d, lds_d);
 }
 
 // Initial state: V = v0, gates at steady state, synaptic variables 0.
@@ -309,8 +364,8 @@ __global__ __launch_bounds__(256) void init_state_kernel(InitArgs a)
 static const WGVariant kVariants[] = {
     WGV(64, 1), WGV(128, 1), WGV(128, 2), WGV(256, 1), WGV(256, 2), WGV(256, 4), WGV(512, 1),
     WGG(64, 1), WGG(128, 1), WGG(128, 2), WGG(256, 1), WGG(256, 2), WGG(256, 4), WGG(512, 1),
-    {kLGThreads, 1, false, true, (const void *)rk4_lg_kernel<false>},
-    {kLGThreads, 1, true, true, (const void *)rk4_lg_kernel<true>},
+    {kLGThreads, 2, false, true, (const void *)rk4_lg_kernel<false, 2>},
+    {kLGThreads, 2, true, true, (const void *)rk4_lg_kernel<true, 2>},
     {0, 0, false, false, nullptr},
 };
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -110,9 +111,18 @@ psst_status batch_launch_direct(psst_batch *b, float *states, const psst_stimulu
                                 int64_t n_steps, int64_t step0, const psst_record *rec,
                                 void *stream);
 
+// Forward recomputation for the adjoint: n_steps steps of every instance of a
+// batch from global step step0, the state read from ckpt_row (not stored
+// back), each step's stage inputs and synaptic sums written to stash
+// (instance b at stash + b * stash_stride, K steps per block).
+typedef std::function<psst_status(const float *ckpt_row, int64_t step0, int64_t n_steps,
+                                  double *stash, int64_t stash_stride, int32_t K,
+                                  hipStream_t stream)>
+    RecomputeFn;
+
 // Discrete adjoint over a batch of per-instance networks (adjoint.hip).
 psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
-                        int64_t nt, const std::vector<int64_t> &offsets, AdjWork **work,
+                        int64_t nt, AdjWork **work, const RecomputeFn &recompute,
                         const float *ckpt, int32_t K, const psst_stimulus *stim, float dt,
                         int64_t n_steps, int64_t step0, const float *dLdV, float *grad_g,
                         float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
@@ -121,8 +131,8 @@ void adjoint_free(AdjWork *w);
 // The same with the workspace in the library's per-device scratch array
 // (no allocation); sizes beyond its capacity are refused.
 psst_status adjoint_run_noalloc(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
-                                int64_t nt, const float *ckpt, int32_t K,
-                                const psst_stimulus *stim, float dt, int64_t n_steps,
+                                int64_t nt, const RecomputeFn &recompute, const float *ckpt,
+                                int32_t K, const psst_stimulus *stim, float dt, int64_t n_steps,
                                 int64_t step0, const float *dLdV, float *grad_g, float *gna,
                                 float *gk, float *gl, int32_t per_instance, int32_t *flag,
                                 size_t lds_max, bool gen, const psst::Tab &tab, void *stream);

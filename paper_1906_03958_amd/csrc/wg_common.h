@@ -188,6 +188,34 @@ __device__ __forceinline__ double stim_nA(const StimDev &s, double Ic, int32_t p
     return I;
 }
 
+// The same current for steps taken in increasing order: the set of pulses
+// that are on changes only at a pulse's on or off step, so the sum (formed as
+// stim_nA forms it, in pulse order) is kept with the first step at which the
+// set changes next, and the pulse table is read again only there.  Start
+// with next = -1.
+struct StimCache {
+    double I;
+    int64_t next;
+};
+
+__device__ __forceinline__ double stim_nA_cached(const StimDev &s, double Ic, int32_t p0,
+                                                 int32_t p1, int64_t g, StimCache &c)
+{
+    if (g >= c.next) {
+        double I = Ic;
+        int64_t nx = INT64_MAX;
+        for (int p = p0; p < p1; ++p) {
+            const int64_t on = s.on_step[p], off = s.off_step[p];
+            if (on <= g && g < off) I += (double)s.amp[p];
+            if (on > g) nx = min(nx, on);
+            else if (off > g) nx = min(nx, off);
+        }
+        c.I = I;
+        c.next = nx;
+    }
+    return c.I;
+}
+
 // Sum of the chunk partials c0 .. c1-1 of one row (stride ld), added in
 // chunk order starting from 0; loads go four at a time.
 __device__ __forceinline__ double chunk_total(lds_double *P, int ld, int c0, int c1)
@@ -377,12 +405,21 @@ struct Slots {
 
 // One RK4 step of the calling thread's neurons, y updated in place and
 // rounded to its stored float32 pair.  Iu: injected current (uA/cm^2).
-template <int NPT, typename Syn, typename Idx, typename Live>
+// post(k, Y) (optional) sees every slot's next stage input -- after each
+// stage's update, and the step's result after the combine -- in the basic
+// block that formed it, so work that only depends on it (the lane-group
+// kernel's slow-GABA activation) can overlap the right-hand side.
+struct NoPost {
+    __device__ void operator()(int, const double (&)[NVAR]) const {}
+};
+
+template <int NPT, typename Syn, typename Idx, typename Live, typename Post = NoPost>
 __device__ __forceinline__ void rk4_step_core(const Slots &sl, Syn &&syn, Idx &&idx, Live &&live,
                                               const Kin &K, double cgf,
                                               const float (&pr)[NPT][NPRM],
                                               const double (&Iu)[NPT], double dt,
-                                              double (&y)[NPT][NVAR], const StageStash *stash)
+                                              double (&y)[NPT][NVAR], const StageStash *stash,
+                                              Post &&post = Post())
 {
     double acc[NPT][NVAR];
     double Y[NPT][NVAR];
@@ -418,6 +455,7 @@ __device__ __forceinline__ void rk4_step_core(const Slots &sl, Syn &&syn, Idx &&
                 acc[k][v] += wq * f[v];
                 if (q < 3) Y[k][v] = y[k][v] + c * f[v];
             }
+            if (q < 3) post(k, Y[k]);
         }
     }
 #pragma unroll
@@ -428,6 +466,7 @@ __device__ __forceinline__ void rk4_step_core(const Slots &sl, Syn &&syn, Idx &&
             float hi, lo;
             y[k][v] = split_store(y[k][v] + (dt / 6.0) * acc[k][v], hi, lo);
         }
+        post(k, y[k]);
     }
 }
 
@@ -437,13 +476,13 @@ __device__ __forceinline__ void rk4_step_core(const Slots &sl, Syn &&syn, Idx &&
 // stored float32 pair.  The stage loop is unrolled so the earlier k stay in
 // registers; T.s is the same for the whole workgroup, so the barriers inside
 // the synaptic sums are reached by every thread.
-template <int NPT, typename Syn, typename Idx, typename Live>
+template <int NPT, typename Syn, typename Idx, typename Live, typename Post = NoPost>
 __device__ __forceinline__ void rk_step_core_tab(const Slots &sl, Syn &&syn, Idx &&idx,
                                                  Live &&live, const Kin &K, double cgf,
                                                  const float (&pr)[NPT][NPRM],
                                                  const double (&Iu)[NPT], double dt,
                                                  double (&y)[NPT][NVAR], const StageStash *stash,
-                                                 const Tab &T)
+                                                 const Tab &T, Post &&post = Post())
 {
     double inc[NPT][NVAR];
     double kq[3][NPT][NVAR];
@@ -468,6 +507,9 @@ __device__ __forceinline__ void rk_step_core_tab(const Slots &sl, Syn &&syn, Idx
                     for (int r = 0; r < q; ++r) acc += T.a[q][r] * kq[r][k][v];
                     Y[k][v] = y[k][v] + dt * acc;
                 }
+#pragma unroll
+            for (int k = 0; k < NPT; ++k)
+                if (live(k)) post(k, Y[k]);
         }
         double sa[NPT], sg[NPT], sb[NPT];
         syn(Y, sa, sg, sb);
@@ -500,6 +542,7 @@ __device__ __forceinline__ void rk_step_core_tab(const Slots &sl, Syn &&syn, Idx
             float hi, lo;
             y[k][v] = split_store(y[k][v] + dt * inc[k][v], hi, lo);
         }
+        post(k, y[k]);
     }
 }
 
