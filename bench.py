@@ -50,10 +50,16 @@ def _counter_rows(path, kernel_substr, counter):
 # the sources each profiled kernel is compiled from: a counter figure is used
 # only while they are unchanged
 KERNEL_SOURCES = {
+    # the batched launch: the LDS-resident kernel and the lane-group kernel
     "rk4_wg_kernel": ("rk4_wg.hip", "wg_common.h", "hh_device.h", "kernels.h"),
     "stage_kernel": ("stage.hip", "stage.h", "hh_device.h"),
-    "adjoint_wg_kernel": ("adjoint.hip", "wg_common.h", "hh_device.h", "kernels.h"),
+    # one psst_adjoint call: the forward kernels' recomputation, the reverse
+    # sweep and the contraction, per segment
+    "adjoint": ("adjoint.hip", "rk4_wg.hip", "wg_common.h", "hh_device.h", "kernels.h"),
 }
+# kernel-name substrings whose dispatches make up one launch of each entry
+KERNEL_NAMES = {"rk4_wg_kernel": ("rk4_wg_kernel", "rk4_lg_kernel"),
+                "stage_kernel": ("stage_kernel",)}
 
 
 def kernel_sha(kernel):
@@ -98,10 +104,17 @@ def write_traffic(args):
     cw = [v for _, v in _counter_rows(cw_csv, "copyBuffer", "WRITE_SIZE")]
     kf = float(ref) / (1024.0 * float(np.median(cf)))
     kw = float(ref) / (1024.0 * float(np.median(cw)))
-    f = _longest(_counter_rows(f_csv, kernel, "FETCH_SIZE"))
-    w = _longest(_counter_rows(w_csv, kernel, "WRITE_SIZE"))
-    fetch = float(np.mean(f)) * 1024 * kf
-    write = float(np.mean(w)) * 1024 * kw
+    # a launch's bytes: for each kernel of the launch, the mean over its
+    # longest dispatches, summed over the kernels
+    fetch = write = 0.0
+    nf = 0
+    for kname in KERNEL_NAMES[kernel]:
+        f = _longest(_counter_rows(f_csv, kname, "FETCH_SIZE"))
+        w = _longest(_counter_rows(w_csv, kname, "WRITE_SIZE"))
+        fetch += float(np.mean(f)) * 1024 * kf
+        write += float(np.mean(w)) * 1024 * kw
+        nf = max(nf, len(f))
+    f = [None] * nf
     out = dict(kernel=kernel, kernel_source_sha=kernel_sha(kernel), **workload_key(args),
                fetch_bytes_per_launch=fetch, write_bytes_per_launch=write,
                hbm_bytes_per_launch=fetch + write, fetch_scale=kf, write_scale=kw,
@@ -134,6 +147,43 @@ def write_flops(args):
                fp64_flops_per_launch=total, counters=per,
                scale={c: FLOP_COUNTERS[c] for c in per})
     with open(os.path.join(ROOT, "profiles", f"{kernel}_{args.workload}_flops.txt"), "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out))
+
+
+def write_adjoint_flops(args):
+    """float64 flops of one psst_adjoint call of the adjoint workload from
+    rocprofv3 counter files of `bench.py --workload adjoint` runs: the VALU
+    counters (SQ_INSTS_VALU_FLOPS_FP64, _TRANS; x 64 lanes) and the
+    matrix-core counter (SQ_INSTS_VALU_MFMA_MOPS_F64; x 512) summed over the
+    reverse and contraction dispatches and over the forward kernels' short
+    recomputation dispatches (the long forward runs of the workload are left
+    out), divided by the number of adjoint calls (reverse dispatches / segments)."""
+    valu_csv, mfma_csv = args.write_adjoint_flops
+    segs = -(-args.adjoint_steps // args.adjoint_K)
+    per = {}
+    calls = None
+    for path, counters in ((valu_csv, ("SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP64_TRANS")),
+                           (mfma_csv, ("SQ_INSTS_VALU_MFMA_MOPS_F64",))):
+        for c in counters:
+            tot = 0.0
+            for kname in ("adjoint_reverse", "adjoint_contract"):
+                rows = _counter_rows(path, kname, c)
+                tot += sum(v for _, v in rows)
+                if kname == "adjoint_reverse" and rows:
+                    calls = len(rows) // segs
+            fwd = _counter_rows(path, "rk4_", c)
+            if fwd:
+                longest = max(d for d, _ in fwd)
+                tot += sum(v for d, v in fwd if d < 0.1 * longest)
+            per[c] = tot
+    total = sum(FLOP_COUNTERS[c] * v for c, v in per.items()) / calls
+    out = dict(kernel="adjoint", kernel_source_sha=kernel_sha("adjoint"),
+               **workload_key(args, "adjoint"), fp64_flops_per_launch=total,
+               counters_summed_over_calls=per, calls=calls,
+               scale={c: FLOP_COUNTERS[c] for c in per})
+    with open(os.path.join(ROOT, "profiles", "adjoint_adjoint_flops.txt"), "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps(out))
@@ -425,20 +475,24 @@ def bench_adjoint(args, torch, psst, W, dev, stream):
     # the recomputed forward's products (4 stages x 2 E) and the reverse
     # stages' transposed products and gradient outer products (4 x 4 E), E =
     # the n^2 entries of the dense matrix -- a lower bound on the work
-    fl = read_flops("adjoint_wg_kernel", args, "adjoint")
+    fl = read_flops("adjoint", args, "adjoint")
     syn = float(T) * B * (4 * 2 + 4 * 4) * n * n
     tf = fl / adj / 1e12 if fl else None
     res["roofline"] = {"bound": "alu", "achieved": round(tf, 3) if tf else None,
                        "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 4) if tf else None,
-                       "traffic": None, "kernel": "adjoint_wg_kernel",
+                       "traffic": None,
+                       "kernel": "one psst_adjoint call: per segment the forward kernels' "
+                                 "recomputation, adjoint_reverse_kernel, "
+                                 "adjoint_contract_kernel (float64 MFMA)",
                        "fp64_flops_per_launch": fl,
                        "synaptic_flops_per_launch": syn,
                        "synaptic_TFLOPs": round(syn / adj / 1e12, 3),
                        "us_per_reverse_step": round(1e6 * adj / T, 2),
                        "note": "peak: float64 vector rate (256 CUs x 128 flop/clk x 2.4 GHz); "
-                               "flops from SQ_INSTS_VALU_FLOPS_FP64(+_TRANS) x 64 and "
-                               "SQ_INSTS_VALU_MFMA_MOPS_F64 x 512"}
+                               "flops per call from SQ_INSTS_VALU_FLOPS_FP64(+_TRANS) x 64 and "
+                               "SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 over the call's kernels; "
+                               "achieved over the call's time"}
     log(f"adjoint: {res['adjoint_neuron_steps_per_s']:.3e} neuron-steps/s "
         f"({res['adjoint_s']:.2f} s for {T} steps; forward {res['forward_with_checkpoints_s']:.2f} s)")
     return res
@@ -470,6 +524,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float32 buffer 5 times (reference kernel "
                          "for scaling HBM counters) and exit")
+    ap.add_argument("--read-calibration", type=int, default=0, metavar="MIB",
+                    help="only sum a MIB-sized float32 buffer 5 times (a read-only "
+                         "reference kernel: checks the copy's FETCH_SIZE factor) and exit")
     ap.add_argument("--write-traffic", nargs=5, metavar=("KERNEL", "FETCH_CSV", "WRITE_CSV",
                                                           "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter files of a "
@@ -489,6 +546,11 @@ def main():
     ap.add_argument("--method", default="rk4",
                     help="explicit Runge-Kutta method of the batched/uncoupled workloads: "
                          "one of the named tableaux (rk4 = the classical kernels)")
+    ap.add_argument("--write-adjoint-flops", nargs=2, metavar=("VALU_CSV", "MFMA_CSV"),
+                    help="turn rocprofv3 --pmc counter files of two --workload adjoint runs "
+                         "(SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FLOPS_FP64_TRANS; "
+                         "SQ_INSTS_VALU_MFMA_MOPS_F64) into profiles/adjoint_adjoint_flops.txt "
+                         "and exit")
     ap.add_argument("--write-flops", nargs=2, metavar=("KERNEL", "CSV"),
                     help="turn a rocprofv3 --pmc SQ_INSTS_VALU_FLOPS_FP64 "
                          "SQ_INSTS_VALU_FLOPS_FP64_TRANS counter file of a bench run (same "
@@ -510,6 +572,9 @@ def main():
         return
     if args.write_flops:
         write_flops(args)
+        return
+    if args.write_adjoint_flops:
+        write_adjoint_flops(args)
         return
 
     if args.gpus != 1:
@@ -534,6 +599,15 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "launches": 5}))
+        return
+    if args.read_calibration:
+        n = args.read_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        tot = 0.0
+        for _ in range(5):
+            tot += float(a.sum())
+        torch.cuda.synchronize()
+        print(json.dumps({"read_calibration_bytes": 4 * n, "launches": 5, "sum": tot}))
         return
 
     if args.workload == "large":
