@@ -36,7 +36,9 @@
  *     never held in LDS: always streamed), PSST_LG=0 (small dense networks
  *     -- at most 128 neurons and 4 column chunks of 64 -- take the
  *     LDS-resident kernels instead of the one holding their conductances in
- *     registers; both give the same bits), PSST_ADJ_MODE=lacc|mma (how the
+ *     registers; both give the same bits), PSST_RR=0 (the batch tuner never
+ *     picks a variant holding leading conductance columns of larger
+ *     networks in registers; same bits), PSST_ADJ_MODE=lacc|mma (how the
  *     adjoint accumulates dL/dg), PSST_ADJ_BS=64|128|256|512 (adjoint
  *     workgroup size, when it covers the batch's largest network).
  *   - A handle holds per-handle device state (control blocks, graphs,
@@ -242,12 +244,17 @@ psst_status psst_network_poll(psst_network *net, void *hip_stream);
  * computational graphs", vectorisation paragraph); nets[b] may repeat
  * (trials of one network share its device conductances).  The batch keeps references: the networks must
  * outlive it.  Instance b owns neurons [off_b, off_b + n_b) of every packed
- * array, off_b = sum of the sizes of instances before b.  Creation also tunes
- * the launch shape on the device (timing a few short candidate runs) unless
- * the environment variable PSST_TUNE=0, or PSST_WG_SHAPE="<threads>x<neurons
- * per thread>" names a shape to use; the result is kept for the process and
- * reused by later batches of the same shape (instance count, sizes, matrix
- * volume, storage, method).  n in [1, 1 << 20]. */
+ * array, off_b = sum of the sizes of instances before b.  Instances are
+ * grouped into launches by size class (neurons up to 192, 256, 320, 384,
+ * 448, 512, 1024; small dense networks on their own kernel); creation tunes
+ * each class's kernel variant -- threads per workgroup, neurons per thread,
+ * conductance columns held in registers -- on the device (timing a few short
+ * candidate runs) and merges neighbouring classes that choose the same
+ * variant, unless the environment variable PSST_TUNE=0 (one launch, default
+ * shape) or PSST_WG_SHAPE="<threads>x<neurons per thread>[r<register
+ * slots>]" names the variant to use.  A class's choice is kept for the
+ * process per (device architecture, size class, method, storage, slow GABA
+ * present) and reused by later batches.  n in [1, 1 << 20]. */
 psst_status psst_batch_create(psst_network *const *nets, int32_t n, psst_batch **out);
 psst_status psst_batch_destroy(psst_batch *batch);
 
@@ -282,8 +289,9 @@ psst_status psst_batch_describe(const psst_batch *batch, char *buf, int32_t buf_
  * memory constraints", item 1: the synaptic update is a product with the
  * conductance matrices, so these bytes are its operand traffic):
  * resident_bytes are read once per launch (the leading columns of every
- * conductance chunk kept in LDS for the whole launch, an instance's whole
- * sparse rows, or a small network's whole matrices held in registers),
+ * conductance chunk kept in registers and LDS for the whole launch, an
+ * instance's whole sparse rows, or a small network's whole matrices held in
+ * registers),
  * streamed_bytes once per stage evaluation (the rest; on the
  * per-stage path of a large shared network, its whole padded matrix).  Trials
  * that share one network count once per workgroup that reads it.  Either

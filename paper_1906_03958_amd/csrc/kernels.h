@@ -71,6 +71,8 @@ struct WGVariant {
     bool gen;
     bool lg;
     const void *fn;
+    int slots;                  // float4 register slots per thread for
+                                // conductance columns (0: none)
 };
 
 // All compiled variants (terminated by fn == nullptr).
@@ -92,6 +94,44 @@ __host__ __device__ inline int resident_columns(int64_t lds_bytes, int ld, int n
     const int64_t per_col = (int64_t)sizeof(float) * nch * ld;
     const int64_t R = per_col == 0 ? kChunkWidth : (room > 0 ? room / per_col : 0);
     return (int)(R < kChunkWidth ? R : kChunkWidth);
+}
+
+// Register columns: a kernel variant with S float4 register slots per thread
+// keeps, for instances that stream part of their conductances, the leading
+// columns of each chunk of the thread's column group in registers -- XC
+// columns (four rows each) of each of its KC chunks, XC = S / KC rounded
+// down to a multiple of kRegBatch (so that no batch of kRegBatch slots spans
+// two chunks), KC at most kMaxRegChunks.
+constexpr int kMaxRegChunks = 8;
+constexpr int kRegBatch = 4;
+
+// On-chip columns of every conductance chunk for a workgroup of bs threads
+// of a variant with `slots` register slots per thread (0: none): an instance
+// that fits the LDS alone keeps every column there (*R = kChunkWidth, *XR =
+// 0); otherwise, when each column group (ld / 4 threads, four rows each)
+// takes KC <= kMaxRegChunks chunks, the first *XR columns of every chunk
+// (slots / KC rounded down to a multiple of kRegBatch) sit in registers and
+// the next *R in LDS; the rest streams every stage.  *KC = 0 when no
+// register columns are used.  The kernels' set-up and the host's byte
+// accounting both use it.
+__host__ __device__ inline void wg_residency(int64_t lds_bytes, int ld, int nch, int bs, int slots,
+                                             int *R, int *XR, int *KC)
+{
+    const int R0 = resident_columns(lds_bytes, ld, nch);
+    *R = R0;
+    *XR = 0;
+    *KC = 0;
+    if (R0 >= kChunkWidth || slots <= 0 || nch == 0 || ld < 4) return;
+    const int ncg = bs / (ld / 4);
+    if (ncg <= 0) return;
+    const int kc = (nch + ncg - 1) / ncg;
+    if (kc > kMaxRegChunks) return;
+    int xr = slots / kc / kRegBatch * kRegBatch;
+    if (xr > kChunkWidth) xr = kChunkWidth;
+    if (xr <= 0) return;
+    *XR = xr;
+    *KC = kc;
+    *R = R0 < kChunkWidth - xr ? R0 : kChunkWidth - xr;
 }
 
 // Column chunks of an instance: cholinergic, fast-GABA and slow-GABA columns.

@@ -440,11 +440,30 @@ extern "C" psst_status psst_state_init(const psst_network *net, const float *v0,
 // the per-instance persistent kernel: variant choice and launch
 // ---------------------------------------------------------------------------
 
-static const WGVariant *find_variant(int bs, int npt, bool gen, bool lg = false)
+static const WGVariant *find_variant(int bs, int npt, bool gen, bool lg = false, int slots = 0)
 {
     for (const WGVariant *v = wg_variants(); v->fn; ++v)
-        if (v->bs == bs && v->npt == npt && v->gen == gen && v->lg == lg) return v;
+        if (v->bs == bs && v->npt == npt && v->gen == gen && v->lg == lg && v->slots == slots)
+            return v;
     return nullptr;
+}
+
+// The variant a launch group runs: register-column variants exist for
+// classical RK4 only, so a group tuned to one runs the same shape without
+// register columns once an explicit tableau is set on its batch.
+static const WGVariant *group_variant(const Group &g, bool gen)
+{
+    const WGVariant *v = find_variant(g.bs, g.npt, gen, g.lg, g.slots);
+    if (!v && g.slots) v = find_variant(g.bs, g.npt, gen, g.lg, 0);
+    return v;
+}
+
+// Register-column variants are candidates of the tuner unless the
+// environment variable PSST_RR=0 turns them off (comparisons: the same bits).
+static bool rr_enabled()
+{
+    const char *e = std::getenv("PSST_RR");
+    return !(e && e[0] == '0');
 }
 
 // The lane-group kernel (conductances in registers) takes the instances it
@@ -685,7 +704,7 @@ static WGArgs group_args(psst_batch *b, const Group &g, float *states, const pss
 
 static psst_status launch_group(const Group &g, bool gen, WGArgs &a, hipStream_t s)
 {
-    const WGVariant *v = find_variant(g.bs, g.npt, gen, g.lg);
+    const WGVariant *v = group_variant(g, gen);
     if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant bs=%d npt=%d", g.bs, g.npt);
     psst_status st = set_lds_attr(v->fn, g.lds);
     if (st != PSST_OK) return st;
@@ -704,29 +723,72 @@ struct EventPair {
     }
 };
 
-// Time candidate shapes for one group on a scratch state (short run, no
-// stimulus, no recording) and keep the fastest.
-static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream_t s)
+// PSST_TUNE_LOG=1 prints every timed candidate to stderr.
+static bool tune_log()
 {
+    const char *e = std::getenv("PSST_TUNE_LOG");
+    return e && e[0] == '1';
+}
+
+// Compute units of the current device.
+static int device_cus()
+{
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cached = prop.multiProcessorCount;
+        if (cached <= 0) cached = 1;
+    }
+    return cached;
+}
+
+// Time candidate variants -- shape (threads x neurons per thread) and
+// register columns -- for one group on a scratch state (short run, no
+// stimulus, no recording) and keep the fastest.  The timed launch covers the
+// group's largest instances, one per compute unit: the size classes of a
+// batch run side by side and fill each other's last rounds, so what counts
+// is the time of a full round, not of a tail with most units idle.
+struct Shape {
+    int bs, npt, slots;
+};
+
+static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream_t s,
+                              Shape *no_regs)
+{
+    *no_regs = Shape{g.bs, g.npt, 0};
     if (g.lg) return PSST_OK;          // one shape
-    std::vector<std::pair<int, int>> cands;
+    std::vector<Shape> cands;
     for (const WGVariant *v = wg_variants(); v->fn; ++v) {
-        if (v->gen != b->gen) continue;
+        if (v->gen != b->gen || v->lg) continue;
+        if (v->slots && !rr_enabled()) continue;
         const int cap = v->bs * v->npt;
         if (cap < g.max_n || cap >= 4 * std::max(g.max_n, 64)) continue;
         if (4 * v->bs < g.max_ld) continue;     // every row quad needs a thread
-        cands.push_back({v->bs, v->npt});
+        cands.push_back({v->bs, v->npt, v->slots});
     }
-    if (cands.size() <= 1) return PSST_OK;
+    if (cands.size() <= 1) {
+        if (cands.size() == 1) {
+            g.bs = cands[0].bs;
+            g.npt = cands[0].npt;
+            g.slots = cands[0].slots;
+            if (!g.slots) *no_regs = cands[0];
+        }
+        return PSST_OK;
+    }
     EventPair ev;
     HIPCHK(hipEventCreate(&ev.e0));
     HIPCHK(hipEventCreate(&ev.e1));
-    float best = 1e30f;
-    int bbs = g.bs, bnpt = g.npt;
+    float best = 1e30f, best_plain = 1e30f;
+    Shape bsh{g.bs, g.npt, g.slots};
+    const size_t round = std::min(g.order.size(), (size_t)device_cus());
     for (auto &c : cands) {
         Group t = g;
-        t.bs = c.first;
-        t.npt = c.second;
+        t.order.resize(round);          // the grid: the first (largest) instances
+        t.bs = c.bs;
+        t.npt = c.npt;
+        t.slots = c.slots;
         WGArgs a = group_args(b, t, scratch, nullptr, 0.01f, 4, 0, nullptr, nullptr, 1);
         psst_status st = launch_group(t, b->gen, a, s);        // warm-up
         if (st != PSST_OK) return st;
@@ -737,11 +799,127 @@ static psst_status tune_group(psst_batch *b, Group &g, float *scratch, hipStream
         HIPCHK(hipEventSynchronize(ev.e1));
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, ev.e0, ev.e1));
-        if (ms < best) { best = ms; bbs = c.first; bnpt = c.second; }
+        if (tune_log())
+            std::fprintf(stderr,
+                         "psst tune: %zu of %zu instances, n <= %d: %d x %d, %d slots: %.3f ms\n",
+                         round, g.order.size(), g.max_n, c.bs, c.npt, c.slots, ms);
+        if (ms < best) {
+            best = ms;
+            bsh = c;
+        }
+        if (!c.slots && ms < best_plain) {
+            best_plain = ms;
+            *no_regs = c;
+        }
     }
-    g.bs = bbs;
-    g.npt = bnpt;
+    g.bs = bsh.bs;
+    g.npt = bsh.npt;
+    g.slots = bsh.slots;
     return PSST_OK;
+}
+
+// Launch groups of a batch from its size classes, largest first: a class
+// joins the group before it when both use the same variant (the instances
+// stay in largest-first order); the lane-group group last.
+static std::vector<Group> merge_classes(const std::vector<Group> &cls, const Group &gl)
+{
+    std::vector<Group> merged;
+    for (int c = (int)cls.size() - 1; c >= 0; --c) {
+        const Group &t = cls[c];
+        if (t.order.empty()) continue;
+        if (!merged.empty() && merged.back().bs == t.bs && merged.back().npt == t.npt &&
+            merged.back().slots == t.slots) {
+            Group &m = merged.back();
+            m.order.insert(m.order.end(), t.order.begin(), t.order.end());
+            m.max_n = std::max(m.max_n, t.max_n);
+            m.max_ld = std::max(m.max_ld, t.max_ld);
+        } else {
+            merged.push_back(t);
+        }
+    }
+    if (!gl.order.empty()) merged.push_back(gl);
+    for (Group &t : merged) t.d_order = nullptr;
+    return merged;
+}
+
+// Time a whole launch plan (its groups as the nodes of one graph, as
+// psst_integrate_batch submits them) over a short run on the scratch state:
+// size classes run side by side, so how they share the chip decides.
+static psst_status time_plan(psst_batch *b, std::vector<Group> &plan, float *scratch,
+                             hipStream_t s, float *ms_out)
+{
+    struct Tmp {
+        std::vector<int32_t *> d;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        ~Tmp()
+        {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            for (auto *p : d) (void)hipFree(p);
+        }
+    } tmp;
+    std::vector<WGArgs> args(plan.size());
+    HIPCHK(hipGraphCreate(&tmp.graph, 0));
+    for (size_t k = 0; k < plan.size(); ++k) {
+        Group &g = plan[k];
+        int32_t *d = nullptr;
+        HIPCHK(hipMalloc(&d, sizeof(int32_t) * g.order.size()));
+        tmp.d.push_back(d);
+        HIPCHK(hipMemcpy(d, g.order.data(), sizeof(int32_t) * g.order.size(),
+                         hipMemcpyHostToDevice));
+        g.d_order = d;
+        args[k] = group_args(b, g, scratch, nullptr, 0.01f, 16, 0, nullptr, nullptr, 1);
+        g.d_order = nullptr;
+        const WGVariant *v = group_variant(g, b->gen);
+        if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant");
+        psst_status st = set_lds_attr(v->fn, g.lds);
+        if (st != PSST_OK) return st;
+        void *kp[] = {&args[k]};
+        hipKernelNodeParams p{};
+        p.func = const_cast<void *>(v->fn);
+        p.gridDim = dim3((unsigned)g.order.size());
+        p.blockDim = dim3(g.bs);
+        p.sharedMemBytes = (unsigned)g.lds;
+        p.kernelParams = kp;
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        HIPCHK(hipGraphAddKernelNode(&node, tmp.graph, nullptr, 0, &p));
+    }
+    HIPCHK(hipGraphInstantiate(&tmp.exec, tmp.graph, nullptr, nullptr, 0));
+    EventPair ev;
+    HIPCHK(hipEventCreate(&ev.e0));
+    HIPCHK(hipEventCreate(&ev.e1));
+    HIPCHK(hipGraphLaunch(tmp.exec, s));          // warm-up
+    HIPCHK(hipEventRecord(ev.e0, s));
+    HIPCHK(hipGraphLaunch(tmp.exec, s));
+    HIPCHK(hipEventRecord(ev.e1, s));
+    HIPCHK(hipEventSynchronize(ev.e1));
+    HIPCHK(hipEventElapsedTime(ms_out, ev.e0, ev.e1));
+    return PSST_OK;
+}
+
+// Size classes of the per-instance kernels (upper bounds of n): each class
+// is tuned on its own; neighbouring classes that choose the same variant
+// share one launch.
+static const int kClassEdges[] = {192, 256, 320, 384, 448, 512, 1024};
+static const int kNumClasses = (int)(sizeof(kClassEdges) / sizeof(kClassEdges[0]));
+
+static int size_class(int n)
+{
+    int c = 0;
+    while (c + 1 < kNumClasses && n > kClassEdges[c]) ++c;
+    return c;
+}
+
+// Name of the device's architecture, for the tuning cache key.
+static std::string device_arch()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    return std::string(prop.gcnArchName);
 }
 
 extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, psst_batch **out)
@@ -821,11 +999,13 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
 
     // Launch groups, workgroups in largest-first (LPT) order of cost ~ n^2:
     // small dense networks the lane-group kernel takes (conductances in
-    // registers) form one group, the rest another whose LDS request is the
-    // full per-workgroup LDS: each instance keeps the leading columns of every
-    // conductance chunk there (all of G when it fits) and streams the rest
-    // from L2/MALL/HBM.  Each group is one launch (a node of the batch's
-    // graph).
+    // registers) form one group; the rest are split into size classes, each
+    // with its own tuned variant (shape and register columns) and the full
+    // per-workgroup LDS: each instance keeps the leading columns of every
+    // conductance chunk on chip (registers, then LDS; all of G when it fits)
+    // and streams the rest from L2/MALL/HBM.  Neighbouring classes that
+    // choose the same variant share one launch.  Each group is one launch (a
+    // node of the batch's graph).
     std::vector<int32_t> idx(n);
     for (int32_t k = 0; k < n; ++k) idx[k] = k;
     std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
@@ -835,92 +1015,182 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     const char *env = std::getenv("PSST_LDS_G");
     const bool allow_lds = !(env && env[0] == '0');
     const char *shp = std::getenv("PSST_WG_SHAPE");
-    Group g, gl;
+    const char *tenv = std::getenv("PSST_TUNE");
+    const bool tune = !shp && !(tenv && tenv[0] == '0');
+    Group gl;
     gl.lg = true;
+    std::vector<Group> cls(tune ? kNumClasses : 1);
+    bool any_syn = false, any_sparse = false, any_gabab = false;
     size_t need = 0;
-    bool any_syn = false;
     for (int32_t k : idx) {
         const psst_network *q = nets[k];
-        Group &t = (!shp && net_lg(q)) ? gl : g;
+        if (!shp && net_lg(q)) {
+            gl.order.push_back(k);
+            gl.max_n = std::max(gl.max_n, q->n);
+            gl.max_ld = std::max(gl.max_ld, q->ld);
+            continue;
+        }
+        Group &t = cls[tune ? size_class(q->n) : 0];
         t.order.push_back(k);
         t.max_n = std::max(t.max_n, q->n);
         t.max_ld = std::max(t.max_ld, q->ld);
-        if (&t == &g) {
-            need = std::max(need, wg_lds_bytes(false, q->ld, q->nch, 0));
-            // networks without synapses need no LDS beyond the small buffers,
-            // so several workgroups share a CU
-            any_syn |= q->desc.n_paths > 0;
-        }
+        need = std::max(need, wg_lds_bytes(false, q->ld, q->nch, 0));
+        // networks without synapses need no LDS beyond the small buffers,
+        // so several workgroups share a CU
+        any_syn |= q->desc.n_paths > 0;
+        any_sparse |= q->sparse;
+        any_gabab |= q->gabab;
     }
-    g.lds = (allow_lds && any_syn) ? lmax : need;
-    default_shape(g.max_n, &g.bs, &g.npt);
+    const size_t glds = (allow_lds && any_syn) ? lmax : need;
+    for (Group &t : cls) {
+        t.lds = glds;
+        default_shape(t.max_n, &t.bs, &t.npt);
+    }
     gl.bs = kLGThreads;
     gl.npt = kLGPairs;
     gl.lds = (size_t)kLGLdsBytes;
-    // PSST_WG_SHAPE="<threads>x<neurons per thread>" fixes the launch shape
-    // (and skips tuning) when that variant can take every instance.
-    bool fixed = g.order.empty();
+    // PSST_WG_SHAPE="<threads>x<neurons per thread>[r<register slots>]"
+    // fixes the launch variant (and skips tuning) when it can take every
+    // instance.
     if (shp) {
-        int bs = 0, npt = 0;
-        if (std::sscanf(shp, "%dx%d", &bs, &npt) == 2 && find_variant(bs, npt, b->gen) &&
-            bs * npt >= g.max_n && 4 * bs >= g.max_ld) {
-            g.bs = bs;
-            g.npt = npt;
-            fixed = true;
+        int bs = 0, npt = 0, sl = 0;
+        const int got = std::sscanf(shp, "%dx%dr%d", &bs, &npt, &sl);
+        if (got >= 2 && find_variant(bs, npt, b->gen, false, got == 3 ? sl : 0) &&
+            bs * npt >= cls[0].max_n && 4 * bs >= cls[0].max_ld) {
+            cls[0].bs = bs;
+            cls[0].npt = npt;
+            cls[0].slots = got == 3 ? sl : 0;
         }
     }
-    for (Group *t : {&g, &gl}) {
-        if (t->order.empty()) continue;
-        BCHK(hipMalloc(&t->d_order, sizeof(int32_t) * t->order.size()));
-        BCHK(hipMemcpy(t->d_order, t->order.data(), sizeof(int32_t) * t->order.size(),
-                       hipMemcpyHostToDevice));
-        b->groups.push_back(*t);
-        t->d_order = nullptr;           // owned by the batch's copy now
-    }
-    Group &gt = b->groups[0];           // the tuned group (the classic kernels) when present
-    // launch-shape tuning on a scratch state, once per batch shape in the
-    // process: batches alike in count, sizes, matrix volume, storage and
-    // method (an autograd loop makes one per forward call) reuse the result
-    const char *tenv = std::getenv("PSST_TUNE");
-    int64_t gsum = 0;
-    int nsparse = 0;
-    for (auto *q : b->nets) {
-        gsum += q->g_floats;
-        nsparse += q->sparse ? 1 : 0;
-    }
-    const auto tkey = std::make_tuple(n, b->nt, g.max_n, gsum, nsparse, b->gen, gt.lds);
-    static std::mutex tune_mu;
-    static std::map<decltype(tkey), std::pair<int, int>> tune_cache;
-    if (!fixed && !(tenv && tenv[0] == '0')) {
-        std::lock_guard<std::mutex> lock(tune_mu);
-        auto it = tune_cache.find(tkey);
-        if (it != tune_cache.end()) {
-            gt.bs = it->second.first;
-            gt.npt = it->second.second;
-            fixed = true;
+    // launch-variant tuning on a scratch state: per size class, the fastest
+    // variant on a full round of the class's largest instances, and the
+    // fastest without register columns; then, when the two differ, the
+    // batch's whole launch with either set of choices (classes run side by
+    // side and share the chip, so their interplay decides).  Per-class
+    // choices are cached per (architecture, size class, method, storage,
+    // slow GABA, LDS, register columns allowed); the plan choice per the
+    // same and the batch's class counts.
+    std::vector<Group> merged;
+    if (tune) {
+        const std::string arch = device_arch();
+        typedef std::tuple<std::string, int, bool, bool, bool, size_t, bool> Key;
+        typedef std::tuple<std::string, std::vector<size_t>, bool, bool, bool, size_t, bool> PlanKey;
+        static std::mutex tune_mu;
+        static std::map<Key, std::pair<Shape, Shape>> tune_cache;
+        static std::map<PlanKey, bool> plan_cache;
+        std::vector<Shape> plain(cls.size());
+        std::vector<int> todo;
+        std::vector<size_t> counts;
+        for (const Group &t : cls) counts.push_back(t.order.size());
+        counts.push_back(gl.order.size());
+        const PlanKey pkey{arch, counts, b->gen, any_sparse, any_gabab, glds, rr_enabled()};
+        int plan_cached = -1;
+        {
+            std::lock_guard<std::mutex> lock(tune_mu);
+            for (int c = 0; c < kNumClasses; ++c) {
+                Group &t = cls[c];
+                if (t.order.empty()) continue;
+                const Key key{arch, c, b->gen, any_sparse, any_gabab, glds, rr_enabled()};
+                auto it = tune_cache.find(key);
+                const Shape &sb = it != tune_cache.end() ? it->second.first : Shape{};
+                const Shape &sp = it != tune_cache.end() ? it->second.second : Shape{};
+                if (it != tune_cache.end() &&
+                    find_variant(sb.bs, sb.npt, b->gen, false, sb.slots) != nullptr &&
+                    sb.bs * sb.npt >= t.max_n && 4 * sb.bs >= t.max_ld &&
+                    find_variant(sp.bs, sp.npt, b->gen, false, 0) != nullptr &&
+                    sp.bs * sp.npt >= t.max_n && 4 * sp.bs >= t.max_ld) {
+                    t.bs = sb.bs;
+                    t.npt = sb.npt;
+                    t.slots = sb.slots;
+                    plain[c] = sp;
+                } else {
+                    todo.push_back(c);
+                }
+            }
+            auto pit = plan_cache.find(pkey);
+            if (pit != plan_cache.end()) plan_cached = pit->second ? 1 : 0;
         }
-    }
-    if (!fixed && !(tenv && tenv[0] == '0')) {
+        std::vector<Group> cls_plain = cls;
+        auto plans_differ = [&]() {
+            for (size_t c = 0; c < cls.size(); ++c)
+                if (!cls[c].order.empty() && cls[c].slots) return true;
+            return false;
+        };
         // scratch state for the timing runs; every buffer is released on
         // every path before an error is returned
         float *scratch = nullptr;
         float *v0 = nullptr;
         hipStream_t st = nullptr;
-        hipError_t e = hipMalloc(&scratch, sizeof(float) * 14 * b->nt);
-        if (e == hipSuccess) e = hipMalloc(&v0, sizeof(float) * b->nt);
-        if (e == hipSuccess) {
-            std::vector<float> hv(b->nt, -65.f);
-            e = hipMemcpy(v0, hv.data(), sizeof(float) * b->nt, hipMemcpyHostToDevice);
+        auto release = [&]() {
+            if (st) (void)hipStreamDestroy(st);
+            (void)hipFree(scratch);
+            (void)hipFree(v0);
+            st = nullptr;
+            scratch = v0 = nullptr;
+        };
+        auto setup = [&]() -> hipError_t {
+            hipError_t e = hipMalloc(&scratch, sizeof(float) * 14 * b->nt);
+            if (e == hipSuccess) e = hipMalloc(&v0, sizeof(float) * b->nt);
+            if (e == hipSuccess) {
+                std::vector<float> hv(b->nt, -65.f);
+                e = hipMemcpy(v0, hv.data(), sizeof(float) * b->nt, hipMemcpyHostToDevice);
+            }
+            if (e == hipSuccess) e = hipStreamCreate(&st);
+            if (e == hipSuccess && launch_init(b->d_desc, n, v0, scratch, b->nt, st) != PSST_OK)
+                e = hipErrorLaunchFailure;
+            return e;
+        };
+        hipError_t e = hipSuccess;
+        if (!todo.empty() || (plan_cached < 0 && plans_differ())) e = setup();
+        if (e == hipSuccess && !todo.empty()) {
+            for (int c : todo) {
+                if (s != PSST_OK || e != hipSuccess) break;
+                Group &t = cls[c];
+                e = hipMalloc(&t.d_order, sizeof(int32_t) * t.order.size());
+                if (e == hipSuccess)
+                    e = hipMemcpy(t.d_order, t.order.data(), sizeof(int32_t) * t.order.size(),
+                                  hipMemcpyHostToDevice);
+                if (e == hipSuccess) s = tune_group(b, t, scratch, st, &plain[c]);
+                const hipError_t e2 = hipStreamSynchronize(st);
+                if (e == hipSuccess) e = e2;
+                (void)hipFree(t.d_order);
+                t.d_order = nullptr;
+            }
+            if (e == hipSuccess && s == PSST_OK) {
+                std::lock_guard<std::mutex> lock(tune_mu);
+                for (int c : todo) {
+                    const Group &t = cls[c];
+                    tune_cache[Key{arch, c, b->gen, any_sparse, any_gabab, glds, rr_enabled()}] =
+                        {Shape{t.bs, t.npt, t.slots}, plain[c]};
+                }
+            }
         }
-        if (e == hipSuccess) e = hipStreamCreate(&st);
-        if (e == hipSuccess) {
-            s = launch_init(b->d_desc, n, v0, scratch, b->nt, st);
-            if (s == PSST_OK) s = tune_group(b, gt, scratch, st);
-            e = hipStreamSynchronize(st);
+        for (size_t c = 0; c < cls.size(); ++c) {
+            cls_plain[c].bs = plain[c].bs;
+            cls_plain[c].npt = plain[c].npt;
+            cls_plain[c].slots = 0;
         }
-        if (st) (void)hipStreamDestroy(st);
-        (void)hipFree(scratch);
-        (void)hipFree(v0);
+        bool use_regs = true;
+        if (e == hipSuccess && s == PSST_OK && plans_differ()) {
+            if (plan_cached >= 0) {
+                use_regs = plan_cached == 1;
+            } else {
+                std::vector<Group> pa = merge_classes(cls, gl), pb = merge_classes(cls_plain, gl);
+                float ta = 0.f, tb = 0.f;
+                s = time_plan(b, pa, scratch, st, &ta);
+                if (s == PSST_OK) s = time_plan(b, pb, scratch, st, &tb);
+                if (s == PSST_OK) {
+                    use_regs = ta < tb;
+                    if (tune_log())
+                        std::fprintf(stderr, "psst tune: whole launch %.3f ms with register "
+                                             "columns, %.3f ms without\n", ta, tb);
+                    std::lock_guard<std::mutex> lock(tune_mu);
+                    plan_cache[pkey] = use_regs;
+                }
+            }
+        }
+        if (e == hipSuccess && scratch) e = hipStreamSynchronize(st);
+        release();
         if (e != hipSuccess && s == PSST_OK)
             s = fail(e == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY : PSST_ERR_DEVICE,
                      "launch-shape tuning failed: %s", hipGetErrorString(e));
@@ -929,14 +1199,24 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
             return s;
         }
         BCHK(hipMemset(b->d_flag, 0, sizeof(int32_t)));
-        std::lock_guard<std::mutex> lock(tune_mu);
-        tune_cache[tkey] = {gt.bs, gt.npt};
+        merged = merge_classes(use_regs ? cls : cls_plain, gl);
+    } else {
+        merged = merge_classes(cls, gl);
+    }
+    for (const Group &t : merged) {
+        b->groups.push_back(t);         // the batch owns (and frees) d_order
+        Group &bg = b->groups.back();
+        BCHK(hipMalloc(&bg.d_order, sizeof(int32_t) * bg.order.size()));
+        BCHK(hipMemcpy(bg.d_order, bg.order.data(), sizeof(int32_t) * bg.order.size(),
+                       hipMemcpyHostToDevice));
     }
 #undef BCHK
     char buf[256];
     for (auto &g : b->groups) {
-        snprintf(buf, sizeof buf, "[%zu inst, n<=%d, %s%d thr x %d neurons, lds %zu B] ",
-                 g.order.size(), g.max_n, g.lg ? "lane-group, " : "", g.bs, g.npt, g.lds);
+        char rr[48] = "";
+        if (g.slots) snprintf(rr, sizeof rr, ", %d register slots", g.slots);
+        snprintf(buf, sizeof buf, "[%zu inst, n<=%d, %s%d thr x %d neurons%s, lds %zu B] ",
+                 g.order.size(), g.max_n, g.lg ? "lane-group, " : "", g.bs, g.npt, rr, g.lds);
         b->describe += buf;
     }
     *out = b;
@@ -976,6 +1256,8 @@ extern "C" psst_status psst_batch_conductance_bytes(const psst_batch *b, int64_t
         str = stage_batch_matrix_bytes(b->stage);
     } else {
         for (const Group &g : b->groups) {
+            const WGVariant *v = group_variant(g, b->gen);
+            const int slots = v ? v->slots : 0;
             for (int32_t k : g.order) {
                 const psst_network *q = b->nets[k];
                 if (q->desc.flags & DESC_NOSYN) continue;
@@ -995,15 +1277,16 @@ extern "C" psst_status psst_batch_conductance_bytes(const psst_batch *b, int64_t
                     continue;
                 }
                 // chunk widths: cholinergic columns, fast-GABA columns, slow
-                // matrix, each cut at kChunkWidth; the first R columns of
-                // every chunk stay in LDS
-                const int R = resident_columns((int64_t)g.lds, q->ld, q->nch);
+                // matrix, each cut at kChunkWidth; the first XR columns of
+                // every chunk stay in registers and the next R in LDS
+                int R = 0, XR = 0, KC = 0;
+                wg_residency((int64_t)g.lds, q->ld, q->nch, g.bs, slots, &R, &XR, &KC);
                 const int n_ln = q->n - q->n_pn;
                 const int spans[3] = {q->n_pn, n_ln, q->gabab ? n_ln : 0};
                 for (int t = 0; t < 3; ++t)
                     for (int j0 = 0; j0 < spans[t]; j0 += kChunkWidth) {
                         const int w = std::min(kChunkWidth, spans[t] - j0);
-                        const int r = std::min(w, R);
+                        const int r = std::min(w, XR + R);
                         res += (int64_t)sizeof(float) * q->ld * r;
                         str += (int64_t)sizeof(float) * q->ld * (w - r);
                     }
@@ -1033,7 +1316,7 @@ static psst_status submit_graph(psst_batch *b, std::vector<WGArgs> &args, hipStr
         b->node_args = args;
         for (size_t k = 0; k < G; ++k) {
             const Group &g = b->groups[k];
-            const WGVariant *v = find_variant(g.bs, g.npt, b->gen, g.lg);
+            const WGVariant *v = group_variant(g, b->gen);
             if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant");
             psst_status st = set_lds_attr(v->fn, g.lds);
             if (st != PSST_OK) return st;
@@ -1053,7 +1336,8 @@ static psst_status submit_graph(psst_batch *b, std::vector<WGArgs> &args, hipStr
             if (std::memcmp(&b->node_args[k], &args[k], sizeof(WGArgs)) == 0) continue;
             b->node_args[k] = args[k];
             const Group &g = b->groups[k];
-            const WGVariant *v = find_variant(g.bs, g.npt, b->gen, g.lg);
+            const WGVariant *v = group_variant(g, b->gen);
+            if (!v) return fail(PSST_ERR_UNSUPPORTED, "no kernel variant");
             void *kp[] = {&b->node_args[k]};
             hipKernelNodeParams p{};
             p.func = const_cast<void *>(v->fn);

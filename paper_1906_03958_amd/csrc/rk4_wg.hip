@@ -305,13 +305,18 @@ __device__ __forceinline__ void lg_integrate(const WGArgs &a, const InstDesc &d,
                       });
 }
 
-template <int BS, int NPT, bool GEN>
+// S > 0: the variant keeps conductance columns in S float4 register slots per
+// thread for instances that stream part of their conductances (the register
+// file of a one-wavefront-per-SIMD workgroup beside its LDS).
+template <int BS, int NPT, bool GEN, int S = 0>
 __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
 {
     extern __shared__ double lds_d[];
     const int32_t b = a.order[blockIdx.x];
     const InstDesc d = a.desc[b];
-    const WGSyn w = wg_setup<BS>(d, lds_d, a.lds_bytes);
+    const WGSyn w = wg_setup<BS>(d, lds_d, a.lds_bytes, S);
+    RegCols<S> rc;
+    if constexpr (S > 0) load_regcols<S>(rr_view(w), rc);
     const int tid = threadIdx.x;
     const Kin K = load_kin(d.kin);
     const double dt = a.dt;
@@ -320,9 +325,9 @@ __global__ __launch_bounds__(BS) void rk4_wg_kernel(WGArgs a)
         [&](const float (&pr)[NPT][NPRM], const double (&Iu)[NPT], double (&y)[NPT][NVAR],
             const StageStash *stash) {
             if constexpr (GEN)
-                rk_step_wg_tab<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, stash, a.tab);
+                rk_step_wg_tab<BS, NPT, S>(w, K, d.cg, pr, Iu, dt, y, stash, a.tab, &rc);
             else
-                rk4_step_wg<BS, NPT>(w, K, d.cg, pr, Iu, dt, y, stash);
+                rk4_step_wg<BS, NPT, S>(w, K, d.cg, pr, Iu, dt, y, stash, &rc);
         });
 }
 
@@ -358,15 +363,17 @@ __global__ __launch_bounds__(256) void init_state_kernel(InitArgs a)
     }
 }
 
-#define WGV(BS, NPT) {BS, NPT, false, false, (const void *)rk4_wg_kernel<BS, NPT, false>}
-#define WGG(BS, NPT) {BS, NPT, true, false, (const void *)rk4_wg_kernel<BS, NPT, true>}
+#define WGV(BS, NPT) {BS, NPT, false, false, (const void *)rk4_wg_kernel<BS, NPT, false>, 0}
+#define WGG(BS, NPT) {BS, NPT, true, false, (const void *)rk4_wg_kernel<BS, NPT, true>, 0}
+#define WGR(BS, NPT, S) {BS, NPT, false, false, (const void *)rk4_wg_kernel<BS, NPT, false, S>, S}
 
 static const WGVariant kVariants[] = {
     WGV(64, 1), WGV(128, 1), WGV(128, 2), WGV(256, 1), WGV(256, 2), WGV(256, 4), WGV(512, 1),
     WGG(64, 1), WGG(128, 1), WGG(128, 2), WGG(256, 1), WGG(256, 2), WGG(256, 4), WGG(512, 1),
-    {kLGThreads, 2, false, true, (const void *)rk4_lg_kernel<false, 2>},
-    {kLGThreads, 2, true, true, (const void *)rk4_lg_kernel<true, 2>},
-    {0, 0, false, false, nullptr},
+    WGR(256, 2, 48),
+    {kLGThreads, 2, false, true, (const void *)rk4_lg_kernel<false, 2>, 0},
+    {kLGThreads, 2, true, true, (const void *)rk4_lg_kernel<true, 2>, 0},
+    {0, 0, false, false, nullptr, 0},
 };
 
 const WGVariant *wg_variants() { return kVariants; }

@@ -78,6 +78,7 @@ struct Group {
     int32_t *d_order = nullptr;
     int max_n = 0, max_ld = 0;
     int bs = 0, npt = 0;
+    int slots = 0;                  // register slots for conductance columns (0: none)
     size_t lds = 0;                 // dynamic LDS of the launch
     bool lg = false;                // lane-group kernel (every instance eligible)
 };

@@ -241,7 +241,9 @@ struct WGSyn {
     double *xf, *xb, *part;    // LDS activations and chunk partials
     Chunks ch;
     int n, n_pn, ld, nch, NCG, r4, cg;
-    int R;                     // resident columns per chunk (CW = whole matrix in LDS)
+    int R;                     // LDS columns per chunk (CW = whole matrix in LDS)
+    int XR;                    // register columns per chunk, before the LDS ones
+    int KC;                    // chunks per column group when XR > 0 (else 0)
     bool gabab;
     bool sparse;               // conductances in sparse rows (sp_col, sp_val)
     bool sp_lds;               // ... copied to LDS for the launch
@@ -303,12 +305,127 @@ __device__ __forceinline__ void sparse_row(const int32_t *col, const float *val,
     }
 }
 
+// Conductance columns a thread keeps in registers for a whole launch: S
+// float4 slots; with KC chunks per column group (chunk cg + k NCG, k < KC)
+// and XC columns per chunk (a multiple of kRegBatch, XC KC <= S), slot
+// k XC + u holds column j0 + u of chunk k's four rows (zeros past the chunk's
+// end and in unused slots).  The slot index is a compile-time constant
+// wherever a slot is touched, so the slots stay in registers whatever KC is.
+// S = 0: none.
+template <int S>
+struct RegCols {
+    v4f g[S];
+};
+template <>
+struct RegCols<0> {
+};
+
+// The pointers and sizes the register-column routines use, passed as values
+// (selecting between fields of the per-workgroup struct would make the
+// compiler address that struct in memory and lose the pointers' address
+// spaces).
+struct RRView {
+    const float *gt, *gtb, *gl;
+    const double *xf, *xb;
+    double *part;
+    Chunks ch;
+    int n, n_pn, ld, nch, NCG, cg, r4, R, XR, KC;
+};
+
+__device__ __forceinline__ RRView rr_view(const WGSyn &w)
+{
+    return RRView{w.gt,  w.gtb,  w.gl,  w.xf,  w.xb,  w.part, w.ch, w.n,  w.n_pn,
+                  w.ld,  w.nch,  w.NCG, w.cg,  w.r4,  w.R,    w.XR, w.KC};
+}
+
+template <int S>
+__device__ __forceinline__ void load_regcols(const RRView v, RegCols<S> &rc)
+{
+    if (v.KC == 0) {            // no register columns (the matrices may not exist)
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) rc.g[sl] = v4f{0.f, 0.f, 0.f, 0.f};
+        return;
+    }
+    const int64_t q = v.ld >> 2;
+    const int XC = v.XR;
+    global_float4 *Gf = (global_float4 *)v.gt + v.r4;
+    global_float4 *Gb = (global_float4 *)(v.gtb ? v.gtb : v.gt) + v.r4;
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+        const int k = sl / XC, u = sl - k * XC;
+        const int c = v.cg + k * v.NCG;
+        const bool valid = k < v.KC && v.cg < v.NCG && c < v.nch;
+        int mat = 0, j0 = 0, j1 = 0;
+        if (valid) chunk_range(v.ch, v.n, v.n_pn, c, mat, j0, j1);
+        const bool in = valid && j0 + u < j1;
+        const int64_t e = in ? (int64_t)(j0 + u) * q : 0;
+        const v4f val = mat ? Gb[e] : Gf[e];
+        rc.g[sl] = in ? val : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
+// One stage's chunk partials with register columns (v.KC > 0): per chunk k of
+// the thread's column group, its register columns (the batches of kRegBatch
+// slots among k XC .. k XC + XC - 1; a column past the chunk's end has g = 0
+// and adds an exact zero, its activation read from the chunk's last column),
+// then its LDS columns, then the streamed rest -- the column-order fma
+// sequence of stage_partials.
+template <int S>
+__device__ __forceinline__ void stage_partials_rr(const RRView v, const RegCols<S> &rc)
+{
+    constexpr int B = kRegBatch;
+    static_assert(S % B == 0, "slots come in whole batches");
+    const int XC = v.XR;
+#pragma unroll 1
+    for (int k = 0; k < v.KC; ++k) {
+        const int c = v.cg + k * v.NCG;
+        if (c >= v.nch) break;
+        int mat, j0, j1;
+        chunk_range(v.ch, v.n, v.n_pn, c, mat, j0, j1);
+        const float *M = mat ? v.gtb : v.gt;
+        const double *Xd = mat ? v.xb : v.xf;
+        lds_double *X = (lds_double *)Xd;
+        const int s_lo = k * XC, s_hi = s_lo + XC;    // this chunk's slots
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+        for (int b0 = 0; b0 < S; b0 += B) {
+            if (b0 < s_lo || b0 >= s_hi) continue;     // uniform: batch of another chunk
+            double xv[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) xv[u] = X[min(j0 + (b0 - s_lo) + u, j1 - 1)];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                // an empty asm makes each stage use the float32 values
+                // afresh: otherwise their float64 widening is hoisted out of
+                // the time loop and takes twice the registers
+                v4f g = rc.g[b0 + u];
+                asm volatile("" : "+v"(g));
+                s0 = fma((double)g.x, xv[u], s0);
+                s1 = fma((double)g.y, xv[u], s1);
+                s2 = fma((double)g.z, xv[u], s2);
+                s3 = fma((double)g.w, xv[u], s3);
+            }
+        }
+        const int ja = min(j1, j0 + XC);
+        const int jr = min(j1, ja + v.R);
+        if (jr > ja)
+            chunk_rows4<8>((lds_float4 *)(v.gl + (int64_t)c * v.R * v.ld), ja, v.ld, Xd, ja, jr,
+                           v.r4, s0, s1, s2, s3);
+        if (j1 > jr)
+            chunk_rows4<8>((global_float4 *)M, 0, v.ld, Xd, jr, j1, v.r4, s0, s1, s2, s3);
+        typedef __attribute__((address_space(3))) double lds_double_w;
+        lds_double_w *pc = (lds_double_w *)(v.part + (size_t)c * v.ld + 4 * v.r4);
+        pc[0] = s0; pc[1] = s1; pc[2] = s2; pc[3] = s3;
+    }
+}
+
 // Synaptic sums (nS) at stage input Y for the calling thread's neurons
 // i = tid + k * BS: write the activations, sync, form the chunk partials, sync,
 // add the partials in chunk order.  Every thread of the workgroup must call.
-template <int BS, int NPT>
+template <int BS, int NPT, int S = 0>
 __device__ __forceinline__ void syn_sums(const WGSyn &w, const Kin &K, const double (&Y)[NPT][NVAR],
-                                         double (&sa)[NPT], double (&sg)[NPT], double (&sb)[NPT])
+                                         double (&sa)[NPT], double (&sg)[NPT], double (&sb)[NPT],
+                                         const RegCols<S> *rc = nullptr)
 {
     const int tid = threadIdx.x;
     if (w.sparse) {
@@ -361,11 +478,20 @@ __device__ __forceinline__ void syn_sums(const WGSyn &w, const Kin &K, const dou
         }
     }
     __syncthreads();
-    if (w.R == CW)
+    if (w.R == CW) {
         stage_partials_lds<8>(w.gl, w.ld, w.xf, w.xb, w.part, w.ch, w.n, w.n_pn, tid, BS);
-    else if (w.cg < w.NCG)
-        stage_partials(w.gt, w.gtb, w.gl, w.R, w.ld, w.xf, w.xb, w.part, w.ch, w.n, w.n_pn, w.cg,
-                       w.NCG, w.r4);
+    } else if (w.cg < w.NCG) {
+        bool done = false;
+        if constexpr (S > 0) {
+            if (w.KC > 0) {
+                stage_partials_rr<S>(rr_view(w), *rc);
+                done = true;
+            }
+        }
+        if (!done)
+            stage_partials(w.gt, w.gtb, w.gl, w.R, w.ld, w.xf, w.xb, w.part, w.ch, w.n, w.n_pn,
+                           w.cg, w.NCG, w.r4);
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -456,6 +582,9 @@ __device__ __forceinline__ void rk4_step_core(const Slots &sl, Syn &&syn, Idx &&
                 if (q < 3) Y[k][v] = y[k][v] + c * f[v];
             }
             if (q < 3) post(k, Y[k]);
+            // one neuron's right-hand side at a time: interleaving several
+            // would multiply the temporaries held at once
+            if constexpr (NPT > 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
 #pragma unroll
@@ -547,33 +676,35 @@ __device__ __forceinline__ void rk_step_core_tab(const Slots &sl, Syn &&syn, Idx
 }
 
 // The per-instance mappings: slot k of thread tid is neuron tid + k BS.
-template <int BS, int NPT>
+template <int BS, int NPT, int S = 0>
 __device__ __forceinline__ void rk4_step_wg(const WGSyn &w, const Kin &K, double cgf,
                                             const float (&pr)[NPT][NPRM], const double (&Iu)[NPT],
                                             double dt, double (&y)[NPT][NVAR],
-                                            const StageStash *stash)
+                                            const StageStash *stash,
+                                            const RegCols<S> *rc = nullptr)
 {
     const int tid = threadIdx.x;
     rk4_step_core<NPT>(
         Slots{w.n, w.n_pn, w.gabab},
         [&](const double (&Y)[NPT][NVAR], double (&sa)[NPT], double (&sg)[NPT],
-            double (&sb)[NPT]) { syn_sums<BS, NPT>(w, K, Y, sa, sg, sb); },
+            double (&sb)[NPT]) { syn_sums<BS, NPT, S>(w, K, Y, sa, sg, sb, rc); },
         [&](int k) { return tid + k * BS; }, [&](int k) { return k * BS < w.n; }, K, cgf, pr,
         Iu, dt, y, stash);
 }
 
-template <int BS, int NPT>
+template <int BS, int NPT, int S = 0>
 __device__ __forceinline__ void rk_step_wg_tab(const WGSyn &w, const Kin &K, double cgf,
                                                const float (&pr)[NPT][NPRM],
                                                const double (&Iu)[NPT], double dt,
                                                double (&y)[NPT][NVAR], const StageStash *stash,
-                                               const Tab &T)
+                                               const Tab &T,
+                                               const RegCols<S> *rc = nullptr)
 {
     const int tid = threadIdx.x;
     rk_step_core_tab<NPT>(
         Slots{w.n, w.n_pn, w.gabab},
         [&](const double (&Y)[NPT][NVAR], double (&sa)[NPT], double (&sg)[NPT],
-            double (&sb)[NPT]) { syn_sums<BS, NPT>(w, K, Y, sa, sg, sb); },
+            double (&sb)[NPT]) { syn_sums<BS, NPT, S>(w, K, Y, sa, sg, sb, rc); },
         [&](int k) { return tid + k * BS; }, [&](int k) { return k * BS < w.n; }, K, cgf, pr,
         Iu, dt, y, stash, T);
 }
@@ -582,7 +713,8 @@ __device__ __forceinline__ void rk_step_wg_tab(const WGSyn &w, const Kin &K, dou
 // part of the conductances -- as many leading columns of every chunk as the
 // launch's LDS allocation leaves room for (all of them when the instance fits).
 template <int BS>
-__device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int64_t lds_bytes)
+__device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int64_t lds_bytes,
+                                          int slots = 0)
 {
     WGSyn w;
     w.n = d.n;
@@ -621,16 +753,17 @@ __device__ __forceinline__ WGSyn wg_setup(const InstDesc &d, double *lds_d, int6
             w.sp_lds = true;
         }
     }
-    w.R = resident_columns(lds_bytes, d.ld, w.nch);
+    wg_residency(lds_bytes, d.ld, w.nch, BS, slots, &w.R, &w.XR, &w.KC);
     const int tid = threadIdx.x;
     if (w.R > 0) {
         const int q = d.ld >> 2;
         for (int c = 0; c < w.nch; ++c) {
             int mat, j0, j1;
             chunk_range(w.ch, d.n, d.n_pn, c, mat, j0, j1);
-            const int rows = min(j1, j0 + w.R) - j0;
+            const int jl = min(j1, j0 + w.XR);      // first LDS column of the chunk
+            const int rows = min(j1, jl + w.R) - jl;
             const float4 *src = reinterpret_cast<const float4 *>((mat ? d.gtb : d.gt) +
-                                                                 (int64_t)j0 * d.ld);
+                                                                 (int64_t)jl * d.ld);
             float4 *dst = reinterpret_cast<float4 *>(gl + (int64_t)c * w.R * d.ld);
             for (int e = tid; e < rows * q; e += BS) dst[e] = src[e];
         }

@@ -192,6 +192,20 @@ def sized_instance(instance: int, n_pn: int, n_ln: int) -> Instance:
     return Instance(net, _v0(cfg, instance, net.n), _const_stim(cfg, instance, net.n))
 
 
+def sized_instance_slow(instance: int, n_pn: int, n_ln: int) -> Instance:
+    """sized_instance with slow GABA added: every LN -> any pair is also a
+    Bernoulli(0.5) candidate for a G-protein synapse, g ~ U(0, 0.5) nS (its
+    own mask and values; seeded by (10, instance))."""
+    base = sized_instance(instance, n_pn, n_ln)
+    n = n_pn + n_ln
+    if n_ln > 0:
+        rm = rng_for(10, instance, S_MASK)
+        rg = rng_for(10, instance, S_G)
+        g, m = _bernoulli_block(rm, rg, (n, n_ln), 0.5, 0.5, (0, n_pn))
+        base.net.pathways.append(Pathway(GABA_B, n_pn, n, 0, n, g, m))
+    return base
+
+
 # ---------------------------------------------------------------------------
 # The five workloads
 # ---------------------------------------------------------------------------
