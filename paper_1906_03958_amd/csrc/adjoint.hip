@@ -672,11 +672,18 @@ __global__ __launch_bounds__(256) void adjoint_finalize(FinArgs f)
 struct AdjWork {
     double *ws = nullptr;
     size_t ws_bytes = 0;
+    double *ws2 = nullptr;          // second stage-record buffer (pipelined calls)
+    size_t ws2_bytes = 0;
     float *gacc = nullptr;
     size_t gacc_bytes = 0;
     int64_t *goff = nullptr;
     double *astate = nullptr;
     size_t astate_bytes = 0;
+    // pipelined calls: the recomputation's stream and the events that order
+    // it against the caller's stream
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_rec[2] = {nullptr, nullptr}, ev_con[2] = {nullptr, nullptr};
 };
 
 static psst_status ensure(void **p, size_t *have, size_t need)
@@ -880,12 +887,102 @@ static psst_status adjoint_launch(const AdjPlan &P, int32_t n, const InstDesc *d
     return PSST_OK;
 }
 
+// The same call with segment s - 1's recomputation (on the work's own
+// stream, from the lean recomputation: a launch that needs little LDS) beside
+// segment s's reverse sweep (on the caller's stream, with the LDS the
+// recomputation leaves): stage records alternate between two workspaces by
+// segment parity; the reverse sweep of a segment waits for its
+// recomputation, and a recomputation waits for the contraction that last
+// read its workspace.  The same kernels' arithmetic as adjoint_launch.
+static psst_status adjoint_launch_pipe(const AdjPlan &P, int32_t n, const InstDesc *d_desc,
+                                       int64_t nt, AdjWork *W, const RecomputeFn &recompute,
+                                       const float *ckpt, int32_t K, const psst_stimulus *stim,
+                                       float dt, int64_t n_steps, int64_t step0,
+                                       const float *dLdV, float *grad_g, float *gna, float *gk,
+                                       float *gl, int32_t per_instance, int32_t *flag,
+                                       const Tab &tab, hipStream_t st)
+{
+    if (P.lds > 65536) {
+        HIPCHK(hipFuncSetAttribute(P.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds));
+        HIPCHK(hipFuncSetAttribute(P.fn_con, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)P.lds));
+    }
+    AdjArgs a{};
+    a.desc = d_desc;
+    a.ckpt = ckpt;
+    a.K = K;
+    a.nt = nt;
+    if (stim) {
+        a.stim.i_const = stim->i_const_nA;
+        a.stim.pulse_ptr = stim->pulse_ptr;
+        a.stim.on_step = stim->on_step;
+        a.stim.off_step = stim->off_step;
+        a.stim.amp = stim->amp_nA;
+    }
+    a.dt = (double)dt;
+    a.n_steps = n_steps;
+    a.step0 = step0;
+    a.dLdV = dLdV;
+    a.ws_stride = P.wstride;
+    a.gacc = W->gacc;
+    a.gacc_stride = P.gstride;
+    a.lds_bytes = (int64_t)P.lds;
+    a.flag = flag;
+    a.tab = tab;
+    a.adj_state = W->astate;
+    a.adj_stride = P.astride;
+    if (const char *e = std::getenv("PSST_ADJ_MODE")) a.mode = std::strcmp(e, "lacc") == 0 ? 1 : 0;
+    double *wsb[2] = {W->ws, W->ws2};
+    hipStream_t aux = W->aux;
+    HIPCHK(hipEventRecord(W->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(aux, W->ev_fork, 0));
+    const int64_t nseg = (n_steps + K - 1) / K;
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int par = (int)(seg & 1);
+        const int64_t s0 = seg * K;
+        const int64_t L = std::min<int64_t>(K, n_steps - s0);
+        // recomputation of seg into wsb[par], after the contraction of seg + 2
+        if (seg + 2 <= nseg - 1) HIPCHK(hipStreamWaitEvent(aux, W->ev_con[par], 0));
+        psst_status s =
+            recompute(ckpt + seg * 14 * nt, step0 + s0, L, wsb[par], P.wstride, K, aux);
+        if (s != PSST_OK) return s;
+        HIPCHK(hipEventRecord(W->ev_rec[par], aux));
+        // reverse sweep and contraction of seg on the caller's stream
+        HIPCHK(hipStreamWaitEvent(st, W->ev_rec[par], 0));
+        a.ws = wsb[par];
+        a.seg = seg;
+        a.first = seg == nseg - 1;
+        void *args[] = {&a};
+        HIPCHK(hipLaunchKernel(P.fn, dim3(n), dim3(P.bs), args, P.lds, st));
+        HIPCHK(hipLaunchKernel(P.fn_con, dim3(n), dim3(P.bs), args, P.lds, st));
+        HIPCHK(hipEventRecord(W->ev_con[par], st));
+    }
+    HIPCHK(hipEventRecord(W->ev_join, aux));
+    HIPCHK(hipStreamWaitEvent(st, W->ev_join, 0));
+    FinArgs f{};
+    f.desc = d_desc;
+    f.n_inst = n;
+    f.gacc = W->gacc;
+    f.gacc_stride = P.gstride;
+    f.goff = W->goff;
+    f.grad_g = grad_g;
+    f.gna = gna;
+    f.gk = gk;
+    f.gl = gl;
+    f.per_instance = per_instance;
+    void *fargs[] = {&f};
+    HIPCHK(hipLaunchKernel((const void *)adjoint_finalize, dim3(per_instance ? n : 1), dim3(256),
+                           fargs, 0, st));
+    return PSST_OK;
+}
+
 psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
                         int64_t nt, AdjWork **work, const RecomputeFn &recompute,
                         const float *ckpt, int32_t K, const psst_stimulus *stim, float dt,
                         int64_t n_steps, int64_t step0, const float *dLdV, float *grad_g,
                         float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
-                        size_t lds_max, bool gen, const Tab &tab, void *stream)
+                        size_t lds_max, bool gen, const Tab &tab, void *stream,
+                        const RecomputeFn *lean, size_t lean_lds)
 {
     const int32_t n = (int32_t)nets.size();
     AdjPlan P;
@@ -893,8 +990,30 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
     if (s != PSST_OK) return s;
     if (!*work) *work = new AdjWork();
     AdjWork *W = *work;
+    // pipelined when a lean recomputation is offered, the call has two
+    // segments or more and the reverse sweep's buffers fit the LDS the
+    // recomputation leaves (PSST_ADJ_PIPE=0: one stream, as adjoint_launch)
+    const char *pe = std::getenv("PSST_ADJ_PIPE");
+    const bool pipe_ok = lean && !(pe && pe[0] == '0') && n_steps > K && lean_lds < lds_max;
+    AdjPlan PP;
+    bool pipe = false;
+    if (pipe_ok && adjoint_plan(nets, K, lds_max - lean_lds, gen, &PP) == PSST_OK) pipe = true;
     if ((s = ensure((void **)&W->ws, &W->ws_bytes, sizeof(double) * P.wstride * n)) != PSST_OK)
         return s;
+    if (pipe) {
+        if ((s = ensure((void **)&W->ws2, &W->ws2_bytes, sizeof(double) * P.wstride * n)) !=
+            PSST_OK)
+            return s;
+        if (!W->aux) {
+            HIPCHK(hipStreamCreateWithFlags(&W->aux, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&W->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&W->ev_join, hipEventDisableTiming));
+            for (int k = 0; k < 2; ++k) {
+                HIPCHK(hipEventCreateWithFlags(&W->ev_rec[k], hipEventDisableTiming));
+                HIPCHK(hipEventCreateWithFlags(&W->ev_con[k], hipEventDisableTiming));
+            }
+        }
+    }
     if ((s = ensure((void **)&W->gacc, &W->gacc_bytes, sizeof(float) * P.gstride * n)) != PSST_OK)
         return s;
     if ((s = ensure((void **)&W->astate, &W->astate_bytes, sizeof(double) * P.astride * n)) !=
@@ -904,6 +1023,9 @@ psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc 
     hipStream_t st = (hipStream_t)stream;
     grad_offsets_kernel<<<dim3(1), dim3(256), 0, st>>>(d_desc, n, W->goff);
     HIPCHK(hipGetLastError());
+    if (pipe)
+        return adjoint_launch_pipe(PP, n, d_desc, nt, W, *lean, ckpt, K, stim, dt, n_steps, step0,
+                                   dLdV, grad_g, gna, gk, gl, per_instance, flag, tab, st);
     return adjoint_launch(P, n, d_desc, nt, W->ws, W->gacc, W->goff, W->astate, recompute, ckpt,
                           K, stim, dt, n_steps, step0, dLdV, grad_g, gna, gk, gl, per_instance,
                           flag, tab, st);
@@ -986,6 +1108,14 @@ psst_status adjoint_run_noalloc(const std::vector<psst_network *> &nets, const I
 void adjoint_free(AdjWork *w)
 {
     if (!w) return;
+    if (w->aux) {
+        (void)hipStreamSynchronize(w->aux);
+        (void)hipStreamDestroy(w->aux);
+    }
+    for (hipEvent_t e : {w->ev_fork, w->ev_join, w->ev_rec[0], w->ev_rec[1], w->ev_con[0],
+                         w->ev_con[1]})
+        if (e) (void)hipEventDestroy(e);
+    (void)hipFree(w->ws2);
     (void)hipFree(w->ws);
     (void)hipFree(w->gacc);
     (void)hipFree(w->goff);

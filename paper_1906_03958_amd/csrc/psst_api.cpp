@@ -669,6 +669,7 @@ static void batch_free(psst_batch *b)
 {
     if (!b) return;
     for (auto &g : b->groups) (void)hipFree(g.d_order);
+    (void)hipFree(b->lean.d_order);
     (void)hipFree(b->d_desc);
     (void)hipFree(b->d_flag);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1423,6 +1424,58 @@ static RecomputeFn batch_recompute(psst_batch *b, const psst_stimulus *stim, flo
     };
 }
 
+// The adjoint's lean recomputation: every instance in one launch of a
+// per-instance variant (no lane-group kernel, no register columns) with only
+// the activation and partial-sum buffers in LDS -- the conductances stream
+// from L2 -- so that it fits on a compute unit beside the reverse sweep.  Its
+// sums follow the same column order as every other mapping (same bits).
+static psst_status ensure_lean(psst_batch *b)
+{
+    Group &g = b->lean;
+    if (g.d_order) return PSST_OK;
+    g = Group{};
+    for (const Group &t : b->groups) g.order.insert(g.order.end(), t.order.begin(), t.order.end());
+    std::stable_sort(g.order.begin(), g.order.end(), [&](int32_t x, int32_t y) {
+        return b->nets[x]->g_floats > b->nets[y]->g_floats;
+    });
+    size_t need = 0;
+    for (int32_t k : g.order) {
+        const psst_network *q = b->nets[k];
+        g.max_n = std::max(g.max_n, q->n);
+        g.max_ld = std::max(g.max_ld, q->ld);
+        need = std::max(need, wg_lds_bytes(false, q->ld, q->nch, 0));
+    }
+    g.lds = need;
+    default_shape(g.max_n, &g.bs, &g.npt);
+    if (!find_variant(g.bs, g.npt, false) || !find_variant(g.bs, g.npt, true))
+        return fail(PSST_ERR_UNSUPPORTED, "no kernel variant for the adjoint's recomputation");
+    int32_t *d = nullptr;
+    HIPCHK(hipMalloc(&d, sizeof(int32_t) * g.order.size()));
+    hipError_t e = hipMemcpy(d, g.order.data(), sizeof(int32_t) * g.order.size(),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(PSST_ERR_DEVICE, "hipMemcpy failed: %s", hipGetErrorString(e));
+    }
+    g.d_order = d;
+    return PSST_OK;
+}
+
+static RecomputeFn batch_recompute_lean(psst_batch *b, const psst_stimulus *stim, float dt)
+{
+    return [b, stim, dt](const float *ckpt_row, int64_t step0, int64_t n_steps, double *stash,
+                         int64_t stash_stride, int32_t K, hipStream_t s) -> psst_status {
+        const Group &g = b->lean;
+        WGArgs a = group_args(b, g, nullptr, stim, dt, n_steps, step0, nullptr, nullptr, 1);
+        a.state_in = ckpt_row;
+        a.store_state = 0;
+        a.stash = stash;
+        a.stash_stride = stash_stride;
+        a.stash_K = K;
+        return launch_group(g, b->gen, a, s);
+    };
+}
+
 extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
                                     const psst_stimulus *stim, float dt, int64_t n_steps,
                                     int64_t step0, const float *dLdV, float *grad_g,
@@ -1440,10 +1493,17 @@ extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
         return fail(PSST_ERR_INVALID_ARGUMENT, "summed gradients need every instance to share one network");
     if (b->stage_path)
         return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available on the per-stage path");
+    const int64_t max_n = b->nets.empty() ? 0 : (*std::max_element(
+        b->nets.begin(), b->nets.end(),
+        [](const psst_network *x, const psst_network *y) { return x->n < y->n; }))->n;
+    if (max_n <= 512 && (s = ensure_lean(b)) != PSST_OK) return s;
+    const RecomputeFn lean = batch_recompute_lean(b, stim, dt);
     return adjoint_run(b->nets, b->d_desc, b->nt, &b->adj, batch_recompute(b, stim, dt), ckpt, K,
                        stim, dt, n_steps,
                        step0, dLdV, grad_g, grad_gNa, grad_gK, grad_gL, per_instance, b->d_flag,
-                       max_lds_per_block(), b->gen, b->tab, stream);
+                       max_lds_per_block(), b->gen, b->tab, stream,
+                       b->lean.d_order ? &lean : nullptr,
+                       ((b->lean.lds + 4095) & ~(size_t)4095) + 4096);
 }
 
 extern "C" psst_status psst_adjoint_noalloc(psst_batch *b, const float *ckpt, int32_t K,

@@ -101,6 +101,9 @@ struct psst_batch {
     std::vector<hipGraphNode_t> nodes;
     std::vector<WGArgs> node_args;
     AdjWork *adj = nullptr;         // adjoint workspace, sized on first use
+    Group lean;                     // every instance on a kernel without conductances
+                                    // in LDS (the adjoint's recomputation beside its
+                                    // reverse sweep), made on first use
     StreamBufs *strm = nullptr;     // streaming buffers, sized on first use
     bool gen = false;               // method: classical RK4 unless gen
     psst::Tab tab{};
@@ -122,12 +125,16 @@ typedef std::function<psst_status(const float *ckpt_row, int64_t step0, int64_t 
     RecomputeFn;
 
 // Discrete adjoint over a batch of per-instance networks (adjoint.hip).
+// lean (optional): a recomputation needing at most lean_lds bytes of LDS per
+// workgroup; with it, and two segments or more, a segment's recomputation
+// runs beside the previous segment's reverse sweep (same results).
 psst_status adjoint_run(const std::vector<psst_network *> &nets, const InstDesc *d_desc,
                         int64_t nt, AdjWork **work, const RecomputeFn &recompute,
                         const float *ckpt, int32_t K, const psst_stimulus *stim, float dt,
                         int64_t n_steps, int64_t step0, const float *dLdV, float *grad_g,
                         float *gna, float *gk, float *gl, int32_t per_instance, int32_t *flag,
-                        size_t lds_max, bool gen, const psst::Tab &tab, void *stream);
+                        size_t lds_max, bool gen, const psst::Tab &tab, void *stream,
+                        const RecomputeFn *lean = nullptr, size_t lean_lds = 0);
 void adjoint_free(AdjWork *w);
 // The same with the workspace in the library's per-device scratch array
 // (no allocation); sizes beyond its capacity are refused.
