@@ -1078,7 +1078,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
         typedef std::tuple<std::string, std::vector<size_t>, bool, bool, bool, size_t, bool> PlanKey;
         static std::mutex tune_mu;
         static std::map<Key, std::pair<Shape, Shape>> tune_cache;
-        static std::map<PlanKey, bool> plan_cache;
+        static std::map<PlanKey, int> plan_cache;
         std::vector<Shape> plain(cls.size());
         std::vector<int> todo;
         std::vector<size_t> counts;
@@ -1109,7 +1109,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
                 }
             }
             auto pit = plan_cache.find(pkey);
-            if (pit != plan_cache.end()) plan_cached = pit->second ? 1 : 0;
+            if (pit != plan_cache.end()) plan_cached = pit->second;
         }
         std::vector<Group> cls_plain = cls;
         auto plans_differ = [&]() {
@@ -1171,22 +1171,43 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
             cls_plain[c].npt = plain[c].npt;
             cls_plain[c].slots = 0;
         }
-        bool use_regs = true;
+        // which classes take their register-column choice: greedily, from the
+        // largest class down, a class switches when the whole launch gets
+        // faster by more than half a percent
+        uint32_t mask = 0;
+        auto plan_of = [&](uint32_t m) {
+            std::vector<Group> pick(cls.size());
+            for (size_t c = 0; c < cls.size(); ++c) pick[c] = (m >> c) & 1u ? cls[c] : cls_plain[c];
+            return merge_classes(pick, gl);
+        };
         if (e == hipSuccess && s == PSST_OK && plans_differ()) {
             if (plan_cached >= 0) {
-                use_regs = plan_cached == 1;
+                mask = (uint32_t)plan_cached;
             } else {
-                std::vector<Group> pa = merge_classes(cls, gl), pb = merge_classes(cls_plain, gl);
-                float ta = 0.f, tb = 0.f;
-                s = time_plan(b, pa, scratch, st, &ta);
-                if (s == PSST_OK) s = time_plan(b, pb, scratch, st, &tb);
-                if (s == PSST_OK) {
-                    use_regs = ta < tb;
+                std::vector<Group> p0 = plan_of(0);
+                float best_t = 0.f;
+                s = time_plan(b, p0, scratch, st, &best_t);
+                if (tune_log() && s == PSST_OK)
+                    std::fprintf(stderr, "psst tune: whole launch %.3f ms without register "
+                                         "columns\n", best_t);
+                for (int c = (int)cls.size() - 1; c >= 0 && s == PSST_OK; --c) {
+                    if (cls[c].order.empty() || !cls[c].slots) continue;
+                    const uint32_t trial = mask | (1u << c);
+                    std::vector<Group> pt = plan_of(trial);
+                    float t = 0.f;
+                    s = time_plan(b, pt, scratch, st, &t);
+                    if (s != PSST_OK) break;
                     if (tune_log())
                         std::fprintf(stderr, "psst tune: whole launch %.3f ms with register "
-                                             "columns, %.3f ms without\n", ta, tb);
+                                             "columns for n <= %d too\n", t, cls[c].max_n);
+                    if (t < 0.995f * best_t) {
+                        best_t = t;
+                        mask = trial;
+                    }
+                }
+                if (s == PSST_OK) {
                     std::lock_guard<std::mutex> lock(tune_mu);
-                    plan_cache[pkey] = use_regs;
+                    plan_cache[pkey] = (int)mask;
                 }
             }
         }
@@ -1200,7 +1221,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
             return s;
         }
         BCHK(hipMemset(b->d_flag, 0, sizeof(int32_t)));
-        merged = merge_classes(use_regs ? cls : cls_plain, gl);
+        merged = plan_of(mask);
     } else {
         merged = merge_classes(cls, gl);
     }
