@@ -370,7 +370,7 @@ __global__ __launch_bounds__(256) void init_state_kernel(InitArgs a)
 static const WGVariant kVariants[] = {
     WGV(64, 1), WGV(128, 1), WGV(128, 2), WGV(256, 1), WGV(256, 2), WGV(256, 4), WGV(512, 1),
     WGG(64, 1), WGG(128, 1), WGG(128, 2), WGG(256, 1), WGG(256, 2), WGG(256, 4), WGG(512, 1),
-    WGR(256, 2, 48),
+    WGR(256, 2, 48), WGR(256, 2, 32),
     {kLGThreads, 2, false, true, (const void *)rk4_lg_kernel<false, 2>, 0},
     {kLGThreads, 2, true, true, (const void *)rk4_lg_kernel<true, 2>, 0},
     {0, 0, false, false, nullptr, 0},

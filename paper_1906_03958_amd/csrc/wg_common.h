@@ -370,7 +370,7 @@ __device__ __forceinline__ void load_regcols(const RRView v, RegCols<S> &rc)
 // and adds an exact zero, its activation read from the chunk's last column),
 // then its LDS columns, then the streamed rest -- the column-order fma
 // sequence of stage_partials.
-template <int S>
+template <int S, int UG = 8>
 __device__ __forceinline__ void stage_partials_rr(const RRView v, const RegCols<S> &rc)
 {
     constexpr int B = kRegBatch;
@@ -412,7 +412,7 @@ __device__ __forceinline__ void stage_partials_rr(const RRView v, const RegCols<
             chunk_rows4<8>((lds_float4 *)(v.gl + (int64_t)c * v.R * v.ld), ja, v.ld, Xd, ja, jr,
                            v.r4, s0, s1, s2, s3);
         if (j1 > jr)
-            chunk_rows4<8>((global_float4 *)M, 0, v.ld, Xd, jr, j1, v.r4, s0, s1, s2, s3);
+            chunk_rows4<UG>((global_float4 *)M, 0, v.ld, Xd, jr, j1, v.r4, s0, s1, s2, s3);
         typedef __attribute__((address_space(3))) double lds_double_w;
         lds_double_w *pc = (lds_double_w *)(v.part + (size_t)c * v.ld + 4 * v.r4);
         pc[0] = s0; pc[1] = s1; pc[2] = s2; pc[3] = s3;
@@ -484,7 +484,7 @@ __device__ __forceinline__ void syn_sums(const WGSyn &w, const Kin &K, const dou
         bool done = false;
         if constexpr (S > 0) {
             if (w.KC > 0) {
-                stage_partials_rr<S>(rr_view(w), *rc);
+                stage_partials_rr<S, S >= 48 ? 8 : 16>(rr_view(w), *rc);
                 done = true;
             }
         }
