@@ -37,14 +37,53 @@ def stratified(sizes, k):
     return [int(b) for b in order[np.linspace(0, len(sizes) - 1, k).astype(int)]]
 
 
-def _counter_rows(path, kernel_substr, counter):
+def _counter_rows(path, kernel_substr, counter, by_name=False):
     import csv
     out = []
     for r in csv.DictReader(open(path)):
         if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter:
             dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-            out.append((dur, float(r["Counter_Value"])))
+            out.append((r["Kernel_Name"], dur, float(r["Counter_Value"])) if by_name
+                       else (dur, float(r["Counter_Value"])))
     return out
+
+
+def _per_launch(path, kernel_substr, counter):
+    """Counter value of one launch summed over its dispatches.  A batch
+    launches one kernel per launch group (a group is a kernel name and grid
+    size; two groups may run the same kernel); the groups of the run's last
+    launch are the dispatches from the last one back to the first repeated
+    group (the launches are sequential; under counter collection so are a
+    launch's own dispatches).  For each of those groups, the mean over its
+    dispatches within 75 % of its longest (the timed launches, not the
+    tuner's shorter runs of the same group), summed over the groups; groups
+    the tuner alone ran are not in the last launch.  Returns (value,
+    dispatches counted per group)."""
+    import csv
+    disp = []
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"]
+        if kernel_substr not in name or r["Counter_Name"] != counter:
+            continue
+        grid = r.get("Grid_Size") or r.get("Grid_Size_X")
+        t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        disp.append((t0, (name, grid), t1 - t0, float(r["Counter_Value"])))
+    if not disp:
+        return 0.0, 0
+    disp.sort(key=lambda d: d[0])
+    final = set()
+    for _, key, _, _ in reversed(disp):
+        if key in final:
+            break
+        final.add(key)
+    total, n = 0.0, 0
+    for key in final:
+        rows = [(d, v) for _, k, d, v in disp if k == key]
+        longest = max(d for d, _ in rows)
+        vals = [v for d, v in rows if d > 0.75 * longest]
+        total += float(np.mean(vals))
+        n = max(n, len(vals))
+    return total, n
 
 
 # the sources each profiled kernel is compiled from: a counter figure is used
@@ -109,11 +148,11 @@ def write_traffic(args):
     fetch = write = 0.0
     nf = 0
     for kname in KERNEL_NAMES[kernel]:
-        f = _longest(_counter_rows(f_csv, kname, "FETCH_SIZE"))
-        w = _longest(_counter_rows(w_csv, kname, "WRITE_SIZE"))
-        fetch += float(np.mean(f)) * 1024 * kf
-        write += float(np.mean(w)) * 1024 * kw
-        nf = max(nf, len(f))
+        fv, n_f = _per_launch(f_csv, kname, "FETCH_SIZE")
+        wv, _ = _per_launch(w_csv, kname, "WRITE_SIZE")
+        fetch += fv * 1024 * kf
+        write += wv * 1024 * kw
+        nf = max(nf, n_f)
     f = [None] * nf
     out = dict(kernel=kernel, kernel_source_sha=kernel_sha(kernel), **workload_key(args),
                fetch_bytes_per_launch=fetch, write_bytes_per_launch=write,

@@ -1,7 +1,9 @@
 // psst_api.cpp -- host runtime behind the C ABI in include/psst.h: argument
 // validation, device copies of networks, batch packing and scheduling, graph
 // submission and launch-shape tuning.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
+#include <sys/stat.h>
 
 #include <algorithm>
 #include <cmath>
@@ -9,6 +11,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <set>
+#include <sstream>
 #include <map>
 #include <mutex>
 #include <string>
@@ -933,6 +938,119 @@ static std::string device_arch()
     return std::string(prop.gcnArchName);
 }
 
+// ---------------------------------------------------------------------------
+// tuning table: per size class, the chosen variant and the fastest without
+// register columns (with their full-round times); per batch composition, the
+// mask of classes that take register columns.  Kept for the process and read
+// from (PSST_TUNE_WRITE=1: written to) a text file per device architecture,
+// tuning/<arch>.txt beside the library (PSST_TUNE_FILE overrides the path),
+// so that a shipped table makes the choices without timing runs.
+// ---------------------------------------------------------------------------
+
+typedef std::tuple<std::string, int, bool, bool, bool, size_t, bool> TuneKey;
+typedef std::tuple<std::string, std::vector<size_t>, bool, bool, bool, size_t, bool> PlanKey;
+struct ClassChoice {
+    Shape best, plain;
+    float t_best, t_plain;          // ms of a full round of the class
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, ClassChoice> g_tune_cache;
+static std::map<PlanKey, int> g_plan_cache;
+static std::set<std::string> g_tables_read;
+
+static std::string tune_table_path(const std::string &arch)
+{
+    if (const char *e = std::getenv("PSST_TUNE_FILE")) return e;
+    Dl_info info;
+    if (!dladdr((void *)&psst_version, &info) || !info.dli_fname) return std::string();
+    const std::string lib(info.dli_fname);
+    const size_t slash = lib.rfind('/');
+    const std::string dir = slash == std::string::npos ? std::string(".") : lib.substr(0, slash);
+    return dir + "/tuning/" + arch.substr(0, arch.find(':')) + ".txt";
+}
+
+// Read the table of arch into the caches once per process (caller holds
+// g_tune_mu).  Lines:
+//   class <arch> <class> <gen> <sparse> <gabab> <lds> <rr> <bs> <npt> <slots>
+//         <plain bs> <plain npt> <t_best ms> <t_plain ms>
+//   plan <arch> <gen> <sparse> <gabab> <lds> <rr> <mask> <n> <count_0> .. <count_n-1>
+// '#' starts a comment line; malformed lines are skipped.
+static void read_tune_table(const std::string &arch)
+{
+    if (!g_tables_read.insert(arch).second) return;
+    const std::string path = tune_table_path(arch);
+    if (path.empty()) return;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream ss(line);
+        std::string kind, a;
+        if (!(ss >> kind >> a) || kind[0] == '#' || a != arch) continue;
+        int gen, sparse, gabab, rr;
+        size_t lds;
+        if (kind == "class") {
+            int c;
+            ClassChoice ch;
+            if (!(ss >> c >> gen >> sparse >> gabab >> lds >> rr >> ch.best.bs >> ch.best.npt >>
+                  ch.best.slots >> ch.plain.bs >> ch.plain.npt >> ch.t_best >> ch.t_plain))
+                continue;
+            ch.plain.slots = 0;
+            g_tune_cache[TuneKey{arch, c, gen != 0, sparse != 0, gabab != 0, lds, rr != 0}] = ch;
+        } else if (kind == "plan") {
+            int mask;
+            size_t nc;
+            if (!(ss >> gen >> sparse >> gabab >> lds >> rr >> mask >> nc) || nc > 64) continue;
+            std::vector<size_t> counts(nc);
+            bool ok = true;
+            for (size_t k = 0; k < nc && ok; ++k) ok = (bool)(ss >> counts[k]);
+            if (ok)
+                g_plan_cache[PlanKey{arch, counts, gen != 0, sparse != 0, gabab != 0, lds,
+                                     rr != 0}] = mask;
+        }
+    }
+}
+
+// Write the caches' entries of arch to its table (caller holds g_tune_mu).
+static void write_tune_table(const std::string &arch)
+{
+    const std::string path = tune_table_path(arch);
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+    const std::string tmp = path + ".tmp";
+    {
+        std::ofstream out(tmp);
+        if (!out) return;
+        out << "# psst batch tuning table (written with PSST_TUNE_WRITE=1)\n";
+        for (const auto &kv : g_tune_cache) {
+            const TuneKey &k = kv.first;
+            if (std::get<0>(k) != arch) continue;
+            const ClassChoice &ch = kv.second;
+            out << "class " << arch << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' '
+                << std::get<3>(k) << ' ' << std::get<4>(k) << ' ' << std::get<5>(k) << ' '
+                << std::get<6>(k) << ' ' << ch.best.bs << ' ' << ch.best.npt << ' '
+                << ch.best.slots << ' ' << ch.plain.bs << ' ' << ch.plain.npt << ' '
+                << ch.t_best << ' ' << ch.t_plain << '\n';
+        }
+        for (const auto &kv : g_plan_cache) {
+            const PlanKey &k = kv.first;
+            if (std::get<0>(k) != arch) continue;
+            out << "plan " << arch << ' ' << std::get<2>(k) << ' ' << std::get<3>(k) << ' '
+                << std::get<4>(k) << ' ' << std::get<5>(k) << ' ' << std::get<6>(k) << ' '
+                << kv.second << ' ' << std::get<1>(k).size();
+            for (size_t c : std::get<1>(k)) out << ' ' << c;
+            out << '\n';
+        }
+    }
+    (void)std::rename(tmp.c_str(), path.c_str());
+}
+
+static bool tune_write()
+{
+    const char *e = std::getenv("PSST_TUNE_WRITE");
+    return e && e[0] == '1';
+}
+
 extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, psst_batch **out)
 {
     if (!out) return fail(PSST_ERR_INVALID_ARGUMENT, "out is NULL");
@@ -1084,15 +1202,11 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     std::vector<Group> merged;
     if (tune) {
         const std::string arch = device_arch();
-        typedef std::tuple<std::string, int, bool, bool, bool, size_t, bool> Key;
-        typedef std::tuple<std::string, std::vector<size_t>, bool, bool, bool, size_t, bool> PlanKey;
-        static std::mutex tune_mu;
-        struct ClassChoice {
-            Shape best, plain;
-            float t_best, t_plain;      // ms of a full round of the class
-        };
-        static std::map<Key, ClassChoice> tune_cache;
-        static std::map<PlanKey, int> plan_cache;
+        typedef TuneKey Key;
+        std::mutex &tune_mu = g_tune_mu;
+        std::map<TuneKey, ClassChoice> &tune_cache = g_tune_cache;
+        std::map<PlanKey, int> &plan_cache = g_plan_cache;
+        bool wrote = false;             // new entries to put in the table
         std::vector<Shape> plain(cls.size());
         std::vector<float> t_best(cls.size(), 0.f), t_plain(cls.size(), 0.f);
         std::vector<int> todo;
@@ -1103,6 +1217,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
         int plan_cached = -1;
         {
             std::lock_guard<std::mutex> lock(tune_mu);
+            read_tune_table(arch);
             for (int c = 0; c < kNumClasses; ++c) {
                 Group &t = cls[c];
                 if (t.order.empty()) continue;
@@ -1187,6 +1302,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
                     const Group &t = cls[c];
                     tune_cache[Key{arch, c, b->gen, any_sparse, any_gabab, glds, rr_enabled()}] =
                         ClassChoice{Shape{t.bs, t.npt, t.slots}, plain[c], t_best[c], t_plain[c]};
+                    wrote = true;
                 }
             }
         }
@@ -1233,6 +1349,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
                 if (s == PSST_OK) {
                     std::lock_guard<std::mutex> lock(tune_mu);
                     plan_cache[pkey] = (int)mask;
+                    wrote = true;
                 }
             }
         }
@@ -1246,6 +1363,10 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
             return s;
         }
         BCHK(hipMemset(b->d_flag, 0, sizeof(int32_t)));
+        if (wrote && tune_write()) {
+            std::lock_guard<std::mutex> lock(tune_mu);
+            write_tune_table(arch);
+        }
         merged = plan_of(mask);
     } else {
         merged = merge_classes(cls, gl);

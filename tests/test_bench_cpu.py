@@ -38,3 +38,33 @@ def test_recorded_rooflines_are_fractions_of_the_peak():
         assert 0.0 < frac <= 1.0, (traffic, frac)
     ms = _avg_ms("rk4_wg_kernel_batched_4096.md", "rk4_wg_kernel<512")
     assert 0.0 < 392.6e9 / (ms / 1e3) / 8e12 <= 1.0
+
+
+def test_per_launch_counters_sum_the_kernels_of_a_launch(tmp_path):
+    """A batch launches one kernel per launch group (a kernel name and grid;
+    two groups may share a kernel): a launch's counter value is the sum over
+    the groups of the run's last launch of each group's mean over its
+    dispatches near its longest, leaving out the tuner's shorter runs and the
+    groups only the tuner ran."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    ms = 1_000_000        # ns
+    rows = [  # kernel, grid, start, end (ns), value
+        ("k<256, 2, 32>", 256, 1 * ms, 3 * ms, 99.0),      # tuner: one round
+        ("k<512, 1>", 900, 5 * ms, 10 * ms, 99.0),         # tuner: another plan
+        ("k<512, 1>", 700, 20 * ms, 25 * ms, 99.0),        # tuner: plan timing, 50 steps
+        # two launches of three groups (two share a kernel), run one after another
+        ("k<512, 1>", 700, 30 * ms, 40 * ms, 10.0), ("k<512, 1>", 200, 40 * ms, 42 * ms, 3.0),
+        ("k<256, 2, 48>", 100, 42 * ms, 46 * ms, 5.0),
+        ("k<512, 1>", 700, 50 * ms, 60 * ms, 12.0), ("k<512, 1>", 200, 60 * ms, 62 * ms, 3.0),
+        ("k<256, 2, 48>", 100, 62 * ms, 65.9 * ms, 7.0),
+        ("other", 1, 0, 5000 * ms, 1e9)]
+    path = tmp_path / "c.csv"
+    with open(path, "w") as fh:
+        fh.write("Kernel_Name,Grid_Size,Counter_Name,Counter_Value,Start_Timestamp,End_Timestamp\n")
+        for k, g, a, b, v in rows:
+            fh.write(f'"{k}",{g},FETCH_SIZE,{v},{int(a)},{int(b)}\n')
+    total, n = bench._per_launch(str(path), "k<", "FETCH_SIZE")
+    assert total == 11.0 + 3.0 + 6.0 and n == 2

@@ -195,3 +195,19 @@ def test_adjoint_recomputation_with_register_columns_bitwise():
         _say(shape, psst.batch_describe(b), "|g| =", float(np.linalg.norm(grads[shape][0])))
     for x, y in zip(grads[RR], grads[NO_RR]):
         np.testing.assert_array_equal(x, y)
+
+
+def test_tuning_table_is_written_on_request(tmp_path):
+    # a batch whose classes are not in the process's tuning cache (register
+    # columns switched off makes a new key) is tuned, and PSST_TUNE_WRITE=1
+    # writes the cache to the table named by PSST_TUNE_FILE
+    path = tmp_path / "table.txt"
+    insts = [_insts()[k] for k in (0, 4)]
+    nets = [psst.network_create(i.net) for i in insts]
+    with _env(PSST_WG_SHAPE=None, PSST_TUNE=None, PSST_RR="0", PSST_TUNE_WRITE="1",
+              PSST_TUNE_FILE=str(path)):
+        b = psst.batch_create(nets)
+    _say(psst.batch_describe(b))
+    lines = [ln.split() for ln in open(path) if ln.startswith("class ")]
+    assert any(int(t[7]) == 0 for t in lines)          # an entry with register columns off
+    assert all(int(t[10]) == 0 for t in lines if int(t[7]) == 0)
