@@ -673,6 +673,12 @@ extern "C" psst_status psst_network_poll(psst_network *net, void *stream)
 static void batch_free(psst_batch *b)
 {
     if (!b) return;
+    for (hipStream_t st : b->aux) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t e : b->aux_done) (void)hipEventDestroy(e);
+    if (b->aux_fork) (void)hipEventDestroy(b->aux_fork);
     for (auto &g : b->groups) (void)hipFree(g.d_order);
     (void)hipFree(b->lean.d_order);
     (void)hipFree(b->d_desc);
@@ -1556,10 +1562,32 @@ psst_status batch_launch_direct(psst_batch *b, float *states, const psst_stimulu
     if (b->stage_path)        // the per-stage graph: parameters go through its control block
         return stage_batch_integrate(b->stage, states, stim, dt, n_steps, step0, rec, nullptr, 0,
                                      stream);
-    for (auto &g : b->groups) {
-        WGArgs a = group_args(b, g, states, stim, dt, n_steps, step0, rec, nullptr, 1);
-        if ((s = launch_group(g, b->gen, a, (hipStream_t)stream)) != PSST_OK) return s;
+    // the launch groups side by side, as in the graph: the first on the
+    // caller's stream, the others on streams of their own forked from it
+    // and joined back
+    const hipStream_t st = (hipStream_t)stream;
+    const size_t G = b->groups.size();
+    if (G > 1 && b->aux.size() < G - 1) {
+        if (!b->aux_fork) HIPCHK(hipEventCreateWithFlags(&b->aux_fork, hipEventDisableTiming));
+        while (b->aux.size() < G - 1) {
+            hipStream_t a = nullptr;
+            HIPCHK(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+            b->aux.push_back(a);
+            hipEvent_t e = nullptr;
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            b->aux_done.push_back(e);
+        }
     }
+    if (G > 1) HIPCHK(hipEventRecord(b->aux_fork, st));
+    for (size_t k = 0; k < G; ++k) {
+        const Group &g = b->groups[k];
+        const hipStream_t gs = k == 0 ? st : b->aux[k - 1];
+        if (k > 0) HIPCHK(hipStreamWaitEvent(gs, b->aux_fork, 0));
+        WGArgs a = group_args(b, g, states, stim, dt, n_steps, step0, rec, nullptr, 1);
+        if ((s = launch_group(g, b->gen, a, gs)) != PSST_OK) return s;
+        if (k > 0) HIPCHK(hipEventRecord(b->aux_done[k - 1], gs));
+    }
+    for (size_t k = 1; k < G; ++k) HIPCHK(hipStreamWaitEvent(st, b->aux_done[k - 1], 0));
     return PSST_OK;
 }
 

@@ -101,6 +101,11 @@ struct psst_batch {
     std::vector<hipGraphNode_t> nodes;
     std::vector<WGArgs> node_args;
     AdjWork *adj = nullptr;         // adjoint workspace, sized on first use
+    // direct launches (no graph): groups after the first run on streams of
+    // their own, forked from and joined to the caller's stream by events
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> aux_done;
+    hipEvent_t aux_fork = nullptr;
     Group lean;                     // every instance on a kernel without conductances
                                     // in LDS (the adjoint's recomputation beside its
                                     // reverse sweep), made on first use
