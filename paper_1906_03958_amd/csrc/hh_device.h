@@ -188,14 +188,32 @@ __device__ inline double gabab_act_d(double G, const Kin &k)
     return k.hill * k.kd * ipow(G, k.hill - 1) / (den * den);
 }
 
-// f(Y) for one neuron.  gs_* are the synaptic conductance sums already in
-// mS/cm^2 (cg * sum_j g_ij x_j); Iu is the injected current in uA/cm^2.
-__device__ inline void hh_rhs(const double Y[NVAR], const Prm &P, const Kin &K,
-                              double gs_ach, double gs_ga, double gs_gb, double Iu,
-                              bool is_ln, bool gabab, double f[NVAR])
+// The voltage-dependent factors of one neuron's right-hand side: the gate
+// rates and the transmitter release(s) at V.
+struct RateSet {
+    Rates r;
+    double T, TB;
+};
+
+__device__ inline RateSet rate_set(double V, const Kin &K, bool is_ln, bool slow)
+{
+    RateSet rs;
+    rs.r = hh_rates(V);
+    releases(V, K, is_ln, slow, rs.T, rs.TB);
+    return rs;
+}
+
+// f(Y) for one neuron with its voltage-dependent factors rs = rate_set(Y[YV],
+// K, is_ln, is_ln && gabab) already formed (a kernel may form them early, to
+// overlap them with other work).  gs_* are the synaptic conductance sums
+// already in mS/cm^2 (cg * sum_j g_ij x_j); Iu is the injected current in
+// uA/cm^2.
+__device__ inline void hh_rhs_rs(const double Y[NVAR], const Prm &P, const Kin &K,
+                                 double gs_ach, double gs_ga, double gs_gb, double Iu,
+                                 bool is_ln, bool gabab, const RateSet &rs, double f[NVAR])
 {
     const double V = Y[YV], m = Y[YM], h = Y[YH], n = Y[YN], s = Y[YS];
-    const Rates r = hh_rates(V);
+    const Rates &r = rs.r;
     const double m3h = m * m * m * h;
     const double n4 = (n * n) * (n * n);
     const double Iion = P.gNa * m3h * (V - P.ENa) + P.gK * n4 * (V - P.EK) + P.gL * (V - P.EL);
@@ -206,8 +224,7 @@ __device__ inline void hh_rhs(const double Y[NVAR], const Prm &P, const Kin &K,
     f[YN] = r.an * (1.0 - n) - r.bn * n;
     const double a = is_ln ? K.a_ga : K.a_ach;
     const double b = is_ln ? K.b_ga : K.b_ach;
-    double T, TB;
-    releases(V, K, is_ln, is_ln && gabab, T, TB);
+    const double T = rs.T, TB = rs.TB;
     f[YS] = a * T * (1.0 - s) - b * s;
     if (is_ln && gabab) {
         f[YR] = K.r1 * TB * (1.0 - Y[YR]) - K.r2 * Y[YR];
@@ -216,6 +233,15 @@ __device__ inline void hh_rhs(const double Y[NVAR], const Prm &P, const Kin &K,
         f[YR] = 0.0;
         f[YG] = 0.0;
     }
+}
+
+// f(Y) for one neuron (hh_rhs_rs with the factors formed here).
+__device__ inline void hh_rhs(const double Y[NVAR], const Prm &P, const Kin &K,
+                              double gs_ach, double gs_ga, double gs_gb, double Iu,
+                              bool is_ln, bool gabab, double f[NVAR])
+{
+    hh_rhs_rs(Y, P, K, gs_ach, gs_ga, gs_gb, Iu, is_ln, gabab,
+              rate_set(Y[YV], K, is_ln, is_ln && gabab), f);
 }
 
 // Vector-Jacobian product of hh_rhs at Y with cotangent w (dL/df): the

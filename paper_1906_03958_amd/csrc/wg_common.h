@@ -539,13 +539,24 @@ struct NoPost {
     __device__ void operator()(int, const double (&)[NVAR]) const {}
 };
 
-template <int NPT, typename Syn, typename Idx, typename Live, typename Post = NoPost>
+// The voltage-dependent factors of slot k's right-hand side at its stage
+// input; a kernel that formed them earlier returns those (same values).
+struct RatesHere {
+    __device__ RateSet operator()(int, const double (&Yk)[NVAR], const Kin &K, bool is_ln,
+                                  bool gabab) const
+    {
+        return rate_set(Yk[YV], K, is_ln, is_ln && gabab);
+    }
+};
+
+template <int NPT, typename Syn, typename Idx, typename Live, typename Post = NoPost,
+          typename RS = RatesHere>
 __device__ __forceinline__ void rk4_step_core(const Slots &sl, Syn &&syn, Idx &&idx, Live &&live,
                                               const Kin &K, double cgf,
                                               const float (&pr)[NPT][NPRM],
                                               const double (&Iu)[NPT], double dt,
                                               double (&y)[NPT][NVAR], const StageStash *stash,
-                                              Post &&post = Post())
+                                              Post &&post = Post(), RS &&rates = RS())
 {
     double acc[NPT][NVAR];
     double Y[NPT][NVAR];
@@ -572,8 +583,8 @@ __device__ __forceinline__ void rk4_step_core(const Slots &sl, Syn &&syn, Idx &&
                 stash->sS[(q * 3 + 2) * stash->ld + i] = sb[k];
             }
             double f[NVAR];
-            hh_rhs(Y[k], prm_of(pr[k]), K, cgf * sa[k], cgf * sg[k], cgf * sb[k], Iu[k],
-                   i >= sl.n_pn, sl.gabab, f);
+            hh_rhs_rs(Y[k], prm_of(pr[k]), K, cgf * sa[k], cgf * sg[k], cgf * sb[k], Iu[k],
+                      i >= sl.n_pn, sl.gabab, rates(k, Y[k], K, i >= sl.n_pn, sl.gabab), f);
             const double wq = (q == 0 || q == 3) ? 1.0 : 2.0;
             const double c = (q == 2) ? dt : 0.5 * dt;
 #pragma unroll
@@ -605,13 +616,15 @@ __device__ __forceinline__ void rk4_step_core(const Slots &sl, Syn &&syn, Idx &&
 // stored float32 pair.  The stage loop is unrolled so the earlier k stay in
 // registers; T.s is the same for the whole workgroup, so the barriers inside
 // the synaptic sums are reached by every thread.
-template <int NPT, typename Syn, typename Idx, typename Live, typename Post = NoPost>
+template <int NPT, typename Syn, typename Idx, typename Live, typename Post = NoPost,
+          typename RS = RatesHere>
 __device__ __forceinline__ void rk_step_core_tab(const Slots &sl, Syn &&syn, Idx &&idx,
                                                  Live &&live, const Kin &K, double cgf,
                                                  const float (&pr)[NPT][NPRM],
                                                  const double (&Iu)[NPT], double dt,
                                                  double (&y)[NPT][NVAR], const StageStash *stash,
-                                                 const Tab &T, Post &&post = Post())
+                                                 const Tab &T, Post &&post = Post(),
+                                                 RS &&rates = RS())
 {
     double inc[NPT][NVAR];
     double kq[3][NPT][NVAR];
@@ -654,8 +667,8 @@ __device__ __forceinline__ void rk_step_core_tab(const Slots &sl, Syn &&syn, Idx
                 stash->sS[(q * 3 + 2) * stash->ld + i] = sb[k];
             }
             double f[NVAR];
-            hh_rhs(Y[k], prm_of(pr[k]), K, cgf * sa[k], cgf * sg[k], cgf * sb[k], Iu[k],
-                   i >= sl.n_pn, sl.gabab, f);
+            hh_rhs_rs(Y[k], prm_of(pr[k]), K, cgf * sa[k], cgf * sg[k], cgf * sb[k], Iu[k],
+                      i >= sl.n_pn, sl.gabab, rates(k, Y[k], K, i >= sl.n_pn, sl.gabab), f);
 #pragma unroll
             for (int v = 0; v < NVAR; ++v) {
                 inc[k][v] += T.b[q] * f[v];
