@@ -355,6 +355,30 @@ psst_status psst_adjoint_noalloc(psst_batch *batch, const float *checkpoints, in
  * occupies in grad_g. */
 psst_status psst_network_grad_size(const psst_network *net, int64_t *n_entries);
 
+/* New values of the parameters psst_adjoint differentiates, written into the
+ * network's device storage where it lies, so that a descent loop keeps one
+ * network and its batches instead of creating them again at every step (the
+ * network is a computational graph built once and then evaluated with new
+ * values, "Brain simulations as computational graphs"; the graph is fixed
+ * before it runs, "Circumventing memory constraints", item 3).
+ *   g: device [psst_network_grad_size] float32 in grad_g's layout (the
+ *     pathway blocks in pathway order, each [post x pre] row-major), or NULL
+ *     to keep the synaptic values; entries where the network has no synapse
+ *     (mask 0 at creation) are ignored and stay zero;
+ *   g_Na, g_K, g_L: device [n] float32 each (mS/cm^2), or NULL to keep.
+ * Sizes, pathways, masks and storage stay those given to
+ * psst_network_create; every storage the network keeps (dense, sparse rows,
+ * the per-stage layout) is rewritten, so later integrate and adjoint calls
+ * on the network, and on batches created from it before or after, use the
+ * new values, bit for bit as a network created with them would.
+ * Asynchronous: one kernel on hip_stream; allocates nothing and copies
+ * nothing from the host.  Work on other streams that reads the network must
+ * be ordered with it by the caller.  Values are not checked: non-finite ones
+ * give non-finite states, which the polls report.
+ * Errors: INVALID_ARGUMENT (NULL network), DEVICE. */
+psst_status psst_network_update(psst_network *net, const float *g, const float *g_Na,
+                                const float *g_K, const float *g_L, void *hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Long runs streamed to host memory                                        */
 /* ------------------------------------------------------------------------ */

@@ -7,6 +7,12 @@ forward  -> psst_integrate_batch with checkpoints every K steps, V every step
 backward -> psst_adjoint (discrete adjoint of the RK4 map, or of the explicit
             method given as a tableau, summed over trials)
 
+The network and its batch are created on the first call and kept: later
+calls write the new conductances into them in place (psst_network_update).
+A network whose values an autograd graph may still differentiate is not
+overwritten; a call made while one is held takes another network (created
+once, then reused alike).
+
 All arithmetic happens in the HIP library; this module only marshals tensors.
 """
 from __future__ import annotations
@@ -18,6 +24,25 @@ import numpy as np
 import torch
 
 from . import psst
+
+
+class _Slot:
+    """A network of the simulation's trials and its batch; held while an
+    autograd context that read its values is alive."""
+
+    def __init__(self, net, batch):
+        self.net, self.batch, self.held = net, batch, False
+
+
+class _Lease:
+    """Holds a slot for the lifetime of the autograd context it is stored on."""
+
+    def __init__(self, slot):
+        self.slot = slot
+        slot.held = True
+
+    def __del__(self):
+        self.slot.held = False
 
 
 class TraceSimulation:
@@ -38,6 +63,7 @@ class TraceSimulation:
         self.stim = psst.DeviceStimulus(
             torch.from_numpy(np.ascontiguousarray(i_nA, np.float32).ravel()).to(self.dev))
         self.v0 = torch.from_numpy(np.ascontiguousarray(v0, np.float32).ravel()).to(self.dev)
+        self._slots: List[_Slot] = []
 
     def pack(self, blocks: List) -> torch.Tensor:
         return torch.cat([torch.as_tensor(b, dtype=torch.float32).reshape(-1) for b in blocks])
@@ -57,6 +83,24 @@ class TraceSimulation:
             net.params[k] = t.detach().to("cpu", torch.float32).numpy().copy()
         return net
 
+    def _dev32(self, t) -> torch.Tensor:
+        return t.detach().to(self.dev, torch.float32).contiguous()
+
+    def acquire(self, g_flat, g_na, g_k, g_l) -> _Slot:
+        """A network holding these values, and its batch: a free kept one with
+        the values written in place, else a new one."""
+        for slot in self._slots:
+            if not slot.held:
+                psst.network_update(slot.net, self._dev32(g_flat), self._dev32(g_na),
+                                    self._dev32(g_k), self._dev32(g_l))
+                return slot
+        net = psst.network_create(self.build(g_flat, g_na, g_k, g_l))
+        if self.tableau is not None:
+            psst.network_set_tableau(net, self.tableau)
+        slot = _Slot(net, psst.batch_create([net] * self.B))
+        self._slots.append(slot)
+        return slot
+
     def __call__(self, g_flat, g_na, g_k, g_l) -> torch.Tensor:
         return PsstTraceFn.apply(self, g_flat, g_na, g_k, g_l)
 
@@ -64,10 +108,8 @@ class TraceSimulation:
 class PsstTraceFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, sim: TraceSimulation, g_flat, g_na, g_k, g_l):
-        net = psst.network_create(sim.build(g_flat, g_na, g_k, g_l))
-        if sim.tableau is not None:
-            psst.network_set_tableau(net, sim.tableau)
-        batch = psst.batch_create([net] * sim.B)
+        slot = sim.acquire(g_flat, g_na, g_k, g_l)
+        net, batch = slot.net, slot.batch
         nt = batch.n_total
         states = torch.zeros(14 * nt, dtype=torch.float32, device=sim.dev)
         psst.batch_state_init(batch, sim.v0, states)
@@ -79,6 +121,7 @@ class PsstTraceFn(torch.autograd.Function):
         psst.batch_poll(batch)
         ctx.sim = sim
         ctx.net, ctx.batch, ctx.ckpt = net, batch, ckpt
+        ctx.lease = _Lease(slot)
         ctx.devs = (g_flat.device, g_na.device, g_k.device, g_l.device)
         return v
 

@@ -16,7 +16,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsst.so")
-SOURCES = ["psst_api.cpp", "streaming.cpp", "rk4_wg.hip", "stage.hip", "adjoint.hip"]
+SOURCES = ["psst_api.cpp", "streaming.cpp", "rk4_wg.hip", "stage.hip", "adjoint.hip", "network.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

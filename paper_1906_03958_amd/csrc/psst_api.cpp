@@ -94,6 +94,8 @@ static void net_free(psst_network *n)
     (void)hipFree(n->d_paths);
     (void)hipFree(n->d_spcol);
     (void)hipFree(n->d_spval);
+    (void)hipFree(n->d_spslot);
+    (void)hipFree(n->d_gbits);
     stage_batch_free(n->single);
     stage_net_free(n->stage);
     delete n;
@@ -204,6 +206,21 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
         else
             for (int64_t e = 0; e < cnt; ++e) present += w.mask[e] != 0;
     }
+    // which gradient-layout entries are synapses, for in-place updates
+    // (only when some pathway has a mask)
+    std::vector<uint32_t> gbits;
+    if (present < goff) {
+        gbits.assign((size_t)((goff + 31) / 32), 0u);
+        for (int q = 0; q < np; ++q) {
+            const psst_pathway &w = paths[q];
+            const int64_t cnt = (int64_t)(w.post_end - w.post_begin) * (w.pre_end - w.pre_begin);
+            for (int64_t e = 0; e < cnt; ++e)
+                if (!w.mask || w.mask[e]) {
+                    const int64_t ge = net->paths[q].grad_off + e;
+                    gbits[(size_t)(ge >> 5)] |= 1u << (ge & 31);
+                }
+        }
+    }
     bool sparse = false;
     if (storage == PSST_STORAGE_SPARSE) {
         if (n > kMaxWGNeurons) {
@@ -215,11 +232,18 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
     } else if (storage == PSST_STORAGE_AUTO) {
         sparse = np > 0 && n <= kMaxWGNeurons && 4 * present <= goff;
     }
-    std::vector<int32_t> sp_col;
+    std::vector<int32_t> sp_col, sp_slot;
     std::vector<float> sp_val;
     if (sparse) {
-        // ELL rows: per postsynaptic i its synapses sorted by presynaptic column
-        std::vector<std::vector<std::pair<int32_t, float>>> rf(n), rb(n);
+        // ELL rows: per postsynaptic i its synapses sorted by presynaptic
+        // column, each with its entry in the gradient layout (so an in-place
+        // update finds its slot)
+        struct Syn {
+            int32_t col;
+            float g;
+            int64_t e;
+        };
+        std::vector<std::vector<Syn>> rf(n), rb(n);
         for (int q = 0; q < np; ++q) {
             const psst_pathway &w = paths[q];
             const int npre = w.pre_end - w.pre_begin;
@@ -227,33 +251,32 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
                 for (int j = w.pre_begin; j < w.pre_end; ++j) {
                     const int64_t e = (int64_t)(i - w.post_begin) * npre + (j - w.pre_begin);
                     if (w.mask && w.mask[e] == 0) continue;
-                    if (w.type == PSST_SYN_GABA_B) rb[i].push_back({j - p->n_pn, w.g_nS[e]});
-                    else rf[i].push_back({j, w.g_nS[e]});
+                    const int64_t ge = net->paths[q].grad_off + e;
+                    if (w.type == PSST_SYN_GABA_B) rb[i].push_back({j - p->n_pn, w.g_nS[e], ge});
+                    else rf[i].push_back({j, w.g_nS[e], ge});
                 }
         }
+        const auto by_col = [](const Syn &x, const Syn &y) { return x.col < y.col; };
         int kf = 1, kb = net->gabab ? 1 : 0;
         for (int i = 0; i < n; ++i) {
-            std::stable_sort(rf[i].begin(), rf[i].end(),
-                             [](const std::pair<int32_t, float> &x, const std::pair<int32_t, float> &y) {
-                                 return x.first < y.first;
-                             });
-            std::stable_sort(rb[i].begin(), rb[i].end(),
-                             [](const std::pair<int32_t, float> &x, const std::pair<int32_t, float> &y) {
-                                 return x.first < y.first;
-                             });
+            std::stable_sort(rf[i].begin(), rf[i].end(), by_col);
+            std::stable_sort(rb[i].begin(), rb[i].end(), by_col);
             kf = std::max(kf, (int)rf[i].size());
             if (net->gabab) kb = std::max(kb, (int)rb[i].size());
         }
         sp_col.assign((size_t)(kf + kb) * ld, 0);
         sp_val.assign((size_t)(kf + kb) * ld, 0.f);
+        sp_slot.assign((size_t)goff, -1);
         for (int i = 0; i < n; ++i) {
             for (int half = 0; half < 2; ++half) {
                 const auto &r = half ? rb[i] : rf[i];
                 const int k0 = half ? kf : 0, K = half ? kb : kf;
                 for (int e = 0; e < K; ++e) {
                     const bool real = e < (int)r.size();
-                    sp_col[(size_t)(k0 + e) * ld + i] = real ? r[e].first : (r.empty() ? 0 : r.back().first);
-                    sp_val[(size_t)(k0 + e) * ld + i] = real ? r[e].second : 0.f;
+                    const size_t slot = (size_t)(k0 + e) * ld + i;
+                    sp_col[slot] = real ? r[e].col : (r.empty() ? 0 : r.back().col);
+                    sp_val[slot] = real ? r[e].g : 0.f;
+                    if (real) sp_slot[(size_t)r[e].e] = (int32_t)slot;
                 }
             }
         }
@@ -313,6 +336,14 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
                          hipMemcpyHostToDevice));
         NETCHK(hipMalloc(&net->d_spval, sizeof(float) * sp_val.size()));
         NETCHK(hipMemcpy(net->d_spval, sp_val.data(), sizeof(float) * sp_val.size(),
+                         hipMemcpyHostToDevice));
+        NETCHK(hipMalloc(&net->d_spslot, sizeof(int32_t) * sp_slot.size()));
+        NETCHK(hipMemcpy(net->d_spslot, sp_slot.data(), sizeof(int32_t) * sp_slot.size(),
+                         hipMemcpyHostToDevice));
+    }
+    if (!gbits.empty()) {
+        NETCHK(hipMalloc(&net->d_gbits, sizeof(uint32_t) * gbits.size()));
+        NETCHK(hipMemcpy(net->d_gbits, gbits.data(), sizeof(uint32_t) * gbits.size(),
                          hipMemcpyHostToDevice));
     }
     if (dense_wg) {
@@ -423,6 +454,36 @@ extern "C" psst_status psst_network_grad_size(const psst_network *net, int64_t *
     if (!net || !n_entries) return fail(PSST_ERR_INVALID_ARGUMENT, "NULL argument");
     *n_entries = net->grad_entries;
     return PSST_OK;
+}
+
+extern "C" psst_status psst_network_update(psst_network *net, const float *g, const float *g_Na,
+                                           const float *g_K, const float *g_L, void *stream)
+{
+    if (!net) return fail(PSST_ERR_INVALID_ARGUMENT, "network is NULL");
+    psst::NetUpdateArgs a{};
+    a.g = net->grad_entries > 0 ? g : nullptr;
+    a.g_na = g_Na;
+    a.g_k = g_K;
+    a.g_l = g_L;
+    a.paths = net->d_paths;
+    a.present_bits = net->d_gbits;
+    a.entries = net->grad_entries;
+    a.n_paths = (int32_t)net->paths.size();
+    a.n = net->n;
+    a.n_pn = net->n_pn;
+    a.ld = net->ld;
+    a.gt = net->d_gt;
+    a.gtb = net->d_gtb;
+    a.sp_val = net->d_spval;
+    a.sp_slot = net->d_spslot;
+    if (net->stage) {
+        a.stage_G = net->stage->G;
+        a.stage_Kp = net->stage->Kp;
+        a.stage_ka = net->stage->ka;
+        a.stage_kg = net->stage->kg;
+    }
+    a.prm = net->d_prm;
+    return network_update_launch(a, (hipStream_t)stream);
 }
 
 static psst_status launch_init(const InstDesc *d_desc, int32_t n_inst, const float *v0,

@@ -35,6 +35,27 @@ void stream_bufs_free(StreamBufs *s);
 using psst::InstDesc;
 using psst::WGArgs;
 
+namespace psst {
+// Arguments of the in-place conductance update (network.hip): values in the
+// gradient layout scattered into each storage the network keeps (NULL
+// pointers: that storage is absent, or those values are left as they are).
+struct NetUpdateArgs {
+    const float *g;                 // [entries] pathway blocks, or NULL
+    const float *g_na, *g_k, *g_l;  // [n] each, or NULL
+    const int64_t *paths;           // [n_paths][6]: type, pre0, pre1, post0, post1, offset
+    const uint32_t *present_bits;   // bit e: entry e is a synapse (NULL: all are)
+    int64_t entries;
+    int32_t n_paths, n, n_pn, ld;
+    float *gt, *gtb;                // dense transposed matrices
+    float *sp_val;                  // sparse rows and each entry's slot (-1: absent)
+    const int32_t *sp_slot;
+    float *stage_G;                 // per-stage layout [Mp x Kp]
+    int64_t stage_Kp, stage_ka, stage_kg;
+    float *prm;                     // [NPRM][ld]
+};
+}  // namespace psst
+psst_status network_update_launch(const psst::NetUpdateArgs &a, hipStream_t s);
+
 struct PathInfo {
     int32_t type, pre0, pre1, post0, post1;
     int64_t grad_off;   // offset of this block in a grad_g copy
@@ -70,6 +91,10 @@ struct psst_network {
     bool sparse = false;
     int32_t *d_spcol = nullptr;
     float *d_spval = nullptr;
+    // in-place updates: each gradient-layout entry's sparse slot, and which
+    // entries are synapses (NULL when every pathway is dense)
+    int32_t *d_spslot = nullptr;
+    uint32_t *d_gbits = nullptr;
 };
 
 

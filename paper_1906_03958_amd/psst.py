@@ -35,6 +35,7 @@ EXPORTS = (
     "psst_batch_describe", "psst_adjoint", "psst_network_grad_size",
     "psst_network_set_tableau", "psst_batch_set_tableau", "psst_network_create_storage",
     "psst_integrate_batch_streamed", "psst_batch_conductance_bytes", "psst_adjoint_noalloc",
+    "psst_network_update",
 )
 STORAGE_AUTO, STORAGE_DENSE, STORAGE_SPARSE = 0, 1, 2
 
@@ -137,6 +138,7 @@ def lib():
             "psst_batch_conductance_bytes": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
             "psst_adjoint_noalloc": (i32, [vp, vp, i32, C.POINTER(Stimulus), f32, i64, i64, vp,
                                            vp, vp, vp, vp, i32, vp]),
+            "psst_network_update": (i32, [vp, vp, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -240,6 +242,21 @@ def network_create(net, storage: Optional[int] = None) -> Network:
     gs = C.c_int64()
     _check(lib().psst_network_grad_size(h, C.byref(gs)))
     return Network(h, int(net.n), int(net.n_pn), int(gs.value), net)
+
+
+def network_update(net: Network, g=None, g_na=None, g_k=None, g_l=None, stream=None):
+    """psst_network_update: new synaptic blocks (device float32 [grad_size],
+    grad_g's layout) and intrinsic conductances (device float32 [n] each)
+    written into the network's storage in place; None keeps a part."""
+    for t, size, name in ((g, net.grad_size, "g"), (g_na, net.n, "g_na"), (g_k, net.n, "g_k"),
+                          (g_l, net.n, "g_l")):
+        if t is None:
+            continue
+        if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 4
+                and t.is_contiguous() and t.numel() == size):
+            raise ValueError(f"{name}: a contiguous float32 device tensor of {size} entries")
+    _check(lib().psst_network_update(net.handle, _ptr(g), _ptr(g_na), _ptr(g_k), _ptr(g_l),
+                                     _stream(stream)))
 
 
 def network_destroy(net: Network):

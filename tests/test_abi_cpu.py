@@ -177,6 +177,7 @@ def test_null_handles_rejected():
     r, s = C.c_int64(), C.c_int64()
     assert L.psst_batch_conductance_bytes(None, C.byref(r), C.byref(s)) == \
         psst.ERR_INVALID_ARGUMENT
+    assert L.psst_network_update(None, None, None, None, None, None) == psst.ERR_INVALID_ARGUMENT
 
 
 def test_missing_library_fails_loudly(monkeypatch):
