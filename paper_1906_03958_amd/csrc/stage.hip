@@ -5,8 +5,8 @@
 // matrix multiplication):
 //   A[i][b] = sum_k G[i][k] X_q[b][k]      float32 GEMM on the matrix cores,
 //                                          one accumulator set per synapse class;
-//                                          each 16-column group's float32 sum is
-//                                          added to float64 totals
+//                                          each 32-column float32 sum is added
+//                                          to float64 totals
 //   f = rhs(Y_q, cg * A, I(g))             float64, fused epilogue
 //   acc += w_q f; Y_{q+1} = y + c_{q+1} dt f; X_{q+1} = x(Y_{q+1})
 // and at q = 3 the combine y <- y + dt/6 acc, spikes and records.  A generic
@@ -18,14 +18,16 @@
 // conductance is read from HBM once per stage.  Tiles of 128 presynaptic
 // columns are staged through LDS (double-buffered) with the next tile loaded
 // into registers -- 64 KiB in flight per workgroup -- while the current one
-// feeds v_mfma_f32_16x16x4f32.  Within a 16-column group, lane l at sub-step
+// feeds v_mfma_f32_16x16x4f32; the next tile's LDS stores follow the current
+// tile's last products, so they overlap the matrix cores' work in flight,
+// and one barrier per tile separates the buffers' writers and readers.  Within a 16-column group, lane l at sub-step
 // s takes column 4 (l / 16) + s, so each lane reads its four A and four B
 // values with one 16-byte LDS load; the column order of the sum is fixed, so
 // results are deterministic.  A float32 running sum over all K columns would
-// carry a rounding error growing with K (16384 here); each 16-column group
-// therefore starts from zero on the matrix cores (four chained products of
-// four columns) and its sum is added in float64, so float32 rounding acts on
-// 16-term sums of non-negative products only.
+// carry a rounding error growing with K (16384 here); each sum of two
+// 16-column groups therefore starts from zero on the matrix cores (eight
+// chained products of four columns) and is added in float64, so float32
+// rounding acts on 32-term sums of non-negative products only.
 //
 // Between launches the per-(neuron, trial) stage input Y and accumulator acc
 // live in a float64 workspace; activations X are double-buffered float32.
@@ -43,6 +45,10 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int KT = 128;       // presynaptic columns per LDS tile
 constexpr int MT = 64;        // postsynaptic rows per workgroup
 constexpr int LDK = KT + 4;   // LDS row stride in floats
+// 16-column groups per float32 matrix-core sum: each sum of 32 columns starts
+// from zero and is added to the float64 totals
+constexpr int kFoldGroups = 2;
+static_assert((KT / 16) % kFoldGroups == 0, "a fold never spans two tiles");
 
 // Dynamic LDS of a stage launch with NTILE trials per workgroup, in floats:
 // the double-buffered G and X tiles during the products, then the float64
@@ -176,9 +182,7 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
         const int ntile = (kend - kbeg) / KT;
         if (ntile == 0) continue;
         floatx4 rg[GV], rx[XVT];
-        tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, kbeg);
-        __syncthreads();     // previous users of the tile buffers are done
-        for (int t = 0; t < ntile; ++t) {
+        auto tile_store = [&](int t) {
             float *g = sG + (t & 1) * MT * LDK;
             float *x = sX + (t & 1) * NTILE * LDK;
 #pragma unroll
@@ -187,21 +191,35 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
 #pragma unroll
             for (int u = 0; u < XVT; ++u)
                 *reinterpret_cast<floatx4 *>(x + (lr + RPP * u) * LDK + lk) = rx[u];
-            __syncthreads();
-            if (t + 1 < ntile)
-                tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, kbeg + (t + 1) * KT);
+        };
+        // tile t + 1 is loaded into registers while tile t feeds the matrix
+        // cores, and stored to the other LDS buffer right after tile t's last
+        // products are issued (its stores overlap them) and before the one
+        // barrier per tile; the last tile is loaded and stored once more past
+        // the end (in bounds, never read), so every iteration is the same
+        const auto next = [&](int t) { return kbeg + min(t, ntile - 1) * KT; };
+        tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, kbeg);
+        __syncthreads();     // previous users of the tile buffers are done
+        tile_store(0);
+        tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, next(1));
+        __syncthreads();
+        for (int t = 0; t < ntile; ++t) {
+            const float *g = sG + (t & 1) * MT * LDK;
+            const float *x = sX + (t & 1) * NTILE * LDK;
             // ask the scheduler to interleave the LDS operand reads of the next
             // sub-step with the matrix-core instructions of the current one
             // instead of grouping every read ahead of its products
             // (single-wave small-GEMM strategy)
             __builtin_amdgcn_iglp_opt(1);
+            floatx4 tacc[BR][BC];
 #pragma unroll
             for (int kk = 0; kk < KT / 16; ++kk) {
-                floatx4 tacc[BR][BC];
+                if (kk % kFoldGroups == 0) {
 #pragma unroll
-                for (int br = 0; br < BR; ++br)
+                    for (int br = 0; br < BR; ++br)
 #pragma unroll
-                    for (int bc = 0; bc < BC; ++bc) tacc[br][bc] = floatx4{0.f, 0.f, 0.f, 0.f};
+                        for (int bc = 0; bc < BC; ++bc) tacc[br][bc] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
                 floatx4 a[BR], bv[BC];
                 const int kq = kk * 16 + 4 * (lane >> 4);
 #pragma unroll
@@ -222,14 +240,20 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
                         for (int bc = 0; bc < BC; ++bc)
                             tacc[br][bc] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                                 a[br][s], bv[bc][s], tacc[br][bc], 0, 0, 0);
+                if (kk % kFoldGroups == kFoldGroups - 1) {
 #pragma unroll
-                for (int br = 0; br < BR; ++br)
+                    for (int br = 0; br < BR; ++br)
 #pragma unroll
-                    for (int bc = 0; bc < BC; ++bc)
+                        for (int bc = 0; bc < BC; ++bc)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            acc[blk][br][bc][r] += (double)tacc[br][bc][r];
+                            for (int r = 0; r < 4; ++r)
+                                acc[blk][br][bc][r] += (double)tacc[br][bc][r];
+                }
             }
+            // the other buffer was last read before the previous barrier
+            tile_store(t + 1);
+            tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, next(t + 2));
+            __syncthreads();
         }
     }
     __syncthreads();
