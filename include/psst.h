@@ -55,10 +55,11 @@
  * product of a float32 g and a float64 activation is exact before the sum);
  * each state variable is stored as a float32 pair (value, compensation) whose
  * sum is the state after every step, rounded to 48 significant bits.  Large
- * shared networks on the per-stage path (more than 1024 neurons) take the
- * synaptic sums from a float32 matrix-core GEMM instead: float32 activations,
- * float32 sums over groups of 16 presynaptic columns, the group sums added in
- * float64.
+ * shared networks on the per-stage path (more than 1024 neurons) take float32
+ * activations, and with dense storage the synaptic sums from a float32
+ * matrix-core GEMM: float32 sums over groups of 32 presynaptic columns, the
+ * group sums added in float64 (sparse storage sums its exact float32
+ * products in float64).
  */
 #ifndef PSST_H
 #define PSST_H
@@ -141,17 +142,22 @@ psst_status psst_network_create(const psst_neuron_params *params, int32_t n_neur
                                 const psst_kinetics kinetics[3], psst_network **out);
 psst_status psst_network_destroy(psst_network *net);
 
-/* Storage of the conductance matrices on the per-instance path.  DENSE keeps
- * every [post x pre] entry (zeros included) and reads each once per stage;
- * SPARSE keeps, per postsynaptic neuron, its present synapses sorted by
- * presynaptic index ("Circumventing memory constraints", item 1: sparse
- * matrices where connectivity is low), so a stage reads 8 bytes per synapse
- * instead of 4 bytes per matrix entry.  Both sum the products in the same
- * fixed order (64-column chunks in column order, partials in chunk order;
- * absent synapses add exact zeros), so the two give the same trajectory bit
- * for bit.  AUTO picks SPARSE when at most a quarter of the pathway entries
- * are synapses and the network takes the per-instance path.  Networks above
- * 1024 neurons are always dense (per-stage path). */
+/* Storage of the conductance matrices ("Circumventing memory constraints",
+ * item 1: sparse matrices where connectivity is low).  DENSE keeps every
+ * [post x pre] entry (zeros included) and reads each once per stage.
+ * SPARSE, on the per-instance path (at most 1024 neurons), keeps per
+ * postsynaptic neuron its present synapses sorted by presynaptic index, so a
+ * stage reads 8 bytes per synapse instead of 4 bytes per matrix entry; both
+ * sum the products in the same fixed order (64-column chunks in column
+ * order, partials in chunk order; absent synapses add exact zeros), so the
+ * two give the same trajectory bit for bit.  SPARSE above 1024 neurons (the
+ * per-stage path, networks shared by trials) keeps the synapses grouped by
+ * 64-row block and 128-column tile, 5 bytes per synapse read once per stage
+ * and tile of 64 trials; each float32 product is summed in float64 in
+ * column order (a tile's sum added to its class total), which is exact to
+ * float64 rounding rather than bitwise the dense path's float32 matrix-core
+ * sums.  AUTO picks SPARSE when at most a quarter of the pathway entries are
+ * synapses. */
 typedef enum {
     PSST_STORAGE_AUTO = 0,
     PSST_STORAGE_DENSE = 1,
@@ -159,7 +165,7 @@ typedef enum {
 } psst_storage;
 
 /* psst_network_create with a storage choice (psst_network_create = AUTO).
- * SPARSE for a network above 1024 neurons returns UNSUPPORTED.  A sparse
+ * A sparse
  * network of at most 512 neurons (the adjoint's limit) also keeps the dense
  * transposed matrices and the synapse mask on the device (5 bytes per
  * matrix entry) for psst_adjoint's transposed products and gradient mask;

@@ -12,7 +12,8 @@
 //   dense per-instance storage   gt[j * ld + i] (fast GABA and ACh) and
 //                                gtb[(j - n_pn) * ld + i] (slow GABA);
 //   sparse rows                  val[slot(e)] for the entry's ELL slot;
-//   per-stage layout             G[i * Kp + k(type, j)];
+//   per-stage layout             G[i * Kp + k(type, j)], or the synapse
+//                                buckets of its sparse form;
 // absent synapses (mask 0) keep their zero, and the intrinsic vectors go to
 // rows g_Na, g_K, g_L of the parameter table.
 
@@ -51,11 +52,25 @@ __global__ __launch_bounds__(256) void network_update_kernel(psst::NetUpdateArgs
             const int32_t slot = a.sp_slot[e];
             if (slot >= 0) a.sp_val[slot] = v;
         }
-        if (a.stage_G) {
+        if (a.stage_G || a.bk_val) {
             const int64_t k = type == PSST_SYN_ACH ? j
                               : (type == PSST_SYN_GABA_A ? a.stage_ka + (j - a.n_pn)
                                                          : a.stage_ka + a.stage_kg + (j - a.n_pn));
-            a.stage_G[(int64_t)i * a.stage_Kp + k] = v;
+            if (a.stage_G) a.stage_G[(int64_t)i * a.stage_Kp + k] = v;
+            if (a.bk_val && present) {
+                // the synapse's bucket (64-row block, 128-column tile,
+                // wavefront, row) holds ascending columns: binary search
+                const int64_t ntl = a.stage_Kp / 128, il = i % 64;
+                const int64_t bk = (((int64_t)(i / 64) * ntl + k / 128) * 8 + il / 8) * 8 + il % 8;
+                int lo = a.bk_off[bk], hi = a.bk_off[bk + 1];
+                const int c = (int)(k % 128);
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (a.bk_col[mid] < c) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo < a.bk_off[bk + 1] && a.bk_col[lo] == c) a.bk_val[lo] = v;
+            }
         }
     }
 }

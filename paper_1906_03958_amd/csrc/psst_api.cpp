@@ -222,16 +222,12 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
         }
     }
     bool sparse = false;
-    if (storage == PSST_STORAGE_SPARSE) {
-        if (n > kMaxWGNeurons) {
-            delete net;
-            return fail(PSST_ERR_UNSUPPORTED, "sparse storage is for networks of at most %d neurons",
-                        kMaxWGNeurons);
-        }
-        sparse = np > 0;
-    } else if (storage == PSST_STORAGE_AUTO) {
-        sparse = np > 0 && n <= kMaxWGNeurons && 4 * present <= goff;
-    }
+    if (storage == PSST_STORAGE_SPARSE) sparse = np > 0;
+    else if (storage == PSST_STORAGE_AUTO) sparse = np > 0 && 4 * present <= goff;
+    // above the per-instance limit the per-stage path keeps its own sparse
+    // layout (synapse buckets) instead of the ELL rows
+    const bool stage_sparse = sparse && n > kMaxWGNeurons;
+    if (stage_sparse) sparse = false;
     std::vector<int32_t> sp_col, sp_slot;
     std::vector<float> sp_val;
     if (sparse) {
@@ -356,7 +352,7 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
         NETCHK(hipMalloc(&net->d_maskt, mt.size()));
         NETCHK(hipMemcpy(net->d_maskt, mt.data(), mt.size(), hipMemcpyHostToDevice));
     } else if (!wg) {
-        psst_status st = stage_net_create(net, paths, np);
+        psst_status st = stage_net_create(net, paths, np, stage_sparse);
         if (st != PSST_OK) {
             net_free(net);
             return st;
@@ -481,6 +477,9 @@ extern "C" psst_status psst_network_update(psst_network *net, const float *g, co
         a.stage_Kp = net->stage->Kp;
         a.stage_ka = net->stage->ka;
         a.stage_kg = net->stage->kg;
+        a.bk_off = net->stage->sp_off;
+        a.bk_col = net->stage->sp_col;
+        a.bk_val = net->stage->sp_val;
     }
     a.prm = net->d_prm;
     return network_update_launch(a, (hipStream_t)stream);

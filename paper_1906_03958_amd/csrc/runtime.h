@@ -51,6 +51,9 @@ struct NetUpdateArgs {
     const int32_t *sp_slot;
     float *stage_G;                 // per-stage layout [Mp x Kp]
     int64_t stage_Kp, stage_ka, stage_kg;
+    const int32_t *bk_off;          // per-stage sparse layout: synapse buckets
+    const uint8_t *bk_col;
+    float *bk_val;
     float *prm;                     // [NPRM][ld]
 };
 }  // namespace psst

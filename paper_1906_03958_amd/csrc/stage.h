@@ -12,14 +12,28 @@
 // row i, presynaptic column k) in nS, the presynaptic axis cut into padded
 // blocks: cholinergic PN columns [0, ka), fast-GABA LN columns [ka, ka + kg),
 // slow-GABA LN columns [ka + kg, Kp).  Padding rows and columns are zero.
+//
+// Sparse storage keeps, instead of G, the synapses themselves grouped by
+// (64-row block, 128-column tile, wavefront, row): the row block's wavefront
+// w owns its rows 8w .. 8w + 7, and bucket ((rb * ntl + kt) * 8 + w) * 8 + r
+// holds row 64 rb + 8 w + r's synapses in tile kt, by ascending column --
+// sp_off[bucket] .. sp_off[bucket + 1] - 1 index sp_col (the column within
+// the tile) and sp_val (nS).
 struct StageNet {
     float *G = nullptr;
     int n = 0, n_pn = 0, Mp = 0, Kp = 0, ka = 0, kg = 0, kb = 0;
     bool gabab = false;
+    bool sparse = false;
+    int32_t *sp_off = nullptr;
+    uint8_t *sp_col = nullptr;
+    float *sp_val = nullptr;
+    int64_t nnz = 0;
 };
 
-// Build the layout on the device from the (validated) pathways.
-psst_status stage_net_create(psst_network *net, const psst_pathway *paths, int32_t np);
+// Build the layout on the device from the (validated) pathways: dense, or
+// (sparse = true) the synapse buckets.
+psst_status stage_net_create(psst_network *net, const psst_pathway *paths, int32_t np,
+                             bool sparse = false);
 void stage_net_free(StageNet *sn);
 
 // The one-trial stage batch of a large network (for psst_integrate).
@@ -34,7 +48,8 @@ psst_status stage_batch_integrate(StageBatch *sb, float *states, const psst_stim
                                   float dt, int64_t n_steps, int64_t step0,
                                   const psst_record *rec, float *ckpt, int32_t K, void *stream);
 psst_status stage_batch_poll(StageBatch *sb, void *stream);
-// Bytes of the padded conductance matrix one stage launch reads.
+// Bytes of the conductances one stage launch reads (the padded matrix once
+// per tile of trials, or the synapse buckets).
 int64_t stage_batch_matrix_bytes(const StageBatch *sb);
 // Switch between classical RK4 (gen = false) and a generic explicit method;
 // the step graph is rebuilt on the next call.

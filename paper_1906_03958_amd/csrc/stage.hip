@@ -31,6 +31,7 @@
 //
 // Between launches the per-(neuron, trial) stage input Y and accumulator acc
 // live in a float64 workspace; activations X are double-buffered float32.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 
@@ -63,6 +64,9 @@ constexpr int NVS = NVAR;
 
 struct StageFixed {
     const float *G;
+    const int32_t *sp_off;    // sparse storage: synapse buckets (stage.h)
+    const uint8_t *sp_col;
+    const float *sp_val;
     int Kp, ka, kg;           // K blocks [0,ka) ACh, [ka,ka+kg) fast GABA, [ka+kg,Kp) slow GABA
     float *X0, *X1;           // [Bp][Kp] activations (double-buffered by stage launch)
     double *Yw, *accw;        // [NVAR][nt] stage input and RK4 accumulator
@@ -132,6 +136,128 @@ __device__ __forceinline__ void tile_load(floatx4 (&rg)[GV], floatx4 (&rx)[XVT],
 #pragma unroll
     for (int u = 0; u < XVT; ++u)
         rx[u] = *reinterpret_cast<const floatx4 *>(X + (int64_t)(n0 + lr + RPP * u) * Kp + k0 + lk);
+}
+
+// The fused epilogue of a stage launch: right-hand side and Runge-Kutta
+// bookkeeping per (neuron, trial) of the workgroup's MT x NTILE block, from
+// the synaptic sums of the three classes in sA [3][MT][NTILE + 1] (LDS).
+template <int NTILE, int NTH, bool GEN>
+__device__ __forceinline__ void stage_epilogue(const StageFixed &fx,
+                                               const StageCtl *__restrict__ dctl, int q,
+                                               const double *sA, float *Xn, int m0, int n0,
+                                               int tid)
+{
+    const Kin K = load_kin(fx.kin);
+    const StageCtl c = *dctl;
+    const double dt = c.dt;
+    const int64_t g = c.g;
+    const int64_t nt = fx.nt;
+    bool bad = false;
+    // without slow GABA the r, G planes have zero derivative: they are neither
+    // read nor written (the state keeps them as they are)
+    const int nv = fx.gabab ? NVS : YR;
+    for (int p = tid; p < MT * NTILE; p += NTH) {
+        const int il = p % MT, bl = p / MT;
+        const int i = m0 + il, b = n0 + bl;
+        if (i >= fx.n || b >= fx.B) continue;
+        const int64_t gi = (int64_t)b * fx.n + i;
+        // y: the step's start state; Y: this stage's input (y itself at stage
+        // 0); a: the weighted sum of the earlier stages' derivatives.  The
+        // generic method keeps, per variable, B = sum_r b_r k_r in accw and
+        // in the slot of each later stage m the partial input
+        // sum_r a_mr k_r, replaced by the input y + dt * sum itself once
+        // stage m - 1 has added the last term.
+        auto slot = [&](int m) { return m == 1 ? fx.Yw : (m == 2 ? fx.P2 : fx.P3); };
+        const int last = GEN ? fx.tab.s - 1 : 3;
+        double Y[NVS], a[NVS], y[NVS];
+#pragma unroll
+        for (int v = 0; v < NVS; ++v) {
+            y[v] = v < nv ? (double)c.state[(2 * v) * nt + gi] + (double)c.state[(2 * v + 1) * nt + gi]
+                          : 0.0;
+            Y[v] = (q == 0 || v >= nv) ? y[v] : slot(GEN ? q : 1)[v * nt + gi];
+            a[v] = (q == 0 || v >= nv) ? 0.0 : fx.accw[v * nt + gi];
+        }
+        Prm P = load_prm(fx.prm, fx.ld, i);
+        double I = c.stim.i_const ? (double)c.stim.i_const[gi] : 0.0;
+        if (c.stim.pulse_ptr)
+            for (int k = c.stim.pulse_ptr[gi]; k < c.stim.pulse_ptr[gi + 1]; ++k)
+                if (c.stim.on_step[k] <= g && g < c.stim.off_step[k]) I += (double)c.stim.amp[k];
+        const double sa = sA[(0 * MT + il) * (NTILE + 1) + bl];
+        const double sg = sA[(1 * MT + il) * (NTILE + 1) + bl];
+        const double sb = sA[(2 * MT + il) * (NTILE + 1) + bl];
+        double f[NVS];
+        hh_rhs(Y, P, K, fx.cg * sa, fx.cg * sg, fx.cg * sb, fx.ci * I, i >= fx.n_pn,
+               fx.gabab != 0, f);
+        double yn[NVS];                       // the step's result (last stage)
+        if constexpr (GEN) {
+#pragma unroll
+            for (int v = 0; v < NVS; ++v) a[v] += fx.tab.b[q] * f[v];
+            if (q < last) {
+#pragma unroll
+                for (int v = 0; v < NVS; ++v) {
+                    for (int m = q + 1; m <= last; ++m) {
+                        const double pm = (q == 0 || v >= nv ? 0.0 : slot(m)[v * nt + gi]) +
+                                          fx.tab.a[m][q] * f[v];
+                        const double val = m == q + 1 ? y[v] + dt * pm : pm;
+                        if (m == q + 1) Y[v] = val;
+                        if (v < nv) slot(m)[v * nt + gi] = val;
+                    }
+                    if (v < nv) fx.accw[v * nt + gi] = a[v];
+                }
+                write_x(fx, Xn, b, i, Y, K);
+            } else {
+#pragma unroll
+                for (int v = 0; v < NVS; ++v) yn[v] = y[v] + dt * a[v];
+            }
+        } else {
+            const double w = (q == 0 || q == 3) ? 1.0 : 2.0;
+#pragma unroll
+            for (int v = 0; v < NVS; ++v) a[v] += w * f[v];
+            if (q < 3) {
+                const double cq = (q == 2) ? dt : 0.5 * dt;
+#pragma unroll
+                for (int v = 0; v < NVS; ++v) {
+                    Y[v] = y[v] + cq * f[v];
+                    if (v < nv) {
+                        fx.Yw[v * nt + gi] = Y[v];
+                        fx.accw[v * nt + gi] = a[v];
+                    }
+                }
+                write_x(fx, Xn, b, i, Y, K);
+            } else {
+#pragma unroll
+                for (int v = 0; v < NVS; ++v) yn[v] = y[v] + (dt / 6.0) * a[v];
+            }
+        }
+        if (q == last) {
+            const double vold = y[YV];
+            double chk = 0.0;
+#pragma unroll
+            for (int v = 0; v < NVS; ++v) {
+                if (v >= nv) continue;
+                float hi, lo;
+                y[v] = split_store(yn[v], hi, lo);
+                c.state[(2 * v) * nt + gi] = hi;
+                c.state[(2 * v + 1) * nt + gi] = lo;
+                chk += y[v];
+            }
+            bad |= !finite_d(chk);
+            write_x(fx, Xn, b, i, y, K);
+            const double vnew = y[YV];
+            if (c.rec.spike_count && vold < 0.0 && vnew >= 0.0) {
+                const int32_t cnt = c.rec.spike_count[gi];
+                if (cnt < c.rec.spike_cap)
+                    c.rec.spike_t[gi * c.rec.spike_cap + cnt] =
+                        (float)(((double)g + (0.0 - vold) / (vnew - vold)) * dt);
+                c.rec.spike_count[gi] = cnt + 1;
+            }
+            if (c.rec.v_out && c.rec.stride > 0 && (g + 1) % c.rec.stride == 0) {
+                const int64_t row = (g + 1) / c.rec.stride - c.step0 / c.rec.stride - 1;
+                if (row < c.rec.capacity) c.rec.v_out[row * nt + gi] = (float)vnew;
+            }
+        }
+    }
+    if (bad) atomicOr(c.flag, 1);
 }
 
 // One workgroup per CU (its LDS tiles take most of the CU's LDS); WR x WC
@@ -273,118 +399,124 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
                 }
     __syncthreads();
 
-    // fused epilogue: right-hand side and RK4 bookkeeping per (neuron, trial)
-    const Kin K = load_kin(fx.kin);
-    const StageCtl c = *dctl;
-    const double dt = c.dt;
-    const int64_t g = c.g;
-    const int64_t nt = fx.nt;
-    bool bad = false;
-    // without slow GABA the r, G planes have zero derivative: they are neither
-    // read nor written (the state keeps them as they are)
-    const int nv = fx.gabab ? NVS : YR;
-    for (int p = tid; p < MT * NTILE; p += NTH) {
-        const int il = p % MT, bl = p / MT;
-        const int i = m0 + il, b = n0 + bl;
-        if (i >= fx.n || b >= fx.B) continue;
-        const int64_t gi = (int64_t)b * fx.n + i;
-        // y: the step's start state; Y: this stage's input (y itself at stage
-        // 0); a: the weighted sum of the earlier stages' derivatives.  The
-        // generic method keeps, per variable, B = sum_r b_r k_r in accw and
-        // in the slot of each later stage m the partial input
-        // sum_r a_mr k_r, replaced by the input y + dt * sum itself once
-        // stage m - 1 has added the last term.
-        auto slot = [&](int m) { return m == 1 ? fx.Yw : (m == 2 ? fx.P2 : fx.P3); };
-        const int last = GEN ? fx.tab.s - 1 : 3;
-        double Y[NVS], a[NVS], y[NVS];
+    stage_epilogue<NTILE, NTH, GEN>(fx, dctl, q, sA, Xn, m0, n0, tid);
+}
+
+// Sparse storage: one workgroup per 64-row block and tile of 64 trials,
+// lane = trial.  The activations of each 128-column tile are staged in LDS
+// transposed (column-major: a column's 64 trials are contiguous), double
+// buffered like the dense kernel's tiles; wavefront w walks its rows'
+// synapses in the tile (64 at a time loaded into registers, one per lane,
+// then taken lane by lane), so each synapse costs one conflict-free LDS read
+// of 64 activations and one float64 fma per trial.  A row's tile sum starts
+// from zero and is added to its class total in float64; the column order of
+// every sum is fixed, so results do not depend on the trials' grouping.
+constexpr int XLD = 64 + 1;   // LDS stride (floats) of a transposed activation column
+constexpr size_t sparse_lds_bytes()
+{
+    const size_t tiles = sizeof(float) * 2 * KT * XLD;
+    const size_t acc = sizeof(double) * 3 * MT * (64 + 1);
+    return tiles > acc ? tiles : acc;
+}
+
+template <bool GEN>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void stage_sparse_kernel(
+    StageFixed fx, const StageCtl *__restrict__ dctl, int q)
+{
+    constexpr int NTILE = 64, NTH = 512;
+    extern __shared__ float smem[];
+    const int rb = blockIdx.x, m0 = rb * MT, n0 = blockIdx.y * NTILE;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t k_launch = (dctl->g - dctl->step0) * (GEN ? fx.tab.s : 4) + q;
+    const float *X = (k_launch & 1) ? fx.X1 : fx.X0;
+    float *Xn = (k_launch & 1) ? fx.X0 : fx.X1;
+    const int ntl = fx.Kp / KT;
+
+    // tile loads: 64 trials x 128 columns, four float4 per thread (trial
+    // row lb + 16 u, columns lc .. lc + 3)
+    const int lb = tid >> 5, lc = (tid & 31) * 4;
+    floatx4 rx[4];
+    auto xload = [&](int kt) {
 #pragma unroll
-        for (int v = 0; v < NVS; ++v) {
-            y[v] = v < nv ? (double)c.state[(2 * v) * nt + gi] + (double)c.state[(2 * v + 1) * nt + gi]
-                          : 0.0;
-            Y[v] = (q == 0 || v >= nv) ? y[v] : slot(GEN ? q : 1)[v * nt + gi];
-            a[v] = (q == 0 || v >= nv) ? 0.0 : fx.accw[v * nt + gi];
-        }
-        Prm P = load_prm(fx.prm, fx.ld, i);
-        double I = c.stim.i_const ? (double)c.stim.i_const[gi] : 0.0;
-        if (c.stim.pulse_ptr)
-            for (int k = c.stim.pulse_ptr[gi]; k < c.stim.pulse_ptr[gi + 1]; ++k)
-                if (c.stim.on_step[k] <= g && g < c.stim.off_step[k]) I += (double)c.stim.amp[k];
-        const double sa = sA[(0 * MT + il) * (NTILE + 1) + bl];
-        const double sg = sA[(1 * MT + il) * (NTILE + 1) + bl];
-        const double sb = sA[(2 * MT + il) * (NTILE + 1) + bl];
-        double f[NVS];
-        hh_rhs(Y, P, K, fx.cg * sa, fx.cg * sg, fx.cg * sb, fx.ci * I, i >= fx.n_pn,
-               fx.gabab != 0, f);
-        double yn[NVS];                       // the step's result (last stage)
-        if constexpr (GEN) {
+        for (int u = 0; u < 4; ++u)
+            rx[u] = *reinterpret_cast<const floatx4 *>(X + (int64_t)(n0 + lb + 16 * u) * fx.Kp +
+                                                       kt * KT + lc);
+    };
+    auto xstore = [&](int kt) {
+        float *x = smem + (kt & 1) * KT * XLD;
 #pragma unroll
-            for (int v = 0; v < NVS; ++v) a[v] += fx.tab.b[q] * f[v];
-            if (q < last) {
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int v = 0; v < NVS; ++v) {
-                    for (int m = q + 1; m <= last; ++m) {
-                        const double pm = (q == 0 || v >= nv ? 0.0 : slot(m)[v * nt + gi]) +
-                                          fx.tab.a[m][q] * f[v];
-                        const double val = m == q + 1 ? y[v] + dt * pm : pm;
-                        if (m == q + 1) Y[v] = val;
-                        if (v < nv) slot(m)[v * nt + gi] = val;
+            for (int e = 0; e < 4; ++e) x[(lc + e) * XLD + lb + 16 * u] = rx[u][e];
+    };
+    double acc[3][8];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) acc[t][r] = 0.0;
+    xload(0);
+    xstore(0);
+    if (ntl > 1) xload(1);
+    __syncthreads();
+    const int32_t *offw = fx.sp_off + ((int64_t)rb * ntl * 8 + wave) * 8;
+    for (int kt = 0; kt < ntl; ++kt) {
+        const float *x = smem + (kt & 1) * KT * XLD + lane;
+        const int32_t *o = offw + (int64_t)kt * 64;
+        int ob[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) ob[r] = o[r];
+        double ta[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) ta[r] = 0.0;
+        for (int base = ob[0]; base < ob[8]; base += 64) {
+            const int e = base + lane < ob[8] ? base + lane : ob[8] - 1;
+            const float lv = fx.sp_val[e];
+            const int lcol = fx.sp_col[e];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int j0 = (ob[r] > base ? ob[r] : base) - base;
+                const int j1 = (ob[r + 1] < base + 64 ? ob[r + 1] : base + 64) - base;
+                // four activations in flight, then their fmas in column order
+                int j = j0;
+                for (; j + 4 <= j1; j += 4) {
+                    float xv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) xv[u] = x[__builtin_amdgcn_readlane(lcol, j + u) * XLD];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float g = __builtin_bit_cast(
+                            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lv), j + u));
+                        ta[r] = fma((double)g, (double)xv[u], ta[r]);
                     }
-                    if (v < nv) fx.accw[v * nt + gi] = a[v];
                 }
-                write_x(fx, Xn, b, i, Y, K);
-            } else {
-#pragma unroll
-                for (int v = 0; v < NVS; ++v) yn[v] = y[v] + dt * a[v];
-            }
-        } else {
-            const double w = (q == 0 || q == 3) ? 1.0 : 2.0;
-#pragma unroll
-            for (int v = 0; v < NVS; ++v) a[v] += w * f[v];
-            if (q < 3) {
-                const double cq = (q == 2) ? dt : 0.5 * dt;
-#pragma unroll
-                for (int v = 0; v < NVS; ++v) {
-                    Y[v] = y[v] + cq * f[v];
-                    if (v < nv) {
-                        fx.Yw[v * nt + gi] = Y[v];
-                        fx.accw[v * nt + gi] = a[v];
-                    }
+                for (; j < j1; ++j) {
+                    const float g = __builtin_bit_cast(
+                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lv), j));
+                    ta[r] = fma((double)g, (double)x[__builtin_amdgcn_readlane(lcol, j) * XLD],
+                                ta[r]);
                 }
-                write_x(fx, Xn, b, i, Y, K);
-            } else {
-#pragma unroll
-                for (int v = 0; v < NVS; ++v) yn[v] = y[v] + (dt / 6.0) * a[v];
             }
         }
-        if (q == last) {
-            const double vold = y[YV];
-            double chk = 0.0;
+        const int t = kt * KT < fx.ka ? 0 : (kt * KT < fx.ka + fx.kg ? 1 : 2);
 #pragma unroll
-            for (int v = 0; v < NVS; ++v) {
-                if (v >= nv) continue;
-                float hi, lo;
-                y[v] = split_store(yn[v], hi, lo);
-                c.state[(2 * v) * nt + gi] = hi;
-                c.state[(2 * v + 1) * nt + gi] = lo;
-                chk += y[v];
-            }
-            bad |= !finite_d(chk);
-            write_x(fx, Xn, b, i, y, K);
-            const double vnew = y[YV];
-            if (c.rec.spike_count && vold < 0.0 && vnew >= 0.0) {
-                const int32_t cnt = c.rec.spike_count[gi];
-                if (cnt < c.rec.spike_cap)
-                    c.rec.spike_t[gi * c.rec.spike_cap + cnt] =
-                        (float)(((double)g + (0.0 - vold) / (vnew - vold)) * dt);
-                c.rec.spike_count[gi] = cnt + 1;
-            }
-            if (c.rec.v_out && c.rec.stride > 0 && (g + 1) % c.rec.stride == 0) {
-                const int64_t row = (g + 1) / c.rec.stride - c.step0 / c.rec.stride - 1;
-                if (row < c.rec.capacity) c.rec.v_out[row * nt + gi] = (float)vnew;
-            }
+        for (int r = 0; r < 8; ++r) {
+            if (t == 0) acc[0][r] += ta[r];
+            else if (t == 1) acc[1][r] += ta[r];
+            else acc[2][r] += ta[r];
         }
+        // the other buffer was last read before the previous barrier
+        if (kt + 1 < ntl) xstore(kt + 1);
+        if (kt + 2 < ntl) xload(kt + 2);
+        __syncthreads();
     }
-    if (bad) atomicOr(c.flag, 1);
+    double *sA = reinterpret_cast<double *>(smem);   // [3][MT][NTILE + 1]
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) sA[(t * MT + 8 * wave + r) * (NTILE + 1) + lane] = acc[t][r];
+    __syncthreads();
+    stage_epilogue<NTILE, NTH, GEN>(fx, dctl, q, sA, Xn, m0, n0, tid);
 }
 
 }  // namespace
@@ -406,7 +538,87 @@ struct StageBatch {
 
 static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-psst_status stage_net_create(psst_network *net, const psst_pathway *paths, int32_t np)
+// The synapse buckets of a sparse large network (layout in stage.h).
+static psst_status stage_net_sparse(StageNet *sn, const psst_network *net,
+                                    const psst_pathway *paths, int32_t np)
+{
+    const int ntl = sn->Kp / KT, nrb = sn->Mp / MT;
+    const int64_t nb = (int64_t)nrb * ntl * 64;
+    auto column = [&](const psst_pathway &w, int j) {
+        return w.type == PSST_SYN_ACH ? j
+                                      : (w.type == PSST_SYN_GABA_A ? sn->ka + (j - net->n_pn)
+                                                                   : sn->ka + sn->kg + (j - net->n_pn));
+    };
+    auto bucket = [&](int i, int k) {
+        const int il = i % MT;
+        return (((int64_t)(i / MT) * ntl + k / KT) * 8 + il / 8) * 8 + il % 8;
+    };
+    std::vector<int64_t> off(nb + 1, 0);
+    for (int q = 0; q < np; ++q) {
+        const psst_pathway &w = paths[q];
+        const int npre = w.pre_end - w.pre_begin;
+        for (int i = w.post_begin; i < w.post_end; ++i)
+            for (int j = w.pre_begin; j < w.pre_end; ++j) {
+                const int64_t e = (int64_t)(i - w.post_begin) * npre + (j - w.pre_begin);
+                if (!w.mask || w.mask[e]) ++off[bucket(i, column(w, j)) + 1];
+            }
+    }
+    for (int64_t b = 0; b < nb; ++b) off[b + 1] += off[b];
+    const int64_t nnz = off[nb];
+    if (nnz >= ((int64_t)1 << 31))
+        return fail(PSST_ERR_UNSUPPORTED, "%lld synapses exceed the sparse layout's 2^31",
+                    (long long)nnz);
+    std::vector<uint8_t> col((size_t)std::max<int64_t>(nnz, 1));
+    std::vector<float> val((size_t)std::max<int64_t>(nnz, 1));
+    std::vector<int64_t> pos(off.begin(), off.end() - 1);
+    for (int q = 0; q < np; ++q) {
+        const psst_pathway &w = paths[q];
+        const int npre = w.pre_end - w.pre_begin;
+        for (int i = w.post_begin; i < w.post_end; ++i)
+            for (int j = w.pre_begin; j < w.pre_end; ++j) {
+                const int64_t e = (int64_t)(i - w.post_begin) * npre + (j - w.pre_begin);
+                if (w.mask && !w.mask[e]) continue;
+                const int k = column(w, j);
+                const int64_t p = pos[bucket(i, k)]++;
+                col[p] = (uint8_t)(k % KT);
+                val[p] = w.g_nS[e];
+            }
+    }
+    // ascending columns within each bucket (pathways of one class may come
+    // in any order; no column repeats, pathways of a type do not overlap)
+    std::vector<std::pair<uint8_t, float>> tmp;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t b0 = off[b], b1 = off[b + 1];
+        tmp.clear();
+        for (int64_t p = b0; p < b1; ++p) tmp.push_back({col[p], val[p]});
+        std::sort(tmp.begin(), tmp.end(),
+                  [](const std::pair<uint8_t, float> &x, const std::pair<uint8_t, float> &y) {
+                      return x.first < y.first;
+                  });
+        for (int64_t p = b0; p < b1; ++p) {
+            col[p] = tmp[p - b0].first;
+            val[p] = tmp[p - b0].second;
+        }
+    }
+    std::vector<int32_t> off32(off.begin(), off.end());
+    hipError_t e = hipMalloc(&sn->sp_off, sizeof(int32_t) * off32.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(sn->sp_off, off32.data(), sizeof(int32_t) * off32.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&sn->sp_col, col.size());
+    if (e == hipSuccess) e = hipMemcpy(sn->sp_col, col.data(), col.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&sn->sp_val, sizeof(float) * val.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(sn->sp_val, val.data(), sizeof(float) * val.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY : PSST_ERR_DEVICE,
+                    "sparse stage layout upload failed: %s", hipGetErrorString(e));
+    sn->sparse = true;
+    sn->nnz = nnz;
+    return PSST_OK;
+}
+
+psst_status stage_net_create(psst_network *net, const psst_pathway *paths, int32_t np,
+                             bool sparse)
 {
     StageNet *sn = new StageNet();
     sn->n = net->n;
@@ -418,6 +630,15 @@ psst_status stage_net_create(psst_network *net, const psst_pathway *paths, int32
     sn->kg = round_up(n_ln, KT);
     sn->kb = net->gabab ? round_up(n_ln, KT) : 0;
     sn->Kp = sn->ka + sn->kg + sn->kb;
+    if (sparse) {
+        psst_status st = stage_net_sparse(sn, net, paths, np);
+        if (st != PSST_OK) {
+            stage_net_free(sn);
+            return st;
+        }
+        net->stage = sn;
+        return PSST_OK;
+    }
     std::vector<float> G((size_t)sn->Mp * sn->Kp, 0.f);
     for (int q = 0; q < np; ++q) {
         const psst_pathway &w = paths[q];
@@ -452,6 +673,9 @@ void stage_net_free(StageNet *sn)
 {
     if (!sn) return;
     (void)hipFree(sn->G);
+    (void)hipFree(sn->sp_off);
+    (void)hipFree(sn->sp_col);
+    (void)hipFree(sn->sp_val);
     delete sn;
 }
 
@@ -463,7 +687,7 @@ psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch *
     StageBatch *sb = new StageBatch();
     sb->net = net;
     sb->B = n_trials;
-    sb->ntile = n_trials <= 16 ? 16 : 64;
+    sb->ntile = n_trials <= 16 && !sn->sparse ? 16 : 64;
     sb->Bp = round_up(n_trials, sb->ntile);
     const int64_t nt = (int64_t)n_trials * net->n;
     hipError_t e = hipSuccess;
@@ -483,6 +707,9 @@ psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch *
     }
     StageFixed &fx = sb->fx;
     fx.G = sn->G;
+    fx.sp_off = sn->sp_off;
+    fx.sp_col = sn->sp_col;
+    fx.sp_val = sn->sp_val;
     fx.Kp = sn->Kp;
     fx.ka = sn->ka;
     fx.kg = sn->kg;
@@ -521,9 +748,16 @@ void stage_batch_set_method(StageBatch *sb, bool gen, const Tab &tab)
     sb->fx.tab = gen ? tab : Tab{};
     const StageNet *sn = sb->net->stage;
     char buf[256];
-    snprintf(buf, sizeof buf,
-             "[per-stage fp32 MFMA GEMM: %d rows x %d trials (tile 64 x %d), K %d, %d launches per step]",
-             sn->Mp, sb->Bp, sb->ntile, sn->Kp, gen ? tab.s : 4);
+    if (sn->sparse)
+        snprintf(buf, sizeof buf,
+                 "[per-stage sparse: %d rows x %d trials (tile 64 x 64), %lld synapses, K %d, %d "
+                 "launches per step]",
+                 sn->Mp, sb->Bp, (long long)sn->nnz, sn->Kp, gen ? tab.s : 4);
+    else
+        snprintf(buf, sizeof buf,
+                 "[per-stage fp32 MFMA GEMM: %d rows x %d trials (tile 64 x %d), K %d, %d launches "
+                 "per step]",
+                 sn->Mp, sb->Bp, sb->ntile, sn->Kp, gen ? tab.s : 4);
     sb->desc = buf;
 }
 
@@ -546,6 +780,9 @@ const char *stage_batch_describe(const StageBatch *sb) { return sb ? sb->desc.c_
 int64_t stage_batch_matrix_bytes(const StageBatch *sb)
 {
     const StageNet *sn = sb->net->stage;
+    if (sn->sparse)
+        return ((int64_t)sizeof(float) + 1) * sn->nnz * (sb->Bp / sb->ntile) +
+               (int64_t)sizeof(int32_t) * ((int64_t)sn->Mp / MT * (sn->Kp / KT) * 64 + 1);
     return (int64_t)sizeof(float) * sn->Mp * sn->Kp * (sb->Bp / sb->ntile);
 }
 
@@ -565,8 +802,11 @@ static size_t stage_lds_bytes(int ntile) { return sizeof(float) * stage_lds_floa
 // One step as a graph: its stages (4 for RK4) then the step-counter advance.
 static psst_status build_graph(StageBatch *sb)
 {
-    const size_t lds = stage_lds_bytes(sb->ntile);
-    const void *fn = stage_fn(sb->ntile, sb->gen);
+    const bool sparse = sb->net->stage->sparse;
+    const size_t lds = sparse ? sparse_lds_bytes() : stage_lds_bytes(sb->ntile);
+    const void *fn = sparse ? (sb->gen ? (const void *)stage_sparse_kernel<true>
+                                       : (const void *)stage_sparse_kernel<false>)
+                            : stage_fn(sb->ntile, sb->gen);
     HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     HIPCHK(hipGraphCreate(&sb->graph, 0));
     hipGraphNode_t prev = nullptr;

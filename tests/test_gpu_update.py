@@ -3,7 +3,7 @@ with one set of values and then given another runs, integrates and
 differentiates bit for bit as a network created with the new values -- in
 every storage (dense with and without slow GABA, lane-group size, sparse
 rows with and without the dense copy, the per-stage layout of a network
-above 1024 neurons) and through batches created before the update; values
+above 1024 neurons, dense and sparse) and through batches created before the update; values
 where the network has no synapse are ignored; parity of an updated network
 with the FP64 oracle; the autograd Function reusing its network."""
 import copy
@@ -74,6 +74,7 @@ CASES = [
     ("sparse rows + dense copy", lambda: W.config3_sparse_instance(17), "sparse"),
     ("sparse rows only (n > 512)", lambda: W.sized_instance(5, 450, 150), "sparse"),
     ("per-stage layout, 1200 neurons", lambda: W.sized_instance(6, 900, 300), None),
+    ("per-stage sparse buckets, 1200 neurons", lambda: W.sized_instance(9, 900, 300), "sparse"),
 ]
 
 
