@@ -259,13 +259,15 @@ MFMA_FP32_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
-def run_large(args, torch, psst, W, dev, stream, steps, warmup, chunk):
-    """16384 neurons (12288 PN, 4096 LN), dense Bernoulli(0.5) g ~ U(0,0.1) nS,
-    64 stimulus trials; one step = chunk RK4 steps (a graph of the method's
-    stage launches per RK4 step).  Returns the measurements and the MFMA
-    roofline of the stage kernel."""
+def run_large(args, torch, psst, W, dev, stream, steps, warmup, chunk, sparse=False):
+    """16384 neurons (12288 PN, 4096 LN), dense Bernoulli(0.5) g ~ U(0,0.1) nS
+    (sparse: Bernoulli(0.1), g ~ U(0,0.5) nS, the same expected input, stored
+    as synapse buckets), 64 stimulus trials; one step = chunk RK4 steps (a
+    graph of the method's stage launches per RK4 step).  Returns the
+    measurements and the stage kernel's roofline (MFMA for the dense form,
+    float64 vector for the sparse one)."""
     t0 = time.time()
-    net = W.config4_network()
+    net = W.config4_network(p=0.1, g_max=0.5) if sparse else W.config4_network()
     B = W.CONFIG4_TRIALS
     i_nA, v0 = W.trial_inputs(4, net.n, B)
     h = psst.network_create(net)
@@ -305,11 +307,36 @@ def run_large(args, torch, psst, W, dev, stream, steps, warmup, chunk):
     psst.batch_poll(batch)
     rk4_steps = chunk * steps
     stage_s = ev0.elapsed_time(ev1) / 1e3 / (stages * rk4_steps)
+    _, g_bytes = psst.batch_conductance_bytes(batch)
+    if sparse:
+        nnz = int(sum(int(np.count_nonzero(p.mask)) for p in net.pathways))
+        flops_stage = 2.0 * nnz * B
+        achieved = flops_stage / stage_s / 1e12
+        res = {"value": nt * rk4_steps / wall, "unit": "neuron-steps/s",
+               "wall_s": wall, "rk4_steps": rk4_steps,
+               "ms_per_rk4_step": 1e3 * wall / rk4_steps,
+               "workload": "large sparse network: 16384 HH neurons (12288 PN, 4096 LN), "
+                           "Bernoulli(0.1) g ~ U(0,0.5) nS, 64 stimulus trials, dt 0.01 ms",
+               "launch": psst.batch_describe(batch),
+               "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                            "traffic": None,
+                            "kernel": "stage_sparse_kernel (float64 fma per synapse and trial, "
+                                      "activations from LDS, + fused RK stage)",
+                            "avg_launch_ms": round(1e3 * stage_s, 4),
+                            "synapses": nnz,
+                            "algorithmic_flops_per_launch": flops_stage,
+                            "conductance_bytes_per_launch": g_bytes,
+                            "conductance_GBps": round(g_bytes / stage_s / 1e9, 1),
+                            "note": "flops: one float64 fma per synapse and trial; launch "
+                                    f"time = graph time per step / {stages}"}}
+        del batch, h
+        return res
     flops_stage = 2.0 * net.n * net.n * B
     achieved = flops_stage / stage_s / 1e12
     # counters on file were taken for classical RK4
     traffic = read_traffic("stage_kernel", args, "large") if args.method == "rk4" else None
-    _, g_bytes = psst.batch_conductance_bytes(batch)
     res = {"value": nt * rk4_steps / wall, "unit": "neuron-steps/s",
            "wall_s": wall, "rk4_steps": rk4_steps, "ms_per_rk4_step": 1e3 * wall / rk4_steps,
            "workload": "large dense network: 16384 HH neurons (12288 PN, 4096 LN), "
@@ -333,13 +360,15 @@ def run_large(args, torch, psst, W, dev, stream, steps, warmup, chunk):
     return res
 
 
-def bench_large(args, torch, psst, W, dev, stream):
-    """The large network on its own line (--workload large)."""
-    r = run_large(args, torch, psst, W, dev, stream, args.steps, args.warmup, args.chunk)
+def bench_large(args, torch, psst, W, dev, stream, sparse=False):
+    """The large network on its own line (--workload large, large-sparse)."""
+    r = run_large(args, torch, psst, W, dev, stream, args.steps, args.warmup, args.chunk,
+                  sparse=sparse)
     out = {"metric": METRIC, "value": r["value"], "unit": "neuron-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * r["wall_s"] / args.steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32 (GEMM) / f64 (RHS)",
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 (synaptic sums and RHS)" if sparse else "f32 (GEMM) / f64 (RHS)",
            "data": "synthetic",
            "config": {"workload": r["workload"], "rk4_steps_per_step": args.chunk,
                       "method": args.method, "launch": r["launch"]},
@@ -571,11 +600,13 @@ def main():
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter files of a "
                          "bench run (same --workload/--chunk/--instances) and of a "
                          "--copy-calibration run into profiles/KERNEL_traffic.txt and exit")
-    ap.add_argument("--workload", choices=("batched", "large", "uncoupled", "sparse", "streamed",
-                                           "al", "adjoint"),
+    ap.add_argument("--workload", choices=("batched", "large", "large-sparse", "uncoupled",
+                                           "sparse", "streamed", "al", "adjoint"),
                     default="batched",
                     help="batched: the 4096-network batch (the default line); large: the "
                          "16384-neuron network x 64 trials on the per-stage MFMA path; "
+                         "large-sparse: that network at connection probability 0.1 with "
+                         "sparse storage (per-stage synapse buckets); "
                          "uncoupled: the batch with every synapse removed (compute only); "
                          "sparse: the batch at connection probability 0.1, sparse storage; "
                          "streamed: the batch with its full V trace (every step) and spikes "
@@ -649,8 +680,8 @@ def main():
         print(json.dumps({"read_calibration_bytes": 4 * n, "launches": 5, "sum": tot}))
         return
 
-    if args.workload == "large":
-        bench_large(args, torch, psst, W, dev, stream)
+    if args.workload in ("large", "large-sparse"):
+        bench_large(args, torch, psst, W, dev, stream, sparse=args.workload == "large-sparse")
         return
     if args.workload == "streamed":
         bench_streamed(args, torch, psst, W, dev, stream)

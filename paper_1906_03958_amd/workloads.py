@@ -349,13 +349,15 @@ CONFIG3_INSTANCES = 4096
 CONFIG3_STEPS = 50_000
 
 
-def config4_network(n_pn: int = 12288, n_ln: int = 4096, chunk_rows: int = 1024
-                    ) -> Network:
-    """Large dense network: Bernoulli(0.5) mask, g ~ U(0, 0.1) nS, no autapses.
+def config4_network(n_pn: int = 12288, n_ln: int = 4096, chunk_rows: int = 1024,
+                    p: float = 0.5, g_max: float = 0.1) -> Network:
+    """Large network: Bernoulli(p) mask, g ~ U(0, g_max) nS, no autapses
+    (default: the dense p = 0.5, g_max = 0.1 network).
 
     Generated in row chunks so the float64 temporaries stay small; each chunk
-    has its own generator (stream id offset by the chunk index)."""
-    cfg = 4
+    has its own generator (stream id offset by the chunk index); a density
+    other than 0.5 draws from workload id 12."""
+    cfg = 4 if p == 0.5 else 12
     n = n_pn + n_ln
     g_ach = np.empty((n, n_pn), np.float32)
     m_ach = np.empty((n, n_pn), np.uint8)
@@ -365,9 +367,9 @@ def config4_network(n_pn: int = 12288, n_ln: int = 4096, chunk_rows: int = 1024
         r1 = min(n, r0 + chunk_rows)
         rm = rng_for(cfg, 0, 100 + 2 * c)
         rg = rng_for(cfg, 0, 101 + 2 * c)
-        g, m = _bernoulli_block(rm, rg, (r1 - r0, n_pn), 0.5, 0.1, (r0, 0))
+        g, m = _bernoulli_block(rm, rg, (r1 - r0, n_pn), p, g_max, (r0, 0))
         g_ach[r0:r1], m_ach[r0:r1] = g, m
-        g, m = _bernoulli_block(rm, rg, (r1 - r0, n_ln), 0.5, 0.1, (r0, n_pn))
+        g, m = _bernoulli_block(rm, rg, (r1 - r0, n_ln), p, g_max, (r0, n_pn))
         g_gab[r0:r1], m_gab[r0:r1] = g, m
     paths = [Pathway(ACH, 0, n_pn, 0, n, g_ach, m_ach),
              Pathway(GABA_A, n_pn, n, 0, n, g_gab, m_gab)]
