@@ -260,7 +260,14 @@ psst_status psst_network_poll(psst_network *net, void *hip_stream);
  * shape) or PSST_WG_SHAPE="<threads>x<neurons per thread>[r<register
  * slots>]" names the variant to use.  A class's choice is kept for the
  * process per (device architecture, size class, method, storage, slow GABA
- * present) and reused by later batches.  n in [1, 1 << 20]. */
+ * present) and reused by later batches.  Networks above 1024 neurons take
+ * the per-stage path: a batch whose instances all share one such network is
+ * one per-stage launch sequence over its trials; in any other batch each run
+ * of consecutive instances of one such network is a per-stage sub-batch of
+ * its own (its trials side by side), run after the other instances' launches
+ * on the same stream, in the same packed arrays.  Checkpoints and the
+ * adjoint are not available for batches with per-stage instances
+ * (UNSUPPORTED).  n in [1, 1 << 20]. */
 psst_status psst_batch_create(psst_network *const *nets, int32_t n, psst_batch **out);
 psst_status psst_batch_destroy(psst_batch *batch);
 
@@ -279,7 +286,8 @@ psst_status psst_batch_state_init(const psst_batch *batch, const float *v0, floa
  * the batch's order and composition).  states, stim, rec are packed over
  * n_total neurons.  checkpoints: NULL, or device [n_steps / K + 1 x n_words]
  * float32 receiving the state before global steps step0 + c K (c = 0, 1,
- * ...), for psst_adjoint.  Submitted as one graph launch. */
+ * ...), for psst_adjoint.  Submitted as one graph launch (plus the
+ * per-stage sub-batches' step graphs, if any). */
 psst_status psst_integrate_batch(psst_batch *batch, float *states, const psst_stimulus *stim,
                                  float dt_ms, int64_t n_steps, int64_t step0,
                                  const psst_record *rec, float *checkpoints, int32_t K,

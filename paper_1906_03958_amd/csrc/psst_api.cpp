@@ -746,6 +746,7 @@ static void batch_free(psst_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     stage_batch_free(b->stage);
+    for (StageBatch *sb : b->subs) stage_batch_free(sb);
     adjoint_free(b->adj);
     stream_bufs_free(b->strm);
     delete b;
@@ -1174,13 +1175,28 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
 
     bool all_wg = true;
     for (auto *q : b->nets) all_wg &= fits_wg(q);
-    if (!all_wg) {
-        if (!b->shared) {
-            batch_free(b);
-            return fail(PSST_ERR_UNSUPPORTED,
-                        "instances above %d neurons are supported when all instances share one network",
-                        kMaxWGNeurons);
+    if (!all_wg && !b->shared) {
+        // runs of consecutive instances of one large network become per-stage
+        // sub-batches inside the batch's arrays, sharing its error flag
+        for (int32_t k = 0; k < n;) {
+            if (fits_wg(nets[k])) {
+                ++k;
+                continue;
+            }
+            int32_t k1 = k + 1;
+            while (k1 < n && nets[k1] == nets[k]) ++k1;
+            StageBatch *sb = nullptr;
+            s = stage_batch_create(nets[k], k1 - k, &sb, b->nt, b->offsets[k]);
+            if (s != PSST_OK) {
+                batch_free(b);
+                return s;
+            }
+            stage_batch_use_flag(sb, b->d_flag);
+            b->subs.push_back(sb);
+            k = k1;
         }
+    }
+    if (!all_wg && b->shared) {
         b->stage_path = true;
         s = stage_batch_create(nets[0], n, &b->stage);
         if (s != PSST_OK) {
@@ -1219,6 +1235,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
     size_t need = 0;
     for (int32_t k : idx) {
         const psst_network *q = nets[k];
+        if (!fits_wg(q)) continue;        // a per-stage sub-batch's instance
         if (!shp && net_lg(q)) {
             gl.order.push_back(k);
             gl.max_n = std::max(gl.max_n, q->n);
@@ -1453,6 +1470,10 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
                  g.order.size(), g.max_n, g.lg ? "lane-group, " : "", g.bs, g.npt, rr, g.lds);
         b->describe += buf;
     }
+    for (StageBatch *sb : b->subs) {
+        b->describe += stage_batch_describe(sb);
+        b->describe += " ";
+    }
     *out = b;
     return PSST_OK;
 }
@@ -1486,6 +1507,7 @@ extern "C" psst_status psst_batch_conductance_bytes(const psst_batch *b, int64_t
 {
     if (!b) return fail(PSST_ERR_INVALID_ARGUMENT, "batch is NULL");
     int64_t res = 0, str = 0;
+    for (const StageBatch *sb : b->subs) str += stage_batch_matrix_bytes(sb);
     if (b->stage_path) {
         str = stage_batch_matrix_bytes(b->stage);
     } else {
@@ -1601,11 +1623,20 @@ extern "C" psst_status psst_integrate_batch(psst_batch *b, float *states, const 
     if (b->stage_path)
         return stage_batch_integrate(b->stage, states, stim, dt, n_steps, step0, rec, ckpt, K,
                                      stream);
+    if (ckpt && !b->subs.empty())
+        return fail(PSST_ERR_UNSUPPORTED, "checkpoints are not supported on the per-stage path");
     if (n_steps == 0) return PSST_OK;
-    std::vector<WGArgs> args;
-    for (auto &g : b->groups)
-        args.push_back(group_args(b, g, states, stim, dt, n_steps, step0, rec, ckpt, K));
-    return submit_graph(b, args, (hipStream_t)stream);
+    if (!b->groups.empty()) {
+        std::vector<WGArgs> args;
+        for (auto &g : b->groups)
+            args.push_back(group_args(b, g, states, stim, dt, n_steps, step0, rec, ckpt, K));
+        if ((s = submit_graph(b, args, (hipStream_t)stream)) != PSST_OK) return s;
+    }
+    for (StageBatch *sb : b->subs)
+        if ((s = stage_batch_integrate(sb, states, stim, dt, n_steps, step0, rec, nullptr, 0,
+                                       stream)) != PSST_OK)
+            return s;
+    return PSST_OK;
 }
 
 // The batch's launches without the graph (the streamed path issues one per
@@ -1638,6 +1669,10 @@ psst_status batch_launch_direct(psst_batch *b, float *states, const psst_stimulu
             b->aux_done.push_back(e);
         }
     }
+    for (StageBatch *sb : b->subs)
+        if ((s = stage_batch_integrate(sb, states, stim, dt, n_steps, step0, rec, nullptr, 0,
+                                       stream)) != PSST_OK)
+            return s;
     if (G > 1) HIPCHK(hipEventRecord(b->aux_fork, st));
     for (size_t k = 0; k < G; ++k) {
         const Group &g = b->groups[k];
@@ -1746,7 +1781,7 @@ extern "C" psst_status psst_adjoint(psst_batch *b, const float *ckpt, int32_t K,
     if ((s = validate_stim(stim)) != PSST_OK) return s;
     if (!per_instance && !b->shared)
         return fail(PSST_ERR_INVALID_ARGUMENT, "summed gradients need every instance to share one network");
-    if (b->stage_path)
+    if (b->stage_path || !b->subs.empty())
         return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available on the per-stage path");
     const int64_t max_n = b->nets.empty() ? 0 : (*std::max_element(
         b->nets.begin(), b->nets.end(),
@@ -1776,7 +1811,7 @@ extern "C" psst_status psst_adjoint_noalloc(psst_batch *b, const float *ckpt, in
     if ((s = validate_stim(stim)) != PSST_OK) return s;
     if (!per_instance && !b->shared)
         return fail(PSST_ERR_INVALID_ARGUMENT, "summed gradients need every instance to share one network");
-    if (b->stage_path)
+    if (b->stage_path || !b->subs.empty())
         return fail(PSST_ERR_UNSUPPORTED, "the adjoint is not available on the per-stage path");
     return adjoint_run_noalloc(b->nets, b->d_desc, b->nt, batch_recompute(b, stim, dt), ckpt, K,
                                stim, dt, n_steps, step0, dLdV,
@@ -1846,6 +1881,7 @@ extern "C" psst_status psst_batch_set_tableau(psst_batch *b, const psst_tableau 
         stage_batch_set_method(b->stage, gen, t);
         b->describe = stage_batch_describe(b->stage);
     }
+    for (StageBatch *sb : b->subs) stage_batch_set_method(sb, gen, t);
     if (gen != b->gen && b->exec) {
         // the graph's kernel changes: build it again on the next call
         HIPCHK(hipGraphExecDestroy(b->exec));

@@ -122,6 +122,10 @@ struct psst_batch {
     bool shared = false;            // every instance is the same network
     bool stage_path = false;        // large shared network: per-stage kernels
     StageBatch *stage = nullptr;
+    // ragged batches with networks above the per-instance limit: each run of
+    // consecutive instances of one such network is a per-stage sub-batch
+    // placed in the batch's arrays; the other instances take the groups
+    std::vector<StageBatch *> subs;
     std::string describe;
     // graph of the persistent launches
     hipGraph_t graph = nullptr;

@@ -41,7 +41,13 @@ psst_status stage_single_prepare(psst_network *net);
 psst_status stage_integrate_single(psst_network *net, float *state, const psst_stimulus *stim,
                                    float dt, int64_t n_steps, int64_t step0,
                                    const psst_record *rec, void *stream);
-psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch **out);
+// n_trials trials of net; st_stride > 0 and st_off place them inside a larger
+// batch's state, stimulus and record arrays (plane stride, first trial's
+// offset: trial b's neuron i at st_off + b * n + i).
+psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch **out,
+                               int64_t st_stride = 0, int64_t st_off = 0);
+// The batch's non-finite flag (the caller's, or its own when flag is NULL).
+void stage_batch_use_flag(StageBatch *sb, int32_t *flag);
 void stage_batch_free(StageBatch *sb);
 const char *stage_batch_describe(const StageBatch *sb);
 psst_status stage_batch_integrate(StageBatch *sb, float *states, const psst_stimulus *stim,

@@ -75,7 +75,11 @@ struct StageFixed {
     const float *prm;         // [NPRM][ld]
     const float *kin;
     int ld, n, n_pn, B, Bp;
-    int64_t nt;               // B * n
+    int64_t nt;               // B * n (workspace planes)
+    // the caller's state, stimulus and record arrays: plane stride and the
+    // first trial's offset (B * n and 0, unless the trials are one run of
+    // instances inside a larger batch)
+    int64_t st_stride, st_off;
     int gabab;
     double cg, ci;
 };
@@ -111,10 +115,12 @@ __global__ __launch_bounds__(256) void stage_prologue(StageFixed fx, StageCtl c,
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < fx.nt;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int b = (int)(p / fx.n), i = (int)(p % fx.n);
+        const int64_t so = fx.st_off + p;
         double y[NVS];
 #pragma unroll
         for (int v = 0; v < NVS; ++v)
-            y[v] = (double)c.state[(2 * v) * fx.nt + p] + (double)c.state[(2 * v + 1) * fx.nt + p];
+            y[v] = (double)c.state[(2 * v) * fx.st_stride + so] +
+                   (double)c.state[(2 * v + 1) * fx.st_stride + so];
         write_x(fx, fx.X0, b, i, y, K);
     }
 }
@@ -151,7 +157,7 @@ __device__ __forceinline__ void stage_epilogue(const StageFixed &fx,
     const StageCtl c = *dctl;
     const double dt = c.dt;
     const int64_t g = c.g;
-    const int64_t nt = fx.nt;
+    const int64_t nt = fx.nt, ST = fx.st_stride;
     bool bad = false;
     // without slow GABA the r, G planes have zero derivative: they are neither
     // read nor written (the state keeps them as they are)
@@ -160,7 +166,8 @@ __device__ __forceinline__ void stage_epilogue(const StageFixed &fx,
         const int il = p % MT, bl = p / MT;
         const int i = m0 + il, b = n0 + bl;
         if (i >= fx.n || b >= fx.B) continue;
-        const int64_t gi = (int64_t)b * fx.n + i;
+        const int64_t gi = (int64_t)b * fx.n + i;   // workspace index
+        const int64_t so = fx.st_off + gi;           // state, stimulus, records
         // y: the step's start state; Y: this stage's input (y itself at stage
         // 0); a: the weighted sum of the earlier stages' derivatives.  The
         // generic method keeps, per variable, B = sum_r b_r k_r in accw and
@@ -172,15 +179,15 @@ __device__ __forceinline__ void stage_epilogue(const StageFixed &fx,
         double Y[NVS], a[NVS], y[NVS];
 #pragma unroll
         for (int v = 0; v < NVS; ++v) {
-            y[v] = v < nv ? (double)c.state[(2 * v) * nt + gi] + (double)c.state[(2 * v + 1) * nt + gi]
+            y[v] = v < nv ? (double)c.state[(2 * v) * ST + so] + (double)c.state[(2 * v + 1) * ST + so]
                           : 0.0;
             Y[v] = (q == 0 || v >= nv) ? y[v] : slot(GEN ? q : 1)[v * nt + gi];
             a[v] = (q == 0 || v >= nv) ? 0.0 : fx.accw[v * nt + gi];
         }
         Prm P = load_prm(fx.prm, fx.ld, i);
-        double I = c.stim.i_const ? (double)c.stim.i_const[gi] : 0.0;
+        double I = c.stim.i_const ? (double)c.stim.i_const[so] : 0.0;
         if (c.stim.pulse_ptr)
-            for (int k = c.stim.pulse_ptr[gi]; k < c.stim.pulse_ptr[gi + 1]; ++k)
+            for (int k = c.stim.pulse_ptr[so]; k < c.stim.pulse_ptr[so + 1]; ++k)
                 if (c.stim.on_step[k] <= g && g < c.stim.off_step[k]) I += (double)c.stim.amp[k];
         const double sa = sA[(0 * MT + il) * (NTILE + 1) + bl];
         const double sg = sA[(1 * MT + il) * (NTILE + 1) + bl];
@@ -237,23 +244,23 @@ __device__ __forceinline__ void stage_epilogue(const StageFixed &fx,
                 if (v >= nv) continue;
                 float hi, lo;
                 y[v] = split_store(yn[v], hi, lo);
-                c.state[(2 * v) * nt + gi] = hi;
-                c.state[(2 * v + 1) * nt + gi] = lo;
+                c.state[(2 * v) * ST + so] = hi;
+                c.state[(2 * v + 1) * ST + so] = lo;
                 chk += y[v];
             }
             bad |= !finite_d(chk);
             write_x(fx, Xn, b, i, y, K);
             const double vnew = y[YV];
             if (c.rec.spike_count && vold < 0.0 && vnew >= 0.0) {
-                const int32_t cnt = c.rec.spike_count[gi];
+                const int32_t cnt = c.rec.spike_count[so];
                 if (cnt < c.rec.spike_cap)
-                    c.rec.spike_t[gi * c.rec.spike_cap + cnt] =
+                    c.rec.spike_t[so * c.rec.spike_cap + cnt] =
                         (float)(((double)g + (0.0 - vold) / (vnew - vold)) * dt);
-                c.rec.spike_count[gi] = cnt + 1;
+                c.rec.spike_count[so] = cnt + 1;
             }
             if (c.rec.v_out && c.rec.stride > 0 && (g + 1) % c.rec.stride == 0) {
                 const int64_t row = (g + 1) / c.rec.stride - c.step0 / c.rec.stride - 1;
-                if (row < c.rec.capacity) c.rec.v_out[row * nt + gi] = (float)vnew;
+                if (row < c.rec.capacity) c.rec.v_out[row * ST + so] = (float)vnew;
             }
         }
     }
@@ -527,6 +534,7 @@ struct StageBatch {
     StageFixed fx{};
     StageCtl *d_ctl = nullptr;
     int32_t *d_flag = nullptr;
+    bool own_flag = true;             // d_flag allocated by the batch
     float *X = nullptr;
     double *work = nullptr;
     hipGraph_t graph = nullptr;
@@ -679,7 +687,8 @@ void stage_net_free(StageNet *sn)
     delete sn;
 }
 
-psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch **out)
+psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch **out,
+                               int64_t st_stride, int64_t st_off)
 {
     *out = nullptr;
     if (!net->stage) return fail(PSST_ERR_UNSUPPORTED, "network has no per-stage layout");
@@ -727,6 +736,8 @@ psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch *
     fx.B = n_trials;
     fx.Bp = sb->Bp;
     fx.nt = nt;
+    fx.st_stride = st_stride > 0 ? st_stride : nt;
+    fx.st_off = st_off;
     fx.gabab = net->gabab ? 1 : 0;
     fx.cg = net->cg;
     fx.ci = net->ci;
@@ -769,11 +780,18 @@ void stage_batch_free(StageBatch *sb)
     (void)hipFree(sb->X);
     (void)hipFree(sb->work);
     (void)hipFree(sb->d_ctl);
-    (void)hipFree(sb->d_flag);
+    if (sb->own_flag) (void)hipFree(sb->d_flag);
     delete sb;
 }
 
 const char *stage_batch_describe(const StageBatch *sb) { return sb ? sb->desc.c_str() : ""; }
+
+void stage_batch_use_flag(StageBatch *sb, int32_t *flag)
+{
+    if (sb->own_flag) (void)hipFree(sb->d_flag);
+    sb->d_flag = flag;
+    sb->own_flag = false;
+}
 
 // Each workgroup column (one tile of trials) reads the whole padded matrix
 // once per stage launch.
