@@ -1470,6 +1470,7 @@ extern "C" psst_status psst_batch_create(psst_network *const *nets, int32_t n, p
                  g.order.size(), g.max_n, g.lg ? "lane-group, " : "", g.bs, g.npt, rr, g.lds);
         b->describe += buf;
     }
+    b->describe_groups = b->describe;
     for (StageBatch *sb : b->subs) {
         b->describe += stage_batch_describe(sb);
         b->describe += " ";
@@ -1881,7 +1882,14 @@ extern "C" psst_status psst_batch_set_tableau(psst_batch *b, const psst_tableau 
         stage_batch_set_method(b->stage, gen, t);
         b->describe = stage_batch_describe(b->stage);
     }
-    for (StageBatch *sb : b->subs) stage_batch_set_method(sb, gen, t);
+    if (!b->subs.empty()) {
+        b->describe = b->describe_groups;
+        for (StageBatch *sb : b->subs) {
+            stage_batch_set_method(sb, gen, t);
+            b->describe += stage_batch_describe(sb);
+            b->describe += " ";
+        }
+    }
     if (gen != b->gen && b->exec) {
         // the graph's kernel changes: build it again on the next call
         HIPCHK(hipGraphExecDestroy(b->exec));

@@ -126,6 +126,7 @@ struct psst_batch {
     // consecutive instances of one such network is a per-stage sub-batch
     // placed in the batch's arrays; the other instances take the groups
     std::vector<StageBatch *> subs;
+    std::string describe_groups;    // the launch groups' part of describe
     std::string describe;
     // graph of the persistent launches
     hipGraph_t graph = nullptr;

@@ -87,6 +87,30 @@ def test_mixed_batch_against_oracle_and_own_kind_bitwise():
     np.testing.assert_array_equal(g["state"][:, :, a:b], L["state"])
 
 
+def test_mixed_batch_tableau_and_description():
+    """An explicit method set on a mixed batch reaches its per-stage
+    sub-batches (the description follows), and the run matches the oracle's
+    run of that tableau."""
+    from paper_1906_03958_amd import psst
+    tab = W.TABLEAUX["heun"]
+    insts = _mixed()
+    nets = _nets(insts)
+    batch = psst.batch_create(nets)
+    assert "4 launches per step" in psst.batch_describe(batch)
+    psst.batch_set_tableau(batch, tab)
+    d = psst.batch_describe(batch)
+    assert "2 launches per step" in d and "4 launches per step" not in d, d
+    for h in nets:
+        psst.network_set_tableau(h, tab)
+    n = 200
+    g = R.gpu_run(insts, n, rec_stride=1, spike_cap=16, nets=nets)
+    o = R.oracle_run(insts, n, rec_stride=1, spike_cap=16, threads=6, tableau=tab)
+    dv = np.abs(g["v"].astype(np.float64) - o["v"]).max()
+    _say(f"  mixed batch, Heun: max|dV| {dv:.2e} mV")
+    assert dv <= 1e-3
+    np.testing.assert_array_equal(g["spike_count"], o["spike_count"])
+
+
 def test_only_large_networks_of_different_kinds():
     """No per-instance instance at all: two different large networks."""
     insts = _mixed()
