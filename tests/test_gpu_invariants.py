@@ -163,10 +163,11 @@ def _slow_gaba_large_network(n_pn=1536, n_ln=512):
     return W.Network(n, n_pn, W.hh_params(n), paths)
 
 
-def test_gates_stay_in_unit_interval_every_step_per_stage_path():
+@pytest.mark.parametrize("sparse", [False, True], ids=["dense", "sparse"])
+def test_gates_stay_in_unit_interval_every_step_per_stage_path(sparse):
     """Every step of 5 ms of a 2048-neuron network with slow GABA x 4 trials
-    on the per-stage matrix-core path (one-step calls; the state after each
-    is copied aside on the device)."""
+    on the per-stage path, matrix-core or sparse storage (one-step calls; the
+    state after each is copied aside on the device)."""
     import torch
     from paper_1906_03958_amd import psst
     dev = torch.device("cuda:0")
@@ -174,7 +175,7 @@ def test_gates_stay_in_unit_interval_every_step_per_stage_path():
     T = 4
     i_nA, v0 = W.trial_inputs(46, net.n, T)
     amp = W.rng_for(46, 0, W.S_PULSE).uniform(1.0, 10.0, net.n * T).astype(np.float32)
-    h = psst.network_create(net)
+    h = psst.network_create(net, storage=psst.STORAGE_SPARSE if sparse else None)
     batch = psst.batch_create([h] * T)
     nt = batch.n_total
     st = torch.zeros(14 * nt, dtype=torch.float32, device=dev)
