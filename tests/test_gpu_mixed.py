@@ -111,6 +111,46 @@ def test_mixed_batch_tableau_and_description():
     np.testing.assert_array_equal(g["spike_count"], o["spike_count"])
 
 
+def test_non_contiguous_runs_and_edge_networks():
+    """One large network in two separate runs (two sub-batches), a sparse
+    large network of projection neurons only (one synapse class) and one
+    whose fast-GABA pathway has no synapse at all, between small instances:
+    every instance against the oracle."""
+    import copy
+    from paper_1906_03958_amd import psst
+    big = W.all_pairs_network(55, 0, 825, 275, g_max=0.1)
+    pn_only = W.all_pairs_network(56, 0, 1030, 0, g_max=0.5, p=0.1)
+    pn_only.pathways = [w for w in pn_only.pathways if w.pre_end > w.pre_begin]
+    empty_gaba = W.all_pairs_network(57, 0, 780, 260, g_max=0.5, p=0.1)
+    empty_gaba = copy.deepcopy(empty_gaba)
+    w = empty_gaba.pathways[1]
+    w.mask[:] = 0
+    w.g_nS[:] = 0.0
+    insts = [_trial(big, 55, 0), W.config3_instance(7), _trial(big, 55, 1),
+             _trial(pn_only, 56, 0), _trial(empty_gaba, 57, 0), W.config3_instance(8)]
+    made = {}
+    nets = []
+    for inst in insts:
+        if id(inst.net) not in made:
+            sparse = inst.net is not big and inst.net.n > 1024
+            made[id(inst.net)] = psst.network_create(
+                inst.net, storage=psst.STORAGE_SPARSE if sparse else None)
+        nets.append(made[id(inst.net)])
+    desc = psst.batch_describe(psst.batch_create(nets))
+    _say(" ", desc)
+    assert desc.count("per-stage fp32 MFMA") == 2 and desc.count("per-stage sparse") == 2
+    n = 200
+    g = R.gpu_run(insts, n, rec_stride=1, spike_cap=16, nets=nets)
+    o = R.oracle_run(insts, n, rec_stride=1, spike_cap=16, threads=6)
+    offs = g["offsets"]
+    for k, inst in enumerate(insts):
+        a, b = offs[k], offs[k + 1]
+        dv = np.abs(g["v"][:, a:b].astype(np.float64) - o["v"][:, a:b]).max()
+        _say(f"  instance {k} (n={inst.net.n}): max|dV| {dv:.2e} mV")
+        assert dv <= 1e-3
+        np.testing.assert_array_equal(g["spike_count"][a:b], o["spike_count"][a:b])
+
+
 def test_only_large_networks_of_different_kinds():
     """No per-instance instance at all: two different large networks."""
     insts = _mixed()
