@@ -1654,14 +1654,19 @@ psst_status batch_launch_direct(psst_batch *b, float *states, const psst_stimulu
     if (b->stage_path)        // the per-stage graph: parameters go through its control block
         return stage_batch_integrate(b->stage, states, stim, dt, n_steps, step0, rec, nullptr, 0,
                                      stream);
-    // the launch groups side by side, as in the graph: the first on the
-    // caller's stream, the others on streams of their own forked from it
-    // and joined back
+    // the launch groups side by side, as in the graph: the heaviest on the
+    // caller's stream, the next on streams of their own forked from it and
+    // joined back, at most kDirectAux of them -- with the caller's stream and
+    // a copy stream that keeps the streams within the device's four hardware
+    // queues (streams beyond them share a queue and run one after another);
+    // the last of them takes the remaining groups in turn
+    constexpr size_t kDirectAux = 2;
     const hipStream_t st = (hipStream_t)stream;
     const size_t G = b->groups.size();
-    if (G > 1 && b->aux.size() < G - 1) {
+    const size_t S = std::min(G, 1 + kDirectAux);     // streams in use
+    if (S > 1 && b->aux.size() < S - 1) {
         if (!b->aux_fork) HIPCHK(hipEventCreateWithFlags(&b->aux_fork, hipEventDisableTiming));
-        while (b->aux.size() < G - 1) {
+        while (b->aux.size() < S - 1) {
             hipStream_t a = nullptr;
             HIPCHK(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
             b->aux.push_back(a);
@@ -1674,16 +1679,27 @@ psst_status batch_launch_direct(psst_batch *b, float *states, const psst_stimulu
         if ((s = stage_batch_integrate(sb, states, stim, dt, n_steps, step0, rec, nullptr, 0,
                                        stream)) != PSST_OK)
             return s;
-    if (G > 1) HIPCHK(hipEventRecord(b->aux_fork, st));
+    // groups by decreasing work (sum of n^2 over their instances)
+    std::vector<size_t> rank(G);
+    std::vector<double> work(G, 0.0);
     for (size_t k = 0; k < G; ++k) {
-        const Group &g = b->groups[k];
-        const hipStream_t gs = k == 0 ? st : b->aux[k - 1];
-        if (k > 0) HIPCHK(hipStreamWaitEvent(gs, b->aux_fork, 0));
+        rank[k] = k;
+        for (int32_t i : b->groups[k].order) work[k] += (double)b->nets[i]->n * b->nets[i]->n;
+    }
+    std::stable_sort(rank.begin(), rank.end(), [&](size_t x, size_t y) { return work[x] > work[y]; });
+    if (S > 1) HIPCHK(hipEventRecord(b->aux_fork, st));
+    for (size_t a = 0; a + 1 < S; ++a) HIPCHK(hipStreamWaitEvent(b->aux[a], b->aux_fork, 0));
+    for (size_t r = 0; r < G; ++r) {
+        const Group &g = b->groups[rank[r]];
+        const size_t si = std::min(r, S - 1);
+        const hipStream_t gs = si == 0 ? st : b->aux[si - 1];
         WGArgs a = group_args(b, g, states, stim, dt, n_steps, step0, rec, nullptr, 1);
         if ((s = launch_group(g, b->gen, a, gs)) != PSST_OK) return s;
-        if (k > 0) HIPCHK(hipEventRecord(b->aux_done[k - 1], gs));
     }
-    for (size_t k = 1; k < G; ++k) HIPCHK(hipStreamWaitEvent(st, b->aux_done[k - 1], 0));
+    for (size_t a = 0; a + 1 < S; ++a) {
+        HIPCHK(hipEventRecord(b->aux_done[a], b->aux[a]));
+        HIPCHK(hipStreamWaitEvent(st, b->aux_done[a], 0));
+    }
     return PSST_OK;
 }
 
