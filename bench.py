@@ -108,8 +108,14 @@ def kernel_sha(kernel):
     return h.hexdigest()[:16]
 
 
-def traffic_file(kernel):
-    return os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+# the workload a kernel's plain traffic file is taken on; others get their own
+PRIMARY_WORKLOAD = {"rk4_wg_kernel": "batched", "stage_kernel": "large"}
+
+
+def traffic_file(kernel, workload=None):
+    if workload is None or workload == PRIMARY_WORKLOAD.get(kernel):
+        return os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+    return os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
 
 
 def workload_key(args, workload=None):
@@ -119,7 +125,7 @@ def workload_key(args, workload=None):
     if wl == "adjoint":
         return {"workload": wl, "trials": args.adjoint_trials, "steps": args.adjoint_steps,
                 "K": args.adjoint_K}
-    if wl == "large":
+    if wl in ("large", "large-sparse"):
         return {"workload": wl}          # one launch is one stage whatever the chunk
     return {"workload": wl, "chunk": args.chunk, "instances": args.instances}
 
@@ -158,7 +164,7 @@ def write_traffic(args):
                fetch_bytes_per_launch=fetch, write_bytes_per_launch=write,
                hbm_bytes_per_launch=fetch + write, fetch_scale=kf, write_scale=kw,
                launches=len(f), copy_reference_bytes=ref)
-    with open(traffic_file(kernel), "w") as fh:
+    with open(traffic_file(kernel, args.workload), "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps(out))
@@ -251,7 +257,8 @@ def read_flops(kernel, args, workload=None):
 def read_traffic(kernel, args, workload=None):
     """HBM bytes per launch measured for this kernel source and workload, or
     None when no such measurement is on file."""
-    t = _on_file(traffic_file(kernel), kernel, workload_key(args, workload))
+    key = workload_key(args, workload)
+    t = _on_file(traffic_file(kernel, key["workload"]), kernel, key)
     return t.get("hbm_bytes_per_launch") if t else None
 
 
@@ -264,13 +271,12 @@ def run_large(args, torch, psst, W, dev, stream, steps, warmup, chunk, sparse=Fa
     (sparse: Bernoulli(0.1), g ~ U(0,0.5) nS, the same expected input, stored
     as synapse buckets), 64 stimulus trials; one step = chunk RK4 steps (a
     graph of the method's stage launches per RK4 step).  Returns the
-    measurements and the stage kernel's roofline (MFMA for the dense form,
-    float64 vector for the sparse one)."""
+    measurements and the stage kernel's fp32 MFMA roofline."""
     t0 = time.time()
     net = W.config4_network(p=0.1, g_max=0.5) if sparse else W.config4_network()
     B = W.CONFIG4_TRIALS
     i_nA, v0 = W.trial_inputs(4, net.n, B)
-    h = psst.network_create(net)
+    h = psst.network_create(net, storage=psst.STORAGE_SPARSE if sparse else psst.STORAGE_DENSE)
     if args.method != "rk4":
         psst.network_set_tableau(h, W.TABLEAUX[args.method])
     stages = len(W.TABLEAUX[args.method]["b"])
@@ -309,28 +315,39 @@ def run_large(args, torch, psst, W, dev, stream, steps, warmup, chunk, sparse=Fa
     stage_s = ev0.elapsed_time(ev1) / 1e3 / (stages * rk4_steps)
     _, g_bytes = psst.batch_conductance_bytes(batch)
     if sparse:
+        # useful work: one product per synapse and trial; the kernel runs the
+        # whole tiles (zeros included) on the matrix cores, as dense storage does
         nnz = int(sum(int(np.count_nonzero(p.mask)) for p in net.pathways))
         flops_stage = 2.0 * nnz * B
+        dense_flops = 2.0 * net.n * net.n * B
         achieved = flops_stage / stage_s / 1e12
+        traffic = read_traffic("stage_kernel", args, "large-sparse") if args.method == "rk4" else None
         res = {"value": nt * rk4_steps / wall, "unit": "neuron-steps/s",
                "wall_s": wall, "rk4_steps": rk4_steps,
                "ms_per_rk4_step": 1e3 * wall / rk4_steps,
                "workload": "large sparse network: 16384 HH neurons (12288 PN, 4096 LN), "
                            "Bernoulli(0.1) g ~ U(0,0.5) nS, 64 stimulus trials, dt 0.01 ms",
                "launch": psst.batch_describe(batch),
-               "roofline": {"bound": "alu", "achieved": round(achieved, 3),
-                            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                            "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-                            "traffic": None,
-                            "kernel": "stage_sparse_kernel (float64 fma per synapse and trial, "
-                                      "activations from LDS, + fused RK stage)",
+               "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
+                            "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4),
+                            "traffic": traffic,
+                            "traffic_GBps": round(traffic / stage_s / 1e9, 1) if traffic else None,
+                            "kernel": "stage_kernel<4,2,1,2,sparse> (conductance tiles built "
+                                      "in LDS from synapse buckets, fp32 MFMA GEMM, + fused "
+                                      "RK stage)",
                             "avg_launch_ms": round(1e3 * stage_s, 4),
                             "synapses": nnz,
                             "algorithmic_flops_per_launch": flops_stage,
+                            "tile_flops_per_launch": dense_flops,
+                            "tile_TFLOPs": round(dense_flops / stage_s / 1e12, 2),
+                            "tile_frac": round(dense_flops / stage_s / 1e12
+                                               / MFMA_FP32_PEAK_TFLOPS, 4),
                             "conductance_bytes_per_launch": g_bytes,
                             "conductance_GBps": round(g_bytes / stage_s / 1e9, 1),
-                            "note": "flops: one float64 fma per synapse and trial; launch "
-                                    f"time = graph time per step / {stages}"}}
+                            "note": "achieved: one product (2 flops) per synapse and trial; "
+                                    "tile_*: the n x n x trials products the matrix cores "
+                                    f"run; launch time = graph time per step / {stages}"}}
         del batch, h
         return res
     flops_stage = 2.0 * net.n * net.n * B
@@ -368,7 +385,7 @@ def bench_large(args, torch, psst, W, dev, stream, sparse=False):
            "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * r["wall_s"] / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64 (synaptic sums and RHS)" if sparse else "f32 (GEMM) / f64 (RHS)",
+           "dtype": "f32 (GEMM) / f64 (RHS)",
            "data": "synthetic",
            "config": {"workload": r["workload"], "rk4_steps_per_step": args.chunk,
                       "method": args.method, "launch": r["launch"]},

@@ -56,10 +56,9 @@
  * each state variable is stored as a float32 pair (value, compensation) whose
  * sum is the state after every step, rounded to 48 significant bits.  Large
  * shared networks on the per-stage path (more than 1024 neurons) take float32
- * activations, and with dense storage the synaptic sums from a float32
- * matrix-core GEMM: float32 sums over groups of 32 presynaptic columns, the
- * group sums added in float64 (sparse storage sums its exact float32
- * products in float64).
+ * activations and the synaptic sums from a float32 matrix-core GEMM: float32
+ * sums over groups of 32 presynaptic columns, the group sums added in
+ * float64 (with dense or sparse storage alike).
  */
 #ifndef PSST_H
 #define PSST_H
@@ -152,12 +151,14 @@ psst_status psst_network_destroy(psst_network *net);
  * order, partials in chunk order; absent synapses add exact zeros), so the
  * two give the same trajectory bit for bit.  SPARSE above 1024 neurons (the
  * per-stage path, networks shared by trials) keeps the synapses grouped by
- * 64-row block and 128-column tile, 5 bytes per synapse read once per stage
- * and tile of 64 trials; each float32 product is summed in float64 in
- * column order (a tile's sum added to its class total), which is exact to
- * float64 rounding rather than bitwise the dense path's float32 matrix-core
- * sums.  AUTO picks SPARSE when at most a quarter of the pathway entries are
- * synapses. */
+ * postsynaptic row and 128-column tile (a float32 value per synapse; per row
+ * and tile a start offset and a 128-bit column mask, 20 bytes), read once
+ * per stage and tile of 64 trials; each stage builds the dense conductance
+ * tiles from them in LDS and feeds the same matrix-core products as DENSE,
+ * so the two give the same trajectory bit for bit: SPARSE saves HBM, not
+ * time.  AUTO picks SPARSE when at most a quarter of the pathway entries are
+ * synapses, and above 1024 neurons only when the dense per-stage matrix
+ * would take more than 16 GiB. */
 typedef enum {
     PSST_STORAGE_AUTO = 0,
     PSST_STORAGE_DENSE = 1,

@@ -58,10 +58,10 @@ __global__ __launch_bounds__(256) void network_update_kernel(psst::NetUpdateArgs
                                                          : a.stage_ka + a.stage_kg + (j - a.n_pn));
             if (a.stage_G) a.stage_G[(int64_t)i * a.stage_Kp + k] = v;
             if (a.bk_val && present) {
-                // the synapse's bucket (64-row block, 128-column tile,
-                // wavefront, row) holds ascending columns: binary search
-                const int64_t ntl = a.stage_Kp / 128, il = i % 64;
-                const int64_t bk = (((int64_t)(i / 64) * ntl + k / 128) * 8 + il / 8) * 8 + il % 8;
+                // the synapse's bucket (64-row block, 128-column tile, row)
+                // holds ascending columns: binary search
+                const int64_t ntl = a.stage_Kp / 128;
+                const int64_t bk = ((int64_t)(i / 64) * ntl + k / 128) * 64 + i % 64;
                 int lo = a.bk_off[bk], hi = a.bk_off[bk + 1];
                 const int c = (int)(k % 128);
                 while (lo < hi) {

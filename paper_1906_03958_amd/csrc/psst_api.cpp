@@ -74,6 +74,9 @@ static bool is_finite_f(float x) { return std::isfinite(x); }
 static size_t max_lds_per_block();
 static bool fits_wg(const psst_network *q);
 static const int kMaxWGNeurons = 1024;   // largest network of the per-instance kernel
+// dense per-stage matrices up to this size stay dense under AUTO (16 GiB, a
+// network of about 65000 neurons)
+static const int64_t kStageDenseAutoBytes = 16LL << 30;
 static const int kMaxAdjointNeurons = 512;  // largest network of the adjoint
 
 // ---------------------------------------------------------------------------
@@ -196,8 +199,8 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
     net->g_floats = (int64_t)n * ld + (net->gabab ? (int64_t)n_ln * ld : 0);
     net->nch = n_chunks(n, p->n_pn, net->gabab);
 
-    // storage: sparse rows when asked, or (AUTO) when at most a quarter of the
-    // pathway entries are synapses; only on the per-instance path
+    // storage: sparse when asked, or (AUTO) when at most a quarter of the
+    // pathway entries are synapses
     int64_t present = 0;
     for (int q = 0; q < np; ++q) {
         const psst_pathway &w = paths[q];
@@ -221,9 +224,18 @@ static psst_status network_create_impl(const psst_neuron_params *p, int32_t n,
                 }
         }
     }
+    // AUTO above the per-instance limit keeps dense storage unless the dense
+    // per-stage matrix would take more than kStageDenseAutoBytes: the sparse
+    // form builds the same matrix-core tiles in LDS (bit for bit the same
+    // run), which saves HBM but adds the tile build to every stage
+    const int64_t stage_dense_bytes = 4LL * ((n + 63) / 64 * 64) *
+                                      ((int64_t)((p->n_pn + 127) / 128) * 128 +
+                                       (net->gabab ? 2LL : 1LL) * ((n_ln + 127) / 128) * 128);
     bool sparse = false;
     if (storage == PSST_STORAGE_SPARSE) sparse = np > 0;
-    else if (storage == PSST_STORAGE_AUTO) sparse = np > 0 && 4 * present <= goff;
+    else if (storage == PSST_STORAGE_AUTO)
+        sparse = np > 0 && 4 * present <= goff &&
+                 (n <= kMaxWGNeurons || stage_dense_bytes > kStageDenseAutoBytes);
     // above the per-instance limit the per-stage path keeps its own sparse
     // layout (synapse buckets) instead of the ELL rows
     const bool stage_sparse = sparse && n > kMaxWGNeurons;

@@ -14,11 +14,13 @@
 // slow-GABA LN columns [ka + kg, Kp).  Padding rows and columns are zero.
 //
 // Sparse storage keeps, instead of G, the synapses themselves grouped by
-// (64-row block, 128-column tile, wavefront, row): the row block's wavefront
-// w owns its rows 8w .. 8w + 7, and bucket ((rb * ntl + kt) * 8 + w) * 8 + r
-// holds row 64 rb + 8 w + r's synapses in tile kt, by ascending column --
-// sp_off[bucket] .. sp_off[bucket + 1] - 1 index sp_col (the column within
-// the tile) and sp_val (nS).
+// (64-row block rb, 128-column tile kt, row r of the block): bucket
+// (rb * ntl + kt) * 64 + r holds row 64 rb + r's synapses in tile kt, by
+// ascending column -- sp_off[bucket] .. sp_off[bucket + 1] - 1 index sp_col
+// (the column within the tile; read by in-place updates only) and sp_val
+// (nS); sp_mask[4 bucket .. 4 bucket + 3] has bit c set for each column c of
+// the tile the bucket holds, so a synapse's place in its bucket is the count
+// of set bits below its column.
 struct StageNet {
     float *G = nullptr;
     int n = 0, n_pn = 0, Mp = 0, Kp = 0, ka = 0, kg = 0, kb = 0;
@@ -27,6 +29,7 @@ struct StageNet {
     int32_t *sp_off = nullptr;
     uint8_t *sp_col = nullptr;
     float *sp_val = nullptr;
+    uint32_t *sp_mask = nullptr;   // per bucket: which of the tile's 128 columns it holds
     int64_t nnz = 0;
 };
 

@@ -67,6 +67,7 @@ struct StageFixed {
     const int32_t *sp_off;    // sparse storage: synapse buckets (stage.h)
     const uint8_t *sp_col;
     const float *sp_val;
+    const uint32_t *sp_mask;
     int Kp, ka, kg;           // K blocks [0,ka) ACh, [ka,ka+kg) fast GABA, [ka+kg,Kp) slow GABA
     float *X0, *X1;           // [Bp][Kp] activations (double-buffered by stage launch)
     double *Yw, *accw;        // [NVAR][nt] stage input and RK4 accumulator
@@ -269,7 +270,11 @@ __device__ __forceinline__ void stage_epilogue(const StageFixed &fx,
 
 // One workgroup per CU (its LDS tiles take most of the CU's LDS); WR x WC
 // wavefronts, each owning BR x BC blocks of 16 x 16 outputs.
-template <int WR, int WC, int BR, int BC, bool GEN>
+// SP: sparse storage -- each conductance tile is built in LDS from the row
+// block's synapse buckets (zeros elsewhere) instead of being loaded dense, so
+// the products, and the results, are those of dense storage bit for bit
+// while HBM carries only the synapses.
+template <int WR, int WC, int BR, int BC, bool GEN, bool SP = false>
 __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR * WC / 4, WR * WC / 4))) void stage_kernel(StageFixed fx, const StageCtl *__restrict__ dctl,
                                                     int q)
 {
@@ -314,27 +319,93 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
         const int kend = blk == 0 ? fx.ka : (blk == 1 ? fx.ka + fx.kg : fx.Kp);
         const int ntile = (kend - kbeg) / KT;
         if (ntile == 0) continue;
-        floatx4 rg[GV], rx[XVT];
+        floatx4 rg[SP ? 1 : GV], rx[XVT];
+        // sparse source: thread tid builds row sr of the tile, columns
+        // [sk SW, (sk + 1) SW) -- zeros, then its synapses there.  The row's
+        // bucket mask and start (loaded a tile ahead) give the segment's
+        // synapses: they follow the bucket's start by the number of set bits
+        // below the segment, in column order; the first SPV of them are
+        // loaded a tile ahead like the dense rows (SPV covers a segment's
+        // count at p = 0.1 but for about one segment in a thousand), the rest
+        // when the tile is built
+        constexpr int SEG = NTH / MT, SW = KT / SEG, SPV = SW == 32 ? 8 : 6;
+        static_assert(SW == 16 || SW == 32, "segment of a mask word or half a word");
+        const int sr = tid / SEG, sk = tid % SEG;
+        uint32_t nmask[4] = {0u, 0u, 0u, 0u};
+        int nb0 = 0;                        // the next tile's bucket
+        uint32_t seg = 0;                   // the loaded tile's segment bits
+        int sbase = 0;                      // its first synapse
+        float spv[SP ? SPV : 1];
+        auto sp_bucket = [&](int kt) {      // kt: tile on the whole K axis
+            const int64_t bk = ((int64_t)blockIdx.x * (fx.Kp / KT) + kt) * MT + sr;
+            const uint4 m = *reinterpret_cast<const uint4 *>(fx.sp_mask + 4 * bk);
+            nmask[0] = m.x, nmask[1] = m.y, nmask[2] = m.z, nmask[3] = m.w;
+            nb0 = fx.sp_off[bk];
+        };
+        auto sp_load = [&](int kt_next) {
+            const int w = (sk * SW) / 32, sh = (sk * SW) % 32;
+            int below = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) below += i < w ? __builtin_popcount(nmask[i]) : 0;
+            uint32_t mw = nmask[0];
+#pragma unroll
+            for (int i = 1; i < 4; ++i) mw = i == w ? nmask[i] : mw;
+            below += __builtin_popcount(sh ? mw & ((1u << sh) - 1u) : 0u);
+            seg = SW == 32 ? mw : (mw >> sh) & 0xFFFFu;
+            sbase = nb0 + below;
+            const int cnt = __builtin_popcount(seg);
+#pragma unroll
+            for (int u = 0; u < SPV; ++u) spv[u] = fx.sp_val[u < cnt ? sbase + u : nb0];
+            sp_bucket(kt_next);
+        };
         auto tile_store = [&](int t) {
             float *g = sG + (t & 1) * MT * LDK;
             float *x = sX + (t & 1) * NTILE * LDK;
+            if constexpr (SP) {
+                float *row = g + sr * LDK + sk * SW;
 #pragma unroll
-            for (int u = 0; u < GV; ++u)
-                *reinterpret_cast<floatx4 *>(g + (lr + RPP * u) * LDK + lk) = rg[u];
+                for (int c = 0; c < SW; c += 4)
+                    *reinterpret_cast<floatx4 *>(row + c) = floatx4{0.f, 0.f, 0.f, 0.f};
+                uint32_t m = seg;
+                for (int u = 0; m; ++u, m &= m - 1u) {
+                    const int c = __builtin_ctz(m);
+                    float v = fx.sp_val[u < SPV ? nb0 : sbase + u];   // the rare long segments
+#pragma unroll
+                    for (int k = 0; k < SPV; ++k) v = u == k ? spv[k] : v;
+                    row[c] = v;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < GV; ++u)
+                    *reinterpret_cast<floatx4 *>(g + (lr + RPP * u) * LDK + lk) = rg[u];
+            }
 #pragma unroll
             for (int u = 0; u < XVT; ++u)
                 *reinterpret_cast<floatx4 *>(x + (lr + RPP * u) * LDK + lk) = rx[u];
+        };
+        // load tile t of this block (at column kbeg + t KT) into registers
+        auto load_tile = [&](int t) {
+            if constexpr (SP) {
+                sp_load(kbeg / KT + min(t + 1, ntile - 1));
+#pragma unroll
+                for (int u = 0; u < XVT; ++u)
+                    rx[u] = *reinterpret_cast<const floatx4 *>(
+                        X + (int64_t)(n0 + lr + RPP * u) * fx.Kp + kbeg + t * KT + lk);
+            } else {
+                tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, kbeg + t * KT);
+            }
         };
         // tile t + 1 is loaded into registers while tile t feeds the matrix
         // cores, and stored to the other LDS buffer right after tile t's last
         // products are issued (its stores overlap them) and before the one
         // barrier per tile; the last tile is loaded and stored once more past
         // the end (in bounds, never read), so every iteration is the same
-        const auto next = [&](int t) { return kbeg + min(t, ntile - 1) * KT; };
-        tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, kbeg);
+        const auto last = [&](int t) { return min(t, ntile - 1); };
+        if constexpr (SP) sp_bucket(kbeg / KT);
+        load_tile(0);
         __syncthreads();     // previous users of the tile buffers are done
         tile_store(0);
-        tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, next(1));
+        load_tile(last(1));
         __syncthreads();
         for (int t = 0; t < ntile; ++t) {
             const float *g = sG + (t & 1) * MT * LDK;
@@ -385,7 +456,7 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
             }
             // the other buffer was last read before the previous barrier
             tile_store(t + 1);
-            tile_load<GV, XVT, RPP>(rg, rx, fx.G, X, fx.Kp, m0, n0, lr, lk, next(t + 2));
+            load_tile(last(t + 2));
             __syncthreads();
         }
     }
@@ -406,123 +477,6 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
                 }
     __syncthreads();
 
-    stage_epilogue<NTILE, NTH, GEN>(fx, dctl, q, sA, Xn, m0, n0, tid);
-}
-
-// Sparse storage: one workgroup per 64-row block and tile of 64 trials,
-// lane = trial.  The activations of each 128-column tile are staged in LDS
-// transposed (column-major: a column's 64 trials are contiguous), double
-// buffered like the dense kernel's tiles; wavefront w walks its rows'
-// synapses in the tile (64 at a time loaded into registers, one per lane,
-// then taken lane by lane), so each synapse costs one conflict-free LDS read
-// of 64 activations and one float64 fma per trial.  A row's tile sum starts
-// from zero and is added to its class total in float64; the column order of
-// every sum is fixed, so results do not depend on the trials' grouping.
-constexpr int XLD = 64 + 1;   // LDS stride (floats) of a transposed activation column
-constexpr size_t sparse_lds_bytes()
-{
-    const size_t tiles = sizeof(float) * 2 * KT * XLD;
-    const size_t acc = sizeof(double) * 3 * MT * (64 + 1);
-    return tiles > acc ? tiles : acc;
-}
-
-template <bool GEN>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void stage_sparse_kernel(
-    StageFixed fx, const StageCtl *__restrict__ dctl, int q)
-{
-    constexpr int NTILE = 64, NTH = 512;
-    extern __shared__ float smem[];
-    const int rb = blockIdx.x, m0 = rb * MT, n0 = blockIdx.y * NTILE;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t k_launch = (dctl->g - dctl->step0) * (GEN ? fx.tab.s : 4) + q;
-    const float *X = (k_launch & 1) ? fx.X1 : fx.X0;
-    float *Xn = (k_launch & 1) ? fx.X0 : fx.X1;
-    const int ntl = fx.Kp / KT;
-
-    // tile loads: 64 trials x 128 columns, four float4 per thread (trial
-    // row lb + 16 u, columns lc .. lc + 3)
-    const int lb = tid >> 5, lc = (tid & 31) * 4;
-    floatx4 rx[4];
-    auto xload = [&](int kt) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            rx[u] = *reinterpret_cast<const floatx4 *>(X + (int64_t)(n0 + lb + 16 * u) * fx.Kp +
-                                                       kt * KT + lc);
-    };
-    auto xstore = [&](int kt) {
-        float *x = smem + (kt & 1) * KT * XLD;
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) x[(lc + e) * XLD + lb + 16 * u] = rx[u][e];
-    };
-    double acc[3][8];
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-        for (int r = 0; r < 8; ++r) acc[t][r] = 0.0;
-    xload(0);
-    xstore(0);
-    if (ntl > 1) xload(1);
-    __syncthreads();
-    const int32_t *offw = fx.sp_off + ((int64_t)rb * ntl * 8 + wave) * 8;
-    for (int kt = 0; kt < ntl; ++kt) {
-        const float *x = smem + (kt & 1) * KT * XLD + lane;
-        const int32_t *o = offw + (int64_t)kt * 64;
-        int ob[9];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) ob[r] = o[r];
-        double ta[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) ta[r] = 0.0;
-        for (int base = ob[0]; base < ob[8]; base += 64) {
-            const int e = base + lane < ob[8] ? base + lane : ob[8] - 1;
-            const float lv = fx.sp_val[e];
-            const int lcol = fx.sp_col[e];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int j0 = (ob[r] > base ? ob[r] : base) - base;
-                const int j1 = (ob[r + 1] < base + 64 ? ob[r + 1] : base + 64) - base;
-                // four activations in flight, then their fmas in column order
-                int j = j0;
-                for (; j + 4 <= j1; j += 4) {
-                    float xv[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) xv[u] = x[__builtin_amdgcn_readlane(lcol, j + u) * XLD];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const float g = __builtin_bit_cast(
-                            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lv), j + u));
-                        ta[r] = fma((double)g, (double)xv[u], ta[r]);
-                    }
-                }
-                for (; j < j1; ++j) {
-                    const float g = __builtin_bit_cast(
-                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lv), j));
-                    ta[r] = fma((double)g, (double)x[__builtin_amdgcn_readlane(lcol, j) * XLD],
-                                ta[r]);
-                }
-            }
-        }
-        const int t = kt * KT < fx.ka ? 0 : (kt * KT < fx.ka + fx.kg ? 1 : 2);
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            if (t == 0) acc[0][r] += ta[r];
-            else if (t == 1) acc[1][r] += ta[r];
-            else acc[2][r] += ta[r];
-        }
-        // the other buffer was last read before the previous barrier
-        if (kt + 1 < ntl) xstore(kt + 1);
-        if (kt + 2 < ntl) xload(kt + 2);
-        __syncthreads();
-    }
-    double *sA = reinterpret_cast<double *>(smem);   // [3][MT][NTILE + 1]
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-        for (int r = 0; r < 8; ++r) sA[(t * MT + 8 * wave + r) * (NTILE + 1) + lane] = acc[t][r];
-    __syncthreads();
     stage_epilogue<NTILE, NTH, GEN>(fx, dctl, q, sA, Xn, m0, n0, tid);
 }
 
@@ -557,10 +511,7 @@ static psst_status stage_net_sparse(StageNet *sn, const psst_network *net,
                                       : (w.type == PSST_SYN_GABA_A ? sn->ka + (j - net->n_pn)
                                                                    : sn->ka + sn->kg + (j - net->n_pn));
     };
-    auto bucket = [&](int i, int k) {
-        const int il = i % MT;
-        return (((int64_t)(i / MT) * ntl + k / KT) * 8 + il / 8) * 8 + il % 8;
-    };
+    auto bucket = [&](int i, int k) { return ((int64_t)(i / MT) * ntl + k / KT) * MT + i % MT; };
     std::vector<int64_t> off(nb + 1, 0);
     for (int q = 0; q < np; ++q) {
         const psst_pathway &w = paths[q];
@@ -576,8 +527,10 @@ static psst_status stage_net_sparse(StageNet *sn, const psst_network *net,
     if (nnz >= ((int64_t)1 << 31))
         return fail(PSST_ERR_UNSUPPORTED, "%lld synapses exceed the sparse layout's 2^31",
                     (long long)nnz);
-    std::vector<uint8_t> col((size_t)std::max<int64_t>(nnz, 1));
-    std::vector<float> val((size_t)std::max<int64_t>(nnz, 1));
+    // one entry more than the synapses: a kernel's read at the start of an
+    // empty last bucket stays in bounds (its value is never used)
+    std::vector<uint8_t> col((size_t)nnz + 1, 0);
+    std::vector<float> val((size_t)nnz + 1, 0.f);
     std::vector<int64_t> pos(off.begin(), off.end() - 1);
     for (int q = 0; q < np; ++q) {
         const psst_pathway &w = paths[q];
@@ -608,6 +561,9 @@ static psst_status stage_net_sparse(StageNet *sn, const psst_network *net,
             val[p] = tmp[p - b0].second;
         }
     }
+    std::vector<uint32_t> mask((size_t)nb * 4, 0u);
+    for (int64_t b = 0; b < nb; ++b)
+        for (int64_t p = off[b]; p < off[b + 1]; ++p) mask[4 * b + col[p] / 32] |= 1u << (col[p] % 32);
     std::vector<int32_t> off32(off.begin(), off.end());
     hipError_t e = hipMalloc(&sn->sp_off, sizeof(int32_t) * off32.size());
     if (e == hipSuccess)
@@ -617,6 +573,9 @@ static psst_status stage_net_sparse(StageNet *sn, const psst_network *net,
     if (e == hipSuccess) e = hipMalloc(&sn->sp_val, sizeof(float) * val.size());
     if (e == hipSuccess)
         e = hipMemcpy(sn->sp_val, val.data(), sizeof(float) * val.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&sn->sp_mask, sizeof(uint32_t) * mask.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(sn->sp_mask, mask.data(), sizeof(uint32_t) * mask.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess)
         return fail(e == hipErrorOutOfMemory ? PSST_ERR_OUT_OF_MEMORY : PSST_ERR_DEVICE,
                     "sparse stage layout upload failed: %s", hipGetErrorString(e));
@@ -684,6 +643,7 @@ void stage_net_free(StageNet *sn)
     (void)hipFree(sn->sp_off);
     (void)hipFree(sn->sp_col);
     (void)hipFree(sn->sp_val);
+    (void)hipFree(sn->sp_mask);
     delete sn;
 }
 
@@ -696,7 +656,7 @@ psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch *
     StageBatch *sb = new StageBatch();
     sb->net = net;
     sb->B = n_trials;
-    sb->ntile = n_trials <= 16 && !sn->sparse ? 16 : 64;
+    sb->ntile = n_trials <= 16 ? 16 : 64;
     sb->Bp = round_up(n_trials, sb->ntile);
     const int64_t nt = (int64_t)n_trials * net->n;
     hipError_t e = hipSuccess;
@@ -719,6 +679,7 @@ psst_status stage_batch_create(psst_network *net, int32_t n_trials, StageBatch *
     fx.sp_off = sn->sp_off;
     fx.sp_col = sn->sp_col;
     fx.sp_val = sn->sp_val;
+    fx.sp_mask = sn->sp_mask;
     fx.Kp = sn->Kp;
     fx.ka = sn->ka;
     fx.kg = sn->kg;
@@ -761,9 +722,9 @@ void stage_batch_set_method(StageBatch *sb, bool gen, const Tab &tab)
     char buf[256];
     if (sn->sparse)
         snprintf(buf, sizeof buf,
-                 "[per-stage sparse: %d rows x %d trials (tile 64 x 64), %lld synapses, K %d, %d "
-                 "launches per step]",
-                 sn->Mp, sb->Bp, (long long)sn->nnz, sn->Kp, gen ? tab.s : 4);
+                 "[per-stage sparse: fp32 MFMA GEMM on tiles built from %lld synapses, %d rows x "
+                 "%d trials (tile 64 x %d), K %d, %d launches per step]",
+                 (long long)sn->nnz, sn->Mp, sb->Bp, sb->ntile, sn->Kp, gen ? tab.s : 4);
     else
         snprintf(buf, sizeof buf,
                  "[per-stage fp32 MFMA GEMM: %d rows x %d trials (tile 64 x %d), K %d, %d launches "
@@ -794,18 +755,28 @@ void stage_batch_use_flag(StageBatch *sb, int32_t *flag)
 }
 
 // Each workgroup column (one tile of trials) reads the whole padded matrix
-// once per stage launch.
+// once per stage launch; sparse storage: every synapse's value and every
+// bucket's start and column mask.
 int64_t stage_batch_matrix_bytes(const StageBatch *sb)
 {
     const StageNet *sn = sb->net->stage;
     if (sn->sparse)
-        return ((int64_t)sizeof(float) + 1) * sn->nnz * (sb->Bp / sb->ntile) +
-               (int64_t)sizeof(int32_t) * ((int64_t)sn->Mp / MT * (sn->Kp / KT) * 64 + 1);
+        return ((int64_t)sizeof(float) * sn->nnz +
+                (int64_t)(sizeof(int32_t) + 4 * sizeof(uint32_t)) * sn->Mp / MT * (sn->Kp / KT) *
+                    MT) *
+               (sb->Bp / sb->ntile);
     return (int64_t)sizeof(float) * sn->Mp * sn->Kp * (sb->Bp / sb->ntile);
 }
 
-static const void *stage_fn(int ntile, bool gen)
+static const void *stage_fn(int ntile, bool gen, bool sparse)
 {
+    if (sparse) {
+        if (gen)
+            return ntile == 16 ? (const void *)stage_kernel<4, 1, 1, 1, true, true>
+                               : (const void *)stage_kernel<4, 2, 1, 2, true, true>;
+        return ntile == 16 ? (const void *)stage_kernel<4, 1, 1, 1, false, true>
+                           : (const void *)stage_kernel<4, 2, 1, 2, false, true>;
+    }
     if (gen)
         return ntile == 16 ? (const void *)stage_kernel<4, 1, 1, 1, true>
                            : (const void *)stage_kernel<4, 2, 1, 2, true>;
@@ -820,11 +791,8 @@ static size_t stage_lds_bytes(int ntile) { return sizeof(float) * stage_lds_floa
 // One step as a graph: its stages (4 for RK4) then the step-counter advance.
 static psst_status build_graph(StageBatch *sb)
 {
-    const bool sparse = sb->net->stage->sparse;
-    const size_t lds = sparse ? sparse_lds_bytes() : stage_lds_bytes(sb->ntile);
-    const void *fn = sparse ? (sb->gen ? (const void *)stage_sparse_kernel<true>
-                                       : (const void *)stage_sparse_kernel<false>)
-                            : stage_fn(sb->ntile, sb->gen);
+    const size_t lds = stage_lds_bytes(sb->ntile);
+    const void *fn = stage_fn(sb->ntile, sb->gen, sb->net->stage->sparse);
     HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     HIPCHK(hipGraphCreate(&sb->graph, 0));
     hipGraphNode_t prev = nullptr;

@@ -42,13 +42,19 @@ def _mixed():
 
 
 def _nets(insts):
+    """Device networks, one per distinct network; sparse storage for every
+    network above 1024 neurons at density 0.25 or less."""
     from paper_1906_03958_amd import psst
     made = {}
     out = []
     for inst in insts:
         key = id(inst.net)
         if key not in made:
-            made[key] = psst.network_create(inst.net)
+            dens = (sum(int(np.count_nonzero(w.mask)) for w in inst.net.pathways)
+                    / max(1, sum(w.mask.size for w in inst.net.pathways)))
+            sparse = inst.net.n > 1024 and dens <= 0.25
+            made[key] = psst.network_create(inst.net,
+                                            storage=psst.STORAGE_SPARSE if sparse else None)
         out.append(made[key])
     return out
 

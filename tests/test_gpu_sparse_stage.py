@@ -33,9 +33,10 @@ def _trials(net, cfg, n_trials, first=0):
     return [W.Instance(net, v0[t], W.Stimulus(i_nA[t])) for t in range(n_trials)]
 
 
-def _run(net, insts, n_steps, storage=None, rec_stride=1, spike_cap=16, tableau=None):
+def _run(net, insts, n_steps, storage="sparse", rec_stride=1, spike_cap=16, tableau=None):
     from paper_1906_03958_amd import psst
-    h = psst.network_create(net, storage=storage)
+    h = psst.network_create(net, storage={"sparse": psst.STORAGE_SPARSE,
+                                          "dense": psst.STORAGE_DENSE, None: None}[storage])
     if tableau is not None:
         psst.network_set_tableau(h, tableau)
     desc = psst.batch_describe(psst.batch_create([h] * len(insts)))
@@ -61,14 +62,19 @@ def _check(g, o, net, picks, n_steps):
 
 def test_sparse_large_network_against_oracle():
     """2048 neurons (1536 PN + 512 LN), p = 0.1 with g ~ U(0, 0.5) nS (the
-    expected input of the p = 0.5, U(0, 0.1) network), 8 trials, 30 ms; the
-    storage choice (AUTO) takes the sparse form."""
+    expected input of the p = 0.5, U(0, 0.1) network), 8 trials, 30 ms,
+    against the oracle and bit for bit against the same network under AUTO
+    storage, which keeps a network of this size dense."""
     net = W.all_pairs_network(48, 0, 1536, 512, g_max=0.5, p=0.1)
     insts = _trials(net, 48, 8)
     n = 3000
     g, desc = _run(net, insts, n)
     _say("sparse per-stage:", desc)
     assert "sparse" in desc
+    a, adesc = _run(net, insts, n, storage=None)
+    assert "sparse" not in adesc and "MFMA" in adesc, adesc
+    np.testing.assert_array_equal(g["v"], a["v"])
+    np.testing.assert_array_equal(g["spike_t"], a["spike_t"])
     picks = [0, 7]
     o = R.oracle_run([insts[t] for t in picks], n, rec_stride=1, spike_cap=16, threads=2)
     _check(g, o, net, picks, n)
@@ -127,17 +133,22 @@ def test_sparse_large_tableau():
 
 def test_sparse_forced_on_a_dense_network():
     """Sparse storage asked for on a p = 0.5 network of 1100 neurons: the
-    sparse path and the matrix-core path both match the oracle."""
+    sparse path and the matrix-core path both match the oracle, and each
+    other bit for bit (the sparse path builds the same conductance tiles in
+    LDS that dense storage loads)."""
     from paper_1906_03958_amd import psst
     net = W.all_pairs_network(51, 0, 825, 275, g_max=0.1)
     insts = _trials(net, 51, 2)
     n = 300
-    s, ds = _run(net, insts, n, storage=psst.STORAGE_SPARSE)
-    d, dd = _run(net, insts, n)
+    s, ds = _run(net, insts, n)
+    d, dd = _run(net, insts, n, storage=None)
     assert "sparse" in ds and "MFMA" in dd
     o = R.oracle_run(insts, n, rec_stride=1, spike_cap=16)
     _check(s, o, net, [0, 1], n)
     _check(d, o, net, [0, 1], n)
+    np.testing.assert_array_equal(s["v"], d["v"])
+    np.testing.assert_array_equal(s["state"], d["state"])
+    np.testing.assert_array_equal(s["spike_t"], d["spike_t"])
 
 
 def test_sparse_large_trial_invariance_bitwise():
