@@ -325,9 +325,9 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
         // bucket mask and start (loaded a tile ahead) give the segment's
         // synapses: they follow the bucket's start by the number of set bits
         // below the segment, in column order; the first SPV of them are
-        // loaded a tile ahead like the dense rows (SPV covers a segment's
-        // count at p = 0.1 but for about one segment in a thousand), the rest
-        // when the tile is built
+        // loaded a tile ahead like the dense rows (at p = 0.1 a 16-column
+        // segment holds more about once in 2,000), the rest when the tile is
+        // built
         constexpr int SEG = NTH / MT, SW = KT / SEG, SPV = SW == 32 ? 8 : 6;
         static_assert(SW == 16 || SW == 32, "segment of a mask word or half a word");
         const int sr = tid / SEG, sk = tid % SEG;
@@ -363,17 +363,23 @@ __global__ __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR
             float *x = sX + (t & 1) * NTILE * LDK;
             if constexpr (SP) {
                 float *row = g + sr * LDK + sk * SW;
+                // zeros, 16 bytes at a time; the start is rotated by the
+                // segment's place so the segments of a row begin in
+                // different banks
 #pragma unroll
-                for (int c = 0; c < SW; c += 4)
+                for (int j = 0; j < SW / 4; ++j) {
+                    const int c = ((j + sk * SW / 64) % (SW / 4)) * 4;
                     *reinterpret_cast<floatx4 *>(row + c) = floatx4{0.f, 0.f, 0.f, 0.f};
-                uint32_t m = seg;
-                for (int u = 0; m; ++u, m &= m - 1u) {
-                    const int c = __builtin_ctz(m);
-                    float v = fx.sp_val[u < SPV ? nb0 : sbase + u];   // the rare long segments
-#pragma unroll
-                    for (int k = 0; k < SPV; ++k) v = u == k ? spv[k] : v;
-                    row[c] = v;
                 }
+                uint32_t m = seg;
+#pragma unroll
+                for (int k = 0; k < SPV; ++k)
+                    if (m) {
+                        row[__builtin_ctz(m)] = spv[k];
+                        m &= m - 1u;
+                    }
+                for (int u = SPV; m; ++u, m &= m - 1u)      // the rare long segments
+                    row[__builtin_ctz(m)] = fx.sp_val[sbase + u];
             } else {
 #pragma unroll
                 for (int u = 0; u < GV; ++u)
