@@ -31,7 +31,9 @@ def test_recorded_rooflines_are_fractions_of_the_peak():
     for traffic, md, row in (("rk4_wg_kernel_traffic.txt", "rk4_wg_kernel_batched_4096.md",
                               "rk4_wg_kernel<512"),
                              ("stage_kernel_traffic.txt", "stage_kernel_large_16384.md",
-                              "stage_kernel<4")):
+                              "stage_kernel<4"),
+                             ("stage_kernel_large-sparse_traffic.txt",
+                              "stage_kernel_large_sparse_16384.md", "stage_kernel<4")):
         t = json.load(open(os.path.join(ROOT, "profiles", traffic)))
         ms = _avg_ms(md, row)
         frac = t["hbm_bytes_per_launch"] / (ms / 1e3) / 8e12
@@ -68,3 +70,33 @@ def test_per_launch_counters_sum_the_kernels_of_a_launch(tmp_path):
             fh.write(f'"{k}",{g},FETCH_SIZE,{v},{int(a)},{int(b)}\n')
     total, n = bench._per_launch(str(path), "k<", "FETCH_SIZE")
     assert total == 11.0 + 3.0 + 6.0 and n == 2
+
+
+def test_traffic_on_file_is_keyed_by_workload_and_source(tmp_path):
+    """The stage kernel's counter bytes for dense and sparse storage live in
+    files of their own, each read back only for its workload, and only while
+    the kernel's sources hash to the value recorded with them."""
+    import argparse
+    import importlib.util
+    import json
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    dense = bench.traffic_file("stage_kernel", "large")
+    sparse = bench.traffic_file("stage_kernel", "large-sparse")
+    assert dense.endswith("stage_kernel_traffic.txt") and sparse != dense
+    args = argparse.Namespace(workload="large", chunk=100, instances=4096)
+    for path, wl in ((dense, "large"), (sparse, "large-sparse")):
+        t = json.load(open(path))
+        assert t["workload"] == wl
+        if t["kernel_source_sha"] == bench.kernel_sha("stage_kernel"):
+            assert bench.read_traffic("stage_kernel", args, wl) == t["hbm_bytes_per_launch"]
+    # a record taken on other sources, or on another workload, is not used
+    rec = json.load(open(dense))
+    cur = dict(rec, kernel_source_sha=bench.kernel_sha("stage_kernel"))
+    for t, key, used in ((cur, {"workload": "large"}, True),
+                         (cur, {"workload": "large-sparse"}, False),
+                         (dict(rec, kernel_source_sha="0" * 16), {"workload": "large"}, False)):
+        path = tmp_path / "t.json"
+        path.write_text(json.dumps(t))
+        assert (bench._on_file(str(path), "stage_kernel", key) is not None) == used
