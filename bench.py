@@ -647,8 +647,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=20000)
     ap.add_argument("--adjoint-K", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--large-steps", type=int, default=5,
-                    help="timed steps of 10 RK4 steps of the large-network leg")
+    ap.add_argument("--large-steps", type=int, default=10,
+                    help="timed steps of 20 RK4 steps of the large-network leg")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -871,7 +871,7 @@ def main():
     # ---------------- the large network (per-stage MFMA path), short ------
     large = None
     if not (args.no_large or uncoupled or sparse) and args.method == "rk4":
-        large = run_large(args, torch, psst, W, dev, stream, args.large_steps, 1, 10)
+        large = run_large(args, torch, psst, W, dev, stream, args.large_steps, 2, 20)
         log(f"large network: {large['value']:.3e} neuron-steps/s, MFMA "
             f"{large['roofline']['achieved']} TFLOP/s ({large['roofline']['frac']} of peak)")
 
