@@ -308,7 +308,9 @@ psst_status psst_batch_describe(const psst_batch *batch, char *buf, int32_t buf_
  * instance's whole sparse rows, or a small network's whole matrices held in
  * registers),
  * streamed_bytes once per stage evaluation (the rest; on the
- * per-stage path of a large shared network, its whole padded matrix).  Trials
+ * per-stage path of a large shared network, its whole padded matrix, or
+ * with sparse storage every synapse value and every bucket's start and
+ * column mask).  Trials
  * that share one network count once per workgroup that reads it.  Either
  * pointer may be NULL.  Synchronous, no device call. */
 psst_status psst_batch_conductance_bytes(const psst_batch *batch, int64_t *resident_bytes,
