@@ -1,8 +1,9 @@
 """Sparse storage of networks above 1024 neurons (the per-stage path's
 synapse buckets) against the FP64 oracle through the C ABI: a 2048-neuron
 network at p = 0.1, ragged row and trial tiles with slow GABA and pulse
-trains, an explicit method other than RK4, sparse storage forced on a p = 0.5
-network next to its dense (matrix-core) form, and trial invariance."""
+trains, explicit methods other than RK4 (also on a full 64-trial tile),
+sparse storage forced on a p = 0.5 network next to its dense (matrix-core)
+form, and trial invariance."""
 import sys
 
 import numpy as np
@@ -129,6 +130,27 @@ def test_sparse_large_tableau():
     assert "sparse" in desc and "2 launches per step" in desc
     o = R.oracle_run(insts, n, rec_stride=1, spike_cap=16, tableau=tab)
     _check(g, o, net, [0, 1, 2], n)
+
+
+def test_sparse_large_tableau_full_trial_tile():
+    """The 3/8 rule on the sparse per-stage path with 20 trials (one 64-trial
+    tile: the eight-wavefront general-tableau kernel): two trials against the
+    oracle's run of the same tableau, and every trial bit for bit against
+    dense storage of the network."""
+    tab = W.TABLEAUX["rk38"]
+    net = W.all_pairs_network(58, 0, 840, 280, g_max=0.5, p=0.1)
+    insts = _trials(net, 58, 20)
+    n = 300
+    s, ds = _run(net, insts, n, tableau=tab)
+    d, dd = _run(net, insts, n, storage="dense", tableau=tab)
+    assert "sparse" in ds and "tile 64 x 64" in ds and "4 launches per step" in ds, ds
+    assert "sparse" not in dd, dd
+    np.testing.assert_array_equal(s["v"], d["v"])
+    np.testing.assert_array_equal(s["state"], d["state"])
+    picks = [0, 19]
+    o = R.oracle_run([insts[t] for t in picks], n, rec_stride=1, spike_cap=16, threads=2,
+                     tableau=tab)
+    _check(s, o, net, picks, n)
 
 
 def test_sparse_forced_on_a_dense_network():
