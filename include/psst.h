@@ -40,7 +40,13 @@
  *     picks a variant holding leading conductance columns of larger
  *     networks in registers; same bits), PSST_ADJ_MODE=lacc|mma (how the
  *     adjoint accumulates dL/dg), PSST_ADJ_BS=64|128|256|512 (adjoint
- *     workgroup size, when it covers the batch's largest network).
+ *     workgroup size, when it covers the batch's largest network),
+ *     PSST_ADJ_PIPE=0 (the adjoint's recomputation on the caller's stream,
+ *     not beside the reverse sweep on a second one; same bits),
+ *     PSST_TUNE_FILE (path of the tuning table, default tuning/<arch>.txt
+ *     beside the library), PSST_TUNE_WRITE=1 (a batch tuned on creation
+ *     writes its choices to that table), PSST_TUNE_LOG=1 (the tuner prints
+ *     its timings to stderr).
  *   - A handle holds per-handle device state (control blocks, graphs,
  *     workspaces, error flags): calls on one network or batch must be issued
  *     from one host thread at a time and on one stream, or the caller orders
